@@ -1,0 +1,28 @@
+"""Builds the FP64 reference library liblbm_oracle.so with gcc.
+
+Test infrastructure: the oracle is compiled here so the tests, the smoke check
+and the CPU-baseline leg of the benchmark can call it; the product library
+never links it.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["lbm_oracle.c", "geom_oracle.c", "amr_oracle.c", "turb_oracle.c"]
+LIB = os.path.join(HERE, "liblbm_oracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE",
+           "-o", LIB + ".tmp"] + srcs + ["-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

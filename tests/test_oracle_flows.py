@@ -1,0 +1,198 @@
+"""Pins of the FP64 oracle's time stepping against closed forms and exact
+invariants: Taylor-Green decay (viscosity and Galilean correction), pipe and
+plane Poiseuille (interpolated / halfway bounce-back), a quiescent fluid around
+a closed body, the per-step momentum balance of the momentum-exchange force and
+the mirror symmetry of a symmetric tree.  Paper Sec. 2.2-2.3."""
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+def _tgv_rate_ratio(N=48, nu=0.05, U=0.01, u0=0.0, steps=300, galilean=True, plane="xy"):
+    dims = {"xy": (N, N, 1), "xz": (N, 1, N), "yz": (1, N, N)}[plane]
+    nx, ny, nz = dims
+    sim = O.UniformSim(nx, ny, nz, O.omega_from_nu(nu), periodic_x=True, galilean=galilean)
+    k = 2 * np.pi / N
+    z, y, x = np.meshgrid(np.arange(nz) + .5, np.arange(ny) + .5, np.arange(nx) + .5, indexing="ij")
+    a, b = {"xy": (x, y), "xz": (x, z), "yz": (y, z)}[plane]
+    ia, ib = {"xy": (0, 1), "xz": (0, 2), "yz": (1, 2)}[plane]
+    uu = np.zeros(a.shape + (3,))
+    uu[..., ia] = -U * np.cos(k * a) * np.sin(k * b) + u0
+    uu[..., ib] = U * np.sin(k * a) * np.cos(k * b)
+    rho = 1 - 0.75 * U * U * (np.cos(2 * k * a) + np.cos(2 * k * b))
+    sim.f[:] = np.stack([O.equilibrium(r, v) for r, v in zip(rho.ravel(), uu.reshape(-1, 3))], 1)
+
+    def amp():
+        _, u = sim.fields()
+        u = u - u.mean(0)
+        return np.sqrt((u ** 2).sum())
+
+    sim.step(40)
+    a0, t0 = amp(), sim.steps
+    sim.step(steps)
+    rate = -np.log(amp() / a0) / (sim.steps - t0)
+    return rate / (2 * nu * k * k)
+
+
+@pytest.mark.parametrize("plane", ["xy", "xz", "yz"])
+def test_taylor_green_decay_rate(plane):
+    """P4: kinetic decay exp(-2 nu k^2 t) with nu = (1/omega1 - 1/2)/3."""
+    assert abs(_tgv_rate_ratio(plane=plane) - 1.0) < 2e-3
+
+
+def test_taylor_green_galilean_correction():
+    """P4 with a superposed advection 0.1: the corrected collision keeps the rate
+    within 0.2 %; without the correction terms it is off by more than 1 %."""
+    with_c = _tgv_rate_ratio(u0=0.1, galilean=True)
+    without = _tgv_rate_ratio(u0=0.1, galilean=False)
+    assert abs(with_c - 1.0) < 2e-3
+    assert abs(without - 1.0) > 1e-2
+
+
+def test_taylor_green_second_order_convergence():
+    e1 = abs(_tgv_rate_ratio(N=16, nu=0.02, steps=200) - 1.0)
+    e2 = abs(_tgv_rate_ratio(N=32, nu=0.02, steps=400) - 1.0)
+    assert e2 < e1 / 3.0
+
+
+def _pipe(R, nu, g=1e-6, steps=None):
+    n = int(2 * R) + 4
+    nx, ny, nz = 2, n, n
+    c = n / 2.0
+    z, y, x = np.meshgrid(np.arange(nz) + .5, np.arange(ny) + .5, np.arange(nx) + .5, indexing="ij")
+    r2 = ((y - c) ** 2 + (z - c) ** 2).ravel()
+    solid = (r2 >= R * R).astype(np.uint8)
+    cells, dirs, qs = [], [], []
+    for cell in np.nonzero(solid == 0)[0]:
+        xi, yi, zi = cell % nx, (cell // nx) % ny, cell // (nx * ny)
+        for i in range(27):
+            sy, sz = yi + O.CY[i], zi + O.CZ[i]
+            if i == 13 or not solid[(xi + O.CX[i]) % nx + nx * (sy + ny * sz)]:
+                continue
+            oy, oz, dy, dz = yi + .5 - c, zi + .5 - c, O.CY[i], O.CZ[i]
+            A, B, Cc = dy * dy + dz * dz, 2 * (oy * dy + oz * dz), oy * oy + oz * oz - R * R
+            cells.append(cell)
+            dirs.append(i)
+            qs.append((-B + np.sqrt(B * B - 4 * A * Cc)) / (2 * A))
+    link = {"cell": np.array(cells, np.int64), "dir": np.array(dirs, np.int8), "q": np.array(qs),
+            "branch": np.zeros(len(cells), np.int32)}
+    sim = O.UniformSim(nx, ny, nz, O.omega_from_nu(nu), solid=solid, link=link, periodic_x=True,
+                       force=(g, 0, 0), n_branch=1)
+    ua = g / (4 * nu) * np.maximum(R * R - r2, 0)
+    f = np.stack([O.equilibrium(1.0, [v, 0, 0]) for v in ua], 1)
+    f[:, solid == 1] = O.weights()[:, None]
+    sim.f[:] = f
+    sim.step(steps or int(25 * R * R))
+    _, u = sim.fields()
+    fl = solid == 0
+    l2 = np.sqrt(((u[fl, 0] - ua[fl]) ** 2).sum() / (ua[fl] ** 2).sum())
+    return l2, sim.last_force[0] / (g * fl.sum()), sim.missing
+
+
+def test_pipe_poiseuille_bouzidi():
+    """P5: curved-wall pipe flow u = g (R^2 - r^2) / (4 nu); <= 1 % at R = 16,
+    second-order convergence from R = 8, and the steady wall force balances the
+    body force on the fluid."""
+    l8, bal8, miss8 = _pipe(8.0, 1 / 6)
+    l16, bal16, miss16 = _pipe(16.0, 1 / 6)
+    assert miss8 == 0 and miss16 == 0
+    assert l16 < 1e-2
+    assert l8 / l16 > 3.0
+    assert abs(bal16 - 1.0) < 1e-6
+
+
+def test_plane_poiseuille_halfway_walls():
+    """P5: channel between halfway walls (q = 1/2) at z = 1 and z = nz - 1."""
+    nx, ny, nz, nu, g = 2, 2, 18, 0.1, 1e-6
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[0] = solid[-1] = 1
+    solid = solid.ravel()
+    cells, dirs = [], []
+    for cell in np.nonzero(solid == 0)[0]:
+        zi = cell // (nx * ny)
+        for i in range(27):
+            if (zi == 1 and O.CZ[i] == -1) or (zi == nz - 2 and O.CZ[i] == 1):
+                cells.append(cell)
+                dirs.append(i)
+    link = {"cell": np.array(cells, np.int64), "dir": np.array(dirs, np.int8),
+            "q": np.full(len(cells), 0.5), "branch": np.zeros(len(cells), np.int32)}
+    sim = O.UniformSim(nx, ny, nz, O.omega_from_nu(nu), solid=solid, link=link, periodic_x=True,
+                       force=(g, 0, 0), n_branch=1)
+    sim.step(6000)
+    _, u = sim.fields()
+    h = nz - 2
+    zc = np.arange(nz) + 0.5 - 1.0
+    ua = g / (2 * nu) * zc * (h - zc)
+    fl = solid == 0
+    zz = (np.arange(nx * ny * nz) // (nx * ny))
+    err = np.abs(u[fl, 0] - ua[zz[fl]]).max() / ua.max()
+    assert err < 2e-3
+    assert abs(sim.last_force[0] / (g * fl.sum()) - 1.0) < 1e-6
+
+
+def _tiny_tree(box=24):
+    p = O.cfg1_tree_params()
+    b = O.tree_generate(p)
+    b = O.tree_place(b, box * 0.75, [box / 2, box / 2, box / 2])
+    return b
+
+
+def test_quiescent_fluid_around_tree_stays_at_rest():
+    """P6: fluid at rest around a closed body stays at rest; zero wall force."""
+    n = 24
+    b = _tiny_tree(n)
+    solid = O.voxelize(b, n, n, n)
+    lk = O.links(b, solid, n, n, n)
+    assert len(lk["cell"]) > 100
+    sim = O.UniformSim(n, n, n, 1.7, solid=solid, link=lk, periodic_x=True, n_branch=len(b))
+    f0 = sim.f.copy()
+    sim.step(5)
+    assert np.abs(sim.f - f0).max() < 1e-15
+    assert np.abs(sim.last_force).max() < 1e-14
+    # each branch's share of the surface is open, so the uniform pressure puts a
+    # force on it; only the closed union carries none
+    assert np.allclose(sim.last_branch_force.sum(0), 0.0, atol=1e-14)
+
+
+def test_momentum_exchange_balances_each_step():
+    """P7: in a periodic box with a body force g and the tree, every step
+    changes the fluid momentum by N_fluid * g minus the momentum-exchange force;
+    the per-branch forces add up to the total."""
+    n = 24
+    b = _tiny_tree(n)
+    solid = O.voxelize(b, n, n, n)
+    lk = O.links(b, solid, n, n, n)
+    g = np.array([2e-5, -1e-5, 3e-6])
+    sim = O.UniformSim(n, n, n, 1.6, solid=solid, link=lk, periodic_x=True, force=tuple(g),
+                       n_branch=len(b))
+    fl = solid == 0
+    assert fl.sum() < n ** 3 - 60
+    sim.step(30)
+    for _ in range(5):
+        p0 = (sim.f[:, fl].T @ O.CVEC).sum(0)
+        sim.step(1)
+        p1 = (sim.f[:, fl].T @ O.CVEC).sum(0)
+        assert np.allclose(p1 - p0, fl.sum() * g - sim.last_force, atol=1e-13, rtol=0)
+        assert np.allclose(sim.last_branch_force.sum(0), sim.last_force, atol=1e-14)
+    assert sim.missing == 0
+
+
+def test_cfg1_mirror_symmetry():
+    """P8: the order-1 tree lies in the y-z plane, symmetric about y = 16: the
+    transverse force and the transverse velocity field are antisymmetric."""
+    nx, ny, nz = 64, 32, 32
+    b = O.build_tree(O.cfg1_tree_params(), 0.0, [16.0, 16.0, 16.0])
+    solid = O.voxelize(b, nx, ny, nz)
+    s3 = solid.reshape(nz, ny, nx)
+    assert np.array_equal(s3, s3[:, ::-1, :])
+    lk = O.links(b, solid, nx, ny, nz)
+    nu = 0.05 * O.tree_height(b) / 100.0
+    sim = O.UniformSim(nx, ny, nz, O.omega_from_nu(nu), u_in=0.05, solid=solid, link=lk,
+                       n_branch=len(b))
+    sim.step(40)
+    assert abs(sim.last_force[1]) < 1e-13 * abs(sim.last_force[0])
+    _, u = sim.fields()
+    uy = u[:, 1].reshape(nz, ny, nx)
+    assert np.abs(uy + uy[:, ::-1, :]).max() < 1e-13
+    assert sim.last_force[0] > 0
