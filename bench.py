@@ -1,0 +1,169 @@
+"""Throughput of the D3Q27 cumulant LBM hot path on one MI355X.
+
+Workload (uniform grid): 512 x 256 x 256 cells (33,554,432), order-3 seeded
+L-system tree with three children per node (pitch 35 +- 5 deg, 90 deg
+phyllotaxis, ratios 0.7, seed 2) scaled to H = 128 cells with its centre of
+mass at (128, 128, 128); Re_H = 2500, uniform inflow u = 0.05 along +x,
+zero-gradient outlet, periodic lateral faces.  Synthetic: the tree and the
+flow are generated here.
+
+A step is one collide-and-stream pass over every fluid cell plus the
+interpolated bounce-back and the FP64 force reduction of the tree.  The timed
+region runs K steps with populations stored as FP32 deviations (the reported
+value) and K steps with FP16 deviations; arithmetic is FP32 in both.
+
+Prints one JSON line.  With the CPU leg on (default) it also times the FP64
+oracle on a bounded sample of the same workload and compares C_D after that
+many steps (GPU FP32 / FP16 against the oracle).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+STREAM = None
+NX, NY, NZ, H = 512, 256, 256, 128.0
+RE_H, U_IN = 2500.0, 0.05
+
+
+def build_tree(lt):
+    p = lt.tree_params(3, 3, 1.0, 0.3, [0.7] * 3, [0.7] * 3, [0.0, 120.0, 240.0], [35.0] * 3, [90.0] * 3,
+                       jitter=5.0, seed=2)
+    arr = lt.tree_generate(p)
+    lt.tree_place(arr, H, [128.0, 128.0, 128.0])
+    return arr
+
+
+def run_storage(lt, torch, arr, storage, steps, warmup, drag_every):
+    stream = STREAM
+    g = lt.Grid(NX, NY, NZ, u_in=U_IN, re_h=RE_H, storage=storage, drag_every=drag_every,
+                stream=stream.cuda_stream)
+    g.set_geometry(arr)
+    info = g.info()
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g.timing(True)
+    e0.record(stream)
+    g.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kt = g.timing_read()
+    g.timing(False)
+    d = g.drag()
+    cells = info["updated_cells"][0]
+    g.close()
+    return {"ms": ms, "cells": cells, "mlups": cells * steps / (ms * 1e-3) / 1e6, "kernel": kt,
+            "links": info["links"], "cd_mean": d["cd"], "device_bytes": info["device_bytes"]}
+
+
+def cd_after(lt, torch, arr, storage, nsteps):
+    stream = STREAM
+    g = lt.Grid(NX, NY, NZ, u_in=U_IN, re_h=RE_H, storage=storage, drag_every=1, stream=stream.cuda_stream)
+    g.set_geometry(arr)
+    g.step(nsteps)
+    s = g.drag_series(1)[0]
+    ax = g.info()["area_x"]
+    g.close()
+    return s[0] / (0.5 * U_IN ** 2 * ax)
+
+
+def cpu_leg(lt, arr, nsteps):
+    import oracle as O
+    b = lt.branches_to_numpy(arr)
+    t0 = time.time()
+    solid = O.voxelize(b, NX, NY, NZ)
+    lk = O.links(b, solid, NX, NY, NZ)
+    ax = O.area_x(solid, NX, NY, NZ)
+    setup = time.time() - t0
+    nu = U_IN * O.tree_height(b) / RE_H
+    sim = O.UniformSim(NX, NY, NZ, O.omega_from_nu(nu), u_in=U_IN, solid=solid, link=lk, n_branch=len(b))
+    t0 = time.time()
+    sim.step(nsteps)
+    dt = time.time() - t0
+    fluid = int((solid == 0).sum())
+    cd = sim.last_force[0] / (0.5 * U_IN ** 2 * ax)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"mlups": fluid * nsteps / dt / 1e6, "seconds": dt, "setup_s": setup, "cores": cores, "cd": cd}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--drag-every", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2603_27954_amd as lt
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    global STREAM
+    # a stream of our own (default priority): the library enqueues on it and
+    # the timing events are recorded on it
+    STREAM = torch.cuda.Stream()
+    arr = build_tree(lt)
+    r32 = run_storage(lt, torch, arr, "fp32", args.steps, args.warmup, args.drag_every)
+    r16 = run_storage(lt, torch, arr, "fp16", args.steps, args.warmup, args.drag_every)
+
+    def roof(r, bytes_per_cell):
+        kt = r["kernel"]
+        avg_ms = kt["collide_ms"] / max(kt["collide_launches"], 1)
+        achieved = bytes_per_cell * r["cells"] / (avg_ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_collide", "avg_launch_ms": round(avg_ms, 5)}
+
+    out = {
+        "metric": "MLUPS & % HBM peak, D3Q27 cumulant FP32 vs FP16-store; C_d err vs FP64 oracle",
+        "value": round(r32["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "uniform 512x256x256, order-3 seeded 3-child tree H=128, Re_H=2500, u=0.05",
+                   "cells": NX * NY * NZ, "fluid_cells": r32["cells"], "links": r32["links"],
+                   "storage": "fp32 deviations", "drag_every": args.drag_every},
+        "roofline": roof(r32, 216),
+        "fp16_storage": {"value": round(r16["mlups"], 1), "unit": "MLUPS",
+                         "ratio_vs_fp32": round(r16["mlups"] / r32["mlups"], 3),
+                         "ms_per_step": round(r16["ms"] / args.steps, 4), "roofline": roof(r16, 108)},
+    }
+    if not args.no_cpu:
+        c = cpu_leg(lt, arr, args.cpu_steps)
+        cd32 = cd_after(lt, torch, arr, "fp32", args.cpu_steps)
+        cd16 = cd_after(lt, torch, arr, "fp16", args.cpu_steps)
+        out["cpu_baseline"] = {"value": round(c["mlups"], 2), "unit": "MLUPS", "cores": c["cores"],
+                               "kind": "oracle",
+                               "sample": f"full 512x256x256 workload, {args.cpu_steps} FP64 steps "
+                                         f"({c['seconds']:.1f} s; geometry setup {c['setup_s']:.1f} s untimed)"}
+        out["cd_error"] = {"steps": args.cpu_steps, "cd_oracle": c["cd"],
+                           "fp32_rel": abs(cd32 - c["cd"]) / abs(c["cd"]),
+                           "fp16_rel": abs(cd16 - c["cd"]) / abs(c["cd"])}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

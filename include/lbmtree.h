@@ -1,0 +1,249 @@
+/*
+ * lbmtree — D3Q27 cumulant lattice-Boltzmann drag of L-system fractal trees
+ * on MI355X (gfx950).  C ABI of liblbmtree.so.
+ *
+ * The method is the one of "Drag Crisis in Fractal Trees Revealed by
+ * Simulation and Theory":
+ *   - tree geometry: parametric L-system of Eq. (1) read by a turtle (Sec. 2.1,
+ *     Table 1), rescaled to a height and placed by its centre of mass (Sec. 2.3);
+ *   - flow: D3Q27 cumulant collision with fully explicit collide-and-stream on
+ *     an octree of cubic leaf blocks, finest near the tree surface, moderate in
+ *     the wake, coarse elsewhere (Sec. 2.2);
+ *   - wall: second-order interpolated bounce-back (Sec. 2.2, Bouzidi et al.);
+ *   - force: momentum exchange summed over the tree surface (Sec. 2.2) and the
+ *     drag coefficient C_D = F_D / (rho U^2 A_x / 2) of Eq. (7).
+ *
+ * Conventions (all functions):
+ *   - every call returns an lbm_status; no exception or signal crosses the ABI;
+ *     on error lbm_last_error() returns a message (per grid, or per thread when
+ *     the grid handle is NULL);
+ *   - lengths are in cells of the finest level, velocities in lattice units of
+ *     the finest level (the same on every level: acoustic scaling);
+ *   - population index i = (cx+1) + 3(cy+1) + 9(cz+1) over c in {-1,0,1}^3,
+ *     opposite direction 26 - i;
+ *   - dense per-level arrays use cell = x + nx_l*(y + ny_l*z) over the level's
+ *     whole box (nx_l = nx >> (levels-1-l), likewise y, z); SoA for populations
+ *     (f[i*N + cell]);
+ *   - all host pointers are owned by the caller, read or written only during
+ *     the call; device memory is allocated and owned by the library;
+ *   - one grid handle is used by one host thread at a time.
+ */
+#ifndef LBMTREE_H
+#define LBMTREE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_grid lbm_grid; /* opaque */
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_E_INVALID = -1,  /* bad argument or description; nothing was changed */
+    LBM_E_NOMEM = -2,    /* device or host allocation failed */
+    LBM_E_DEVICE = -3,   /* a HIP call failed (message names it) */
+    LBM_E_UNSTABLE = -4, /* NaN / density outside [0.5, 1.5] detected */
+    LBM_E_STATE = -5     /* call out of order (e.g. step before set_geometry) */
+} lbm_status;
+
+typedef enum {
+    LBM_FP32 = 0,     /* populations stored as FP32 deviations f_i - w_i */
+    LBM_FP16_DEV = 1, /* stored as FP16 deviations f_i - w_i, FP32 arithmetic */
+    LBM_BF16_DEV = 2  /* stored as BF16 deviations f_i - w_i, FP32 arithmetic */
+} lbm_storage;
+
+/* flags of lbm_grid_desc.flags */
+#define LBM_F_NO_GALILEAN 1u /* drop the Galilean-correction terms of the second-order relaxation */
+#define LBM_F_GRAPH 2u       /* replay each coarse step from a captured HIP graph */
+#define LBM_F_PERSISTENT 4u  /* run each coarse step as one persistent launch */
+#define LBM_F_AUTOTUNE 8u    /* time the tile candidates at set_geometry and keep the fastest */
+
+/* One cylinder of the tree (Sec. 2.1: the tree is an assembly of cylinders).
+ * The solid is the union of the cylinders and of a sphere of the same
+ * diameter at each p1. */
+typedef struct {
+    double p0[3], p1[3]; /* axis start and end, finest cells */
+    double diameter;     /* finest cells */
+    int32_t generation;  /* trunk 0 */
+    int32_t parent;      /* -1 for the trunk */
+    int32_t id;          /* 0 .. n-1, unique */
+} lbm_branch;
+
+/* Turtle parameters of Eq. (1) with up to four children per apex.  Child j
+ * applies a roll by pre_roll[j] about H, a pitch by pitch[j] (+ jitter) about
+ * U and a roll by post_roll[j] about H, then draws F(s * len_ratio[j]) with
+ * diameter w * wid_ratio[j].  order = number of child generations below the
+ * trunk.  jitter > 0 draws one uniform angle in [-jitter, jitter] degrees per
+ * child, in depth-first pre-order, from SplitMix64 seeded with seed. */
+typedef struct {
+    int32_t m, order;
+    double s0, w0;
+    double len_ratio[4], wid_ratio[4];
+    double pre_roll[4], pitch[4], post_roll[4];
+    double jitter;
+    uint64_t seed;
+} lbm_tree_params;
+
+typedef struct {
+    int32_t nx, ny, nz;   /* finest-level cells; multiples of block_edge << (levels-1) */
+    int32_t block_edge;   /* 8 or 16 */
+    int32_t levels;       /* 1 (uniform) .. 4 */
+    double u_in;          /* inflow speed along +x, lattice units; Mach sqrt(3) u_in < 0.3 */
+    double re_h;          /* Re_H = u_in H / nu_finest, H = tree height; used when nu <= 0 */
+    double nu;            /* finest-level lattice viscosity; > 0 overrides re_h */
+    int32_t storage;      /* lbm_storage */
+    int32_t periodic_yz;  /* must be 1: periodic lateral faces */
+    double turb_intensity; /* inlet I_u (0 = uniform inflow) */
+    double turb_length;    /* integral length of the inflow turbulence, finest cells */
+    uint64_t turb_seed;
+    int32_t turb_modes;    /* number of random Fourier modes (0 -> 200) */
+    int32_t drag_every;    /* finest sub-steps between force samples (>= 1) */
+    uint32_t flags;        /* LBM_F_* */
+    int32_t device;        /* HIP device ordinal */
+    void *stream;          /* hipStream_t to run on; NULL = the library's own stream */
+} lbm_grid_desc;
+
+/* Refinement bands (Sec. 2.2: finest near the surface, moderate in the wake).
+ * For level l = 1 .. levels-1, a leaf block of level l-1 is refined when it
+ * lies within band[l] finest cells of a branch surface or inside the wake box
+ * that extends wake[l] finest cells downstream of the tree's bounding box
+ * (laterally padded by band[l]).  Refinement is then closed so that every
+ * refined block has all 26 neighbours at its own level.  Ignored when
+ * levels == 1. */
+typedef struct {
+    int32_t band[4];
+    int32_t wake[4];
+} lbm_refine_desc;
+
+typedef struct {
+    double force[3];   /* FP64 mean force on the tree over the samples since the last lbm_drag */
+    double cd;         /* C_D = force[0] / (0.5 * u_in^2 * area_x), Eq. (7), rho0 = 1 */
+    double area_x;     /* frontal area: finest (y,z) columns holding a solid cell */
+    double height;     /* tree height H, finest cells */
+    double mass;       /* sum of rho * cell volume (finest units) over all active cells */
+    int64_t samples;   /* force samples averaged */
+    int64_t step;      /* coarse steps done */
+} lbm_drag_result;
+
+typedef struct {
+    int32_t levels, block_edge, storage;
+    int64_t blocks[4];        /* allocated blocks per level (active + covered + ghost) */
+    int64_t active_cells[4];  /* leaf fluid + solid cells per level */
+    int64_t updated_cells[4]; /* cells collided per level sub-step */
+    int64_t links;
+    int32_t branches;
+    double omega1[4];
+    double height, area_x, nu_finest;
+    size_t device_bytes;
+    int32_t tile_cells;       /* cells per work-group iteration of the collide kernel */
+} lbm_info;
+
+/* ---- lifecycle ------------------------------------------------------------ */
+
+/* Validates d on the host (sizes, Mach, levels, storage) and creates a grid
+ * bound to d->device.  No device memory is allocated yet. */
+lbm_status lbm_create_grid(const lbm_grid_desc *d, lbm_grid **out);
+
+/* Voxelises the branches (copied), builds boundary links with their wall
+ * distances q, the block grid and its refinement (refine may be NULL when
+ * levels == 1), uploads everything and initialises f = f_eq(1, u_in) in fluid.
+ * Fails with LBM_E_INVALID when a branch or refined region comes within one
+ * block of the box faces.  device_bytes_out (may be NULL) receives the device
+ * memory held. */
+lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b,
+                            const lbm_refine_desc *refine, size_t *device_bytes_out);
+
+/* Advances n coarse steps (2^(levels-1) finest sub-steps each), asynchronously
+ * on the grid's stream. */
+lbm_status lbm_step(lbm_grid *g, int32_t n_coarse_steps);
+
+/* Synchronises, returns the mean force over the samples taken since the
+ * previous lbm_drag (then restarts the mean), C_D, mass; per_branch (3*n_b
+ * doubles, may be NULL) receives the mean force per branch id.  Returns
+ * LBM_E_UNSTABLE when the run has produced NaN or a density outside
+ * [0.5, 1.5]. */
+lbm_status lbm_drag(lbm_grid *g, lbm_drag_result *out, double *per_branch);
+
+/* Copies out up to cap force samples (3 doubles each, FP64, oldest first) of
+ * the ring of the last 65536 samples; *n receives the count copied. */
+lbm_status lbm_drag_series(lbm_grid *g, double *out, int64_t cap, int64_t *n);
+
+void lbm_destroy_grid(lbm_grid *g);
+const char *lbm_last_error(const lbm_grid *g);
+lbm_status lbm_get_info(const lbm_grid *g, lbm_info *out);
+
+/* ---- geometry helpers (host only) ------------------------------------------ */
+
+/* Writes up to cap branches of the tree of p (trunk base at the origin,
+ * heading +z, left +y); *n receives the full count. */
+lbm_status lbm_tree_generate(const lbm_tree_params *p, lbm_branch *out, int32_t cap, int32_t *n);
+
+/* Scales about the trunk base to height target_h (when > 0) and translates so
+ * the cylinder-volume centre of mass is at com.  *height_out (may be NULL)
+ * receives the final height. */
+lbm_status lbm_tree_place(lbm_branch *b, int32_t n, double target_h, const double com[3],
+                          double *height_out);
+
+/* ---- state access for tests and checkpoints (synchronous) ------------------ */
+
+/* Dense FP64 populations of level l over its box, f[i*N + cell].  Cells the
+ * level does not hold read as NaN and are ignored on write. */
+lbm_status lbm_get_populations(lbm_grid *g, int32_t level, double *f);
+lbm_status lbm_set_populations(lbm_grid *g, int32_t level, const double *f);
+
+/* Dense density and velocity (u[3*cell + a]) of level l; NaN where not held. */
+lbm_status lbm_get_fields(lbm_grid *g, int32_t level, double *rho, double *u);
+
+/* Finest-level solid mask (uint8 over the finest box) and the link table in
+ * (cell, direction) order: cell index over the finest box, direction pointing
+ * into the solid, q, branch id. */
+lbm_status lbm_get_solid(lbm_grid *g, uint8_t *solid);
+lbm_status lbm_get_links(lbm_grid *g, int64_t cap, int64_t *cell, int8_t *dir, double *q,
+                         int32_t *branch, int64_t *n);
+
+/* Block map of level l over its block lattice (nbx_l * nby_l * nbz_l int8):
+ * 0 none, 1 leaf, 2 refined (covered by level l+1), 3 ghost storage. */
+lbm_status lbm_get_block_map(lbm_grid *g, int32_t level, int8_t *map);
+
+/* FP64 mass sum over active cells (synchronous). */
+lbm_status lbm_mass(lbm_grid *g, double *mass);
+
+/* Per-kernel timing with HIP events recorded on the grid's stream around each
+ * collide launch and each bounce-back launch.  lbm_timing_enable(g, 1) clears
+ * the totals and starts recording, (g, 0) stops.  lbm_timing_read synchronises
+ * and returns total milliseconds and launch counts (any pointer may be NULL). */
+lbm_status lbm_timing_enable(lbm_grid *g, int32_t enable);
+lbm_status lbm_timing_read(lbm_grid *g, double *collide_ms, int64_t *collide_launches, double *links_ms,
+                           int64_t *links_launches);
+
+/* Picks the collide-kernel tile by timing the candidates on this grid; caches
+ * the choice in cache_path (may be NULL). */
+lbm_status lbm_autotune(lbm_grid *g, const char *cache_path);
+
+/* Checkpoint of populations, step counters and force accumulators. */
+lbm_status lbm_save(lbm_grid *g, const char *path);
+lbm_status lbm_load(lbm_grid *g, const char *path);
+
+/* Host-only geometry of a uniform box: solid mask (uint8 over nx*ny*nz, may be
+ * NULL), up to cap links in (cell, direction) order (any array may be NULL),
+ * *n_links the full count, *area_x the frontal area.  The same routines feed
+ * lbm_set_geometry; no device is touched. */
+lbm_status lbm_geometry_build(const lbm_branch *b, int32_t n_b, int32_t nx, int32_t ny, int32_t nz,
+                              uint8_t *solid, int64_t cap, int64_t *cell, int8_t *dir, double *q,
+                              int32_t *branch, int64_t *n_links, double *area_x);
+
+/* ---- host probe (tests) ------------------------------------------------------ */
+
+/* Runs the FP32 cumulant collision of the kernels on the host for one cell:
+ * f_in, f_out are 27 full populations (FP64 in and out, rounded to FP32
+ * deviations inside), omega1 / omega2 the shear and bulk rates, galilean 0/1
+ * for the correction terms.  No device is touched. */
+lbm_status lbm_collide_cell_host(const double *f_in, double *f_out, double omega1, double omega2, int galilean);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

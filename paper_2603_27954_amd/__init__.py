@@ -1,0 +1,357 @@
+"""Python binding of liblbmtree (C ABI in include/lbmtree.h).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels of
+the shared library.  Importing this package fails loudly when the library has
+not been built (``python -m paper_2603_27954_amd.build`` or
+``__graft_entry__.build()``); there is no fallback path.
+"""
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmtree.so")
+
+LBM_OK, LBM_E_INVALID, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_STATE = 0, -1, -2, -3, -4, -5
+LBM_FP32, LBM_FP16_DEV, LBM_BF16_DEV = 0, 1, 2
+LBM_F_NO_GALILEAN, LBM_F_GRAPH, LBM_F_PERSISTENT, LBM_F_AUTOTUNE = 1, 2, 4, 8
+STORAGE = {"fp32": LBM_FP32, "fp16": LBM_FP16_DEV, "bf16": LBM_BF16_DEV}
+
+_STATUS_NAMES = {0: "LBM_OK", -1: "LBM_E_INVALID", -2: "LBM_E_NOMEM", -3: "LBM_E_DEVICE",
+                 -4: "LBM_E_UNSTABLE", -5: "LBM_E_STATE"}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Branch(C.Structure):
+    _fields_ = [("p0", C.c_double * 3), ("p1", C.c_double * 3), ("diameter", C.c_double),
+                ("generation", C.c_int32), ("parent", C.c_int32), ("id", C.c_int32)]
+
+
+class TreeParams(C.Structure):
+    _fields_ = [("m", C.c_int32), ("order", C.c_int32), ("s0", C.c_double), ("w0", C.c_double),
+                ("len_ratio", C.c_double * 4), ("wid_ratio", C.c_double * 4),
+                ("pre_roll", C.c_double * 4), ("pitch", C.c_double * 4),
+                ("post_roll", C.c_double * 4), ("jitter", C.c_double), ("seed", C.c_uint64)]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("block_edge", C.c_int32),
+                ("levels", C.c_int32), ("u_in", C.c_double), ("re_h", C.c_double), ("nu", C.c_double),
+                ("storage", C.c_int32), ("periodic_yz", C.c_int32), ("turb_intensity", C.c_double),
+                ("turb_length", C.c_double), ("turb_seed", C.c_uint64), ("turb_modes", C.c_int32),
+                ("drag_every", C.c_int32), ("flags", C.c_uint32), ("device", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class RefineDesc(C.Structure):
+    _fields_ = [("band", C.c_int32 * 4), ("wake", C.c_int32 * 4)]
+
+
+class DragResult(C.Structure):
+    _fields_ = [("force", C.c_double * 3), ("cd", C.c_double), ("area_x", C.c_double),
+                ("height", C.c_double), ("mass", C.c_double), ("samples", C.c_int64), ("step", C.c_int64)]
+
+
+class Info(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("block_edge", C.c_int32), ("storage", C.c_int32),
+                ("blocks", C.c_int64 * 4), ("active_cells", C.c_int64 * 4),
+                ("updated_cells", C.c_int64 * 4), ("links", C.c_int64), ("branches", C.c_int32),
+                ("omega1", C.c_double * 4), ("height", C.c_double), ("area_x", C.c_double),
+                ("nu_finest", C.c_double), ("device_bytes", C.c_size_t), ("tile_cells", C.c_int32)]
+
+
+_lib = None
+_P = C.c_void_p
+_dp = C.POINTER(C.c_double)
+
+
+def lib():
+    """Loads liblbmtree.so; raises when it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2603_27954_amd.build")
+    L = C.CDLL(LIB_PATH)
+    sigs = {
+        "lbm_create_grid": [C.POINTER(GridDesc), C.POINTER(_P)],
+        "lbm_set_geometry": [_P, C.POINTER(Branch), C.c_int32, C.POINTER(RefineDesc), C.POINTER(C.c_size_t)],
+        "lbm_step": [_P, C.c_int32],
+        "lbm_drag": [_P, C.POINTER(DragResult), _dp],
+        "lbm_drag_series": [_P, _dp, C.c_int64, C.POINTER(C.c_int64)],
+        "lbm_get_info": [_P, C.POINTER(Info)],
+        "lbm_tree_generate": [C.POINTER(TreeParams), C.POINTER(Branch), C.c_int32, C.POINTER(C.c_int32)],
+        "lbm_tree_place": [C.POINTER(Branch), C.c_int32, C.c_double, _dp, _dp],
+        "lbm_get_populations": [_P, C.c_int32, _dp],
+        "lbm_set_populations": [_P, C.c_int32, _dp],
+        "lbm_get_fields": [_P, C.c_int32, _dp, _dp],
+        "lbm_get_solid": [_P, C.POINTER(C.c_uint8)],
+        "lbm_get_links": [_P, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int8), _dp,
+                          C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
+        "lbm_get_block_map": [_P, C.c_int32, C.POINTER(C.c_int8)],
+        "lbm_mass": [_P, _dp],
+        "lbm_autotune": [_P, C.c_char_p],
+        "lbm_save": [_P, C.c_char_p],
+        "lbm_load": [_P, C.c_char_p],
+        "lbm_collide_cell_host": [_dp, _dp, C.c_double, C.c_double, C.c_int],
+        "lbm_timing_enable": [_P, C.c_int32],
+        "lbm_timing_read": [_P, _dp, C.POINTER(C.c_int64), _dp, C.POINTER(C.c_int64)],
+        "lbm_geometry_build": [C.POINTER(Branch), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                               C.POINTER(C.c_uint8), C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int8),
+                               _dp, C.POINTER(C.c_int32), C.POINTER(C.c_int64), _dp],
+    }
+    for name, args in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.lbm_destroy_grid.argtypes = [_P]
+    L.lbm_destroy_grid.restype = None
+    L.lbm_last_error.argtypes = [_P]
+    L.lbm_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(st, handle=None):
+    if st != LBM_OK:
+        msg = lib().lbm_last_error(handle)
+        raise LbmError(st, msg.decode() if msg else "")
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+# ---- geometry helpers --------------------------------------------------------
+
+def tree_params(m, order, s0, w0, len_ratio, wid_ratio, pre_roll, pitch, post_roll, jitter=0.0, seed=0):
+    p = TreeParams()
+    p.m, p.order, p.s0, p.w0 = m, order, s0, w0
+    for name, vals in (("len_ratio", len_ratio), ("wid_ratio", wid_ratio), ("pre_roll", pre_roll),
+                       ("pitch", pitch), ("post_roll", post_roll)):
+        arr = getattr(p, name)
+        for j in range(4):
+            arr[j] = vals[j] if j < len(vals) else 0.0
+    p.jitter = jitter
+    p.seed = seed & 0xFFFFFFFFFFFFFFFF
+    return p
+
+
+def tree_generate(p: TreeParams):
+    n = C.c_int32(0)
+    _check(lib().lbm_tree_generate(C.byref(p), None, 0, C.byref(n)))
+    arr = (Branch * n.value)()
+    _check(lib().lbm_tree_generate(C.byref(p), arr, n.value, C.byref(n)))
+    return arr
+
+
+def tree_place(arr, target_h: float, com: Sequence[float]):
+    c = np.ascontiguousarray(com, dtype=np.float64)
+    h = C.c_double(0.0)
+    _check(lib().lbm_tree_place(arr, len(arr), target_h, _dptr(c), C.byref(h)))
+    return h.value
+
+
+def branches_to_numpy(arr) -> np.ndarray:
+    out = np.zeros((len(arr), 10))
+    for i, b in enumerate(arr):
+        out[i, 0:3] = list(b.p0)
+        out[i, 3:6] = list(b.p1)
+        out[i, 6] = b.diameter
+        out[i, 7:10] = (b.generation, b.parent, b.id)
+    return out
+
+
+def branches_from_numpy(a: np.ndarray):
+    arr = (Branch * len(a))()
+    for i, r in enumerate(a):
+        for k in range(3):
+            arr[i].p0[k] = r[k]
+            arr[i].p1[k] = r[3 + k]
+        arr[i].diameter = r[6]
+        arr[i].generation, arr[i].parent, arr[i].id = int(r[7]), int(r[8]), int(r[9])
+    return arr
+
+
+def geometry_build(branches, nx, ny, nz):
+    """Host-side solid mask, links and frontal area of a uniform box."""
+    if isinstance(branches, np.ndarray):
+        branches = branches_from_numpy(branches)
+    n = C.c_int64(0)
+    ax = C.c_double(0.0)
+    solid = np.zeros(nx * ny * nz, np.uint8)
+    _check(lib().lbm_geometry_build(branches, len(branches), nx, ny, nz,
+                                    solid.ctypes.data_as(C.POINTER(C.c_uint8)), 0, None, None, None, None,
+                                    C.byref(n), C.byref(ax)))
+    m = n.value
+    cell = np.zeros(m, np.int64)
+    d = np.zeros(m, np.int8)
+    q = np.zeros(m)
+    br = np.zeros(m, np.int32)
+    _check(lib().lbm_geometry_build(branches, len(branches), nx, ny, nz, None, m,
+                                    cell.ctypes.data_as(C.POINTER(C.c_int64)), d.ctypes.data_as(C.POINTER(C.c_int8)),
+                                    _dptr(q), br.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(n), None))
+    return solid, {"cell": cell, "dir": d, "q": q, "branch": br}, ax.value
+
+
+def collide_cell_host(f, omega1, omega2=1.0, galilean=True):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.empty(27)
+    _check(lib().lbm_collide_cell_host(_dptr(f), _dptr(out), omega1, omega2, int(galilean)))
+    return out
+
+
+# ---- grid --------------------------------------------------------------------
+
+class Grid:
+    """Owns one lbm_grid handle."""
+
+    def __init__(self, nx, ny, nz, u_in=0.05, re_h=0.0, nu=0.0, block_edge=16, levels=1,
+                 storage="fp32", drag_every=1, flags=0, device=0, stream=None,
+                 turb_intensity=0.0, turb_length=0.0, turb_seed=0, turb_modes=0):
+        d = GridDesc()
+        d.nx, d.ny, d.nz = nx, ny, nz
+        d.block_edge, d.levels = block_edge, levels
+        d.u_in, d.re_h, d.nu = u_in, re_h, nu
+        d.storage = STORAGE[storage] if isinstance(storage, str) else storage
+        d.periodic_yz = 1
+        d.turb_intensity, d.turb_length, d.turb_seed, d.turb_modes = turb_intensity, turb_length, turb_seed, turb_modes
+        d.drag_every, d.flags, d.device = drag_every, flags, device
+        d.stream = stream
+        self.desc = d
+        self.h = _P()
+        _check(lib().lbm_create_grid(C.byref(d), C.byref(self.h)))
+        self.n_branch = 0
+
+    def close(self):
+        if self.h:
+            lib().lbm_destroy_grid(self.h)
+            self.h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_shape(self, level):
+        s = self.desc.levels - 1 - level
+        return self.desc.nx >> s, self.desc.ny >> s, self.desc.nz >> s
+
+    def set_geometry(self, branches, refine: Optional[dict] = None):
+        if isinstance(branches, np.ndarray):
+            branches = branches_from_numpy(branches)
+        r = None
+        if refine is not None:
+            r = RefineDesc()
+            for k, v in enumerate(refine.get("band", [])):
+                r.band[k] = v
+            for k, v in enumerate(refine.get("wake", [])):
+                r.wake[k] = v
+        nbytes = C.c_size_t(0)
+        _check(lib().lbm_set_geometry(self.h, branches, len(branches), C.byref(r) if r else None,
+                                      C.byref(nbytes)), self.h)
+        self.n_branch = len(branches)
+        return nbytes.value
+
+    def step(self, n=1):
+        _check(lib().lbm_step(self.h, n), self.h)
+
+    def drag(self, per_branch=False):
+        r = DragResult()
+        pb = np.zeros(3 * max(self.n_branch, 1)) if per_branch else None
+        _check(lib().lbm_drag(self.h, C.byref(r), _dptr(pb) if pb is not None else None), self.h)
+        out = {"force": np.array(r.force), "cd": r.cd, "area_x": r.area_x, "height": r.height,
+               "mass": r.mass, "samples": r.samples, "step": r.step}
+        if per_branch:
+            out["per_branch"] = pb.reshape(-1, 3)[: self.n_branch]
+        return out
+
+    def drag_series(self, cap=65536):
+        out = np.zeros(3 * cap)
+        n = C.c_int64(0)
+        _check(lib().lbm_drag_series(self.h, _dptr(out), cap, C.byref(n)), self.h)
+        return out[: 3 * n.value].reshape(-1, 3)
+
+    def info(self):
+        i = Info()
+        _check(lib().lbm_get_info(self.h, C.byref(i)), self.h)
+        return {"levels": i.levels, "block_edge": i.block_edge, "storage": i.storage,
+                "blocks": list(i.blocks), "active_cells": list(i.active_cells),
+                "updated_cells": list(i.updated_cells), "links": i.links, "branches": i.branches,
+                "omega1": list(i.omega1), "height": i.height, "area_x": i.area_x,
+                "nu_finest": i.nu_finest, "device_bytes": i.device_bytes, "tile_cells": i.tile_cells}
+
+    def get_populations(self, level=0):
+        nx, ny, nz = self.level_shape(level)
+        f = np.empty((27, nx * ny * nz))
+        _check(lib().lbm_get_populations(self.h, level, _dptr(f)), self.h)
+        return f
+
+    def set_populations(self, f, level=0):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        _check(lib().lbm_set_populations(self.h, level, _dptr(f)), self.h)
+
+    def fields(self, level=0):
+        nx, ny, nz = self.level_shape(level)
+        N = nx * ny * nz
+        rho = np.empty(N)
+        u = np.empty((N, 3))
+        _check(lib().lbm_get_fields(self.h, level, _dptr(rho), _dptr(u)), self.h)
+        return rho, u
+
+    def solid(self):
+        s = np.empty(self.desc.nx * self.desc.ny * self.desc.nz, np.uint8)
+        _check(lib().lbm_get_solid(self.h, s.ctypes.data_as(C.POINTER(C.c_uint8))), self.h)
+        return s
+
+    def links(self):
+        n = C.c_int64(0)
+        _check(lib().lbm_get_links(self.h, 0, None, None, None, None, C.byref(n)), self.h)
+        m = n.value
+        cell = np.zeros(m, np.int64)
+        d = np.zeros(m, np.int8)
+        q = np.zeros(m)
+        br = np.zeros(m, np.int32)
+        _check(lib().lbm_get_links(self.h, m, cell.ctypes.data_as(C.POINTER(C.c_int64)),
+                                   d.ctypes.data_as(C.POINTER(C.c_int8)), _dptr(q),
+                                   br.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(n)), self.h)
+        return {"cell": cell, "dir": d, "q": q, "branch": br}
+
+    def block_map(self, level):
+        B = self.desc.block_edge
+        nx, ny, nz = self.level_shape(level)
+        m = np.zeros((nx // B) * (ny // B) * (nz // B), np.int8)
+        _check(lib().lbm_get_block_map(self.h, level, m.ctypes.data_as(C.POINTER(C.c_int8))), self.h)
+        return m
+
+    def mass(self):
+        m = C.c_double(0.0)
+        _check(lib().lbm_mass(self.h, C.byref(m)), self.h)
+        return m.value
+
+    def timing(self, enable: bool):
+        _check(lib().lbm_timing_enable(self.h, int(enable)), self.h)
+
+    def timing_read(self):
+        cm, lm = C.c_double(0), C.c_double(0)
+        cn, ln = C.c_int64(0), C.c_int64(0)
+        _check(lib().lbm_timing_read(self.h, C.byref(cm), C.byref(cn), C.byref(lm), C.byref(ln)), self.h)
+        return {"collide_ms": cm.value, "collide_launches": cn.value, "links_ms": lm.value,
+                "links_launches": ln.value}
+
+    def autotune(self, cache_path=None):
+        _check(lib().lbm_autotune(self.h, cache_path.encode() if cache_path else None), self.h)
+
+    def save(self, path):
+        _check(lib().lbm_save(self.h, path.encode()), self.h)
+
+    def load(self, path):
+        _check(lib().lbm_load(self.h, path.encode()), self.h)

@@ -1,0 +1,391 @@
+// Host geometry for liblbmtree: L-system trees (paper Sec. 2.1, Eq. (1),
+// Table 1), placement (Sec. 2.3), voxelisation of the union of branch shapes,
+// boundary links with their wall distance q (interpolated bounce-back,
+// Sec. 2.2) and the frontal area A_x of Eq. (7).
+//
+// Turtle conventions: start at the origin with heading H = +z, left L = +y,
+// up U = H x L = -x.  Pitch "+(a)" turns H towards L about U; roll "/(p)"
+// turns L towards U about H.  Child j of an apex rolls by pre_roll[j], pitches
+// by pitch[j] (plus a jitter draw), rolls by post_roll[j] and draws
+// F(s len_ratio[j]) with diameter w wid_ratio[j].  Jitter draws come from
+// SplitMix64 (Steele, Lea & Flood 2014), one per child, in depth-first
+// pre-order of the children.
+#include "lbm_geometry.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+namespace lbm {
+
+namespace {
+
+struct V3 {
+    double x, y, z;
+};
+inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+struct Frame {
+    V3 pos, head, left, up;
+};
+
+struct SplitMix64 {
+    uint64_t s;
+    uint64_t next()
+    {
+        s += 0x9E3779B97F4A7C15ULL;
+        uint64_t z = s;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return double(next() >> 11) * 0x1.0p-53; }
+};
+
+Frame pitch(Frame f, double deg)
+{
+    const double r = deg * (M_PI / 180.0), c = std::cos(r), s = std::sin(r);
+    const V3 h = f.head, l = f.left;
+    f.head = c * h + s * l;
+    f.left = c * l - s * h;
+    return f;
+}
+
+Frame roll(Frame f, double deg)
+{
+    const double r = deg * (M_PI / 180.0), c = std::cos(r), s = std::sin(r);
+    const V3 l = f.left, u = f.up;
+    f.left = c * l + s * u;
+    f.up = c * u - s * l;
+    return f;
+}
+
+}  // namespace
+
+int tree_generate(const lbm_tree_params &p, std::vector<lbm_branch> &out)
+{
+    struct Pending {
+        Frame parent_end;  // frame at the end of the parent branch
+        double s, w;       // parent's length and diameter
+        int gen, parent, child;
+    };
+    out.clear();
+    SplitMix64 rng{p.seed};
+    std::vector<Pending> stack;
+    // trunk
+    {
+        Frame f{{0, 0, 0}, {0, 0, 1}, {0, 1, 0}, {-1, 0, 0}};
+        lbm_branch b{};
+        const V3 e = f.pos + p.s0 * f.head;
+        b.p0[0] = f.pos.x, b.p0[1] = f.pos.y, b.p0[2] = f.pos.z;
+        b.p1[0] = e.x, b.p1[1] = e.y, b.p1[2] = e.z;
+        b.diameter = p.w0;
+        b.generation = 0;
+        b.parent = -1;
+        b.id = 0;
+        out.push_back(b);
+        f.pos = e;
+        if (p.order > 0)
+            for (int j = p.m - 1; j >= 0; --j)
+                stack.push_back({f, p.s0, p.w0, 1, 0, j});
+    }
+    while (!stack.empty()) {
+        const Pending pe = stack.back();
+        stack.pop_back();
+        const int j = pe.child;
+        const double jit = p.jitter != 0.0 ? p.jitter * (2.0 * rng.uniform() - 1.0) : 0.0;
+        Frame f = roll(pe.parent_end, p.pre_roll[j]);
+        f = pitch(f, p.pitch[j] + jit);
+        f = roll(f, p.post_roll[j]);
+        const double s = pe.s * p.len_ratio[j], w = pe.w * p.wid_ratio[j];
+        const V3 e = f.pos + s * f.head;
+        lbm_branch b{};
+        b.p0[0] = f.pos.x, b.p0[1] = f.pos.y, b.p0[2] = f.pos.z;
+        b.p1[0] = e.x, b.p1[1] = e.y, b.p1[2] = e.z;
+        b.diameter = w;
+        b.generation = pe.gen;
+        b.parent = pe.parent;
+        b.id = (int32_t)out.size();
+        out.push_back(b);
+        f.pos = e;
+        if (pe.gen < p.order)
+            for (int c = p.m - 1; c >= 0; --c)
+                stack.push_back({f, s, w, pe.gen + 1, b.id, c});
+    }
+    return (int)out.size();
+}
+
+double tree_height(const lbm_branch *b, int n)
+{
+    double top = b[0].p0[2];
+    for (int i = 0; i < n; ++i)
+        top = std::max(top, std::max(b[i].p0[2], b[i].p1[2]));
+    return top - b[0].p0[2];
+}
+
+void tree_place(lbm_branch *b, int n, double target_h, const double com[3])
+{
+    const double h = tree_height(b, n);
+    const double sc = (target_h > 0.0 && h > 0.0) ? target_h / h : 1.0;
+    const double o[3] = {b[0].p0[0], b[0].p0[1], b[0].p0[2]};
+    double vol = 0.0, m[3] = {0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            b[i].p0[a] = o[a] + sc * (b[i].p0[a] - o[a]);
+            b[i].p1[a] = o[a] + sc * (b[i].p1[a] - o[a]);
+        }
+        b[i].diameter *= sc;
+        const double dx = b[i].p1[0] - b[i].p0[0], dy = b[i].p1[1] - b[i].p0[1], dz = b[i].p1[2] - b[i].p0[2];
+        const double v = 0.25 * M_PI * b[i].diameter * b[i].diameter * std::sqrt(dx * dx + dy * dy + dz * dz);
+        vol += v;
+        for (int a = 0; a < 3; ++a)
+            m[a] += v * 0.5 * (b[i].p0[a] + b[i].p1[a]);
+    }
+    for (int a = 0; a < 3; ++a) {
+        const double shift = com[a] - m[a] / vol;
+        for (int i = 0; i < n; ++i) {
+            b[i].p0[a] += shift;
+            b[i].p1[a] += shift;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// shapes
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Shape {
+    V3 p0, p1, axis;   // axis: unit vector p0 -> p1
+    double len, r, r2;
+    int id;
+    double lo[3], hi[3];  // bounding box
+};
+
+Shape make_shape(const lbm_branch &b)
+{
+    Shape s;
+    s.p0 = {b.p0[0], b.p0[1], b.p0[2]};
+    s.p1 = {b.p1[0], b.p1[1], b.p1[2]};
+    const V3 d = s.p1 - s.p0;
+    s.len = std::sqrt(dot(d, d));
+    s.axis = (1.0 / s.len) * d;
+    s.r = 0.5 * b.diameter;
+    s.r2 = s.r * s.r;
+    s.id = b.id;
+    const double p0[3] = {s.p0.x, s.p0.y, s.p0.z}, p1[3] = {s.p1.x, s.p1.y, s.p1.z};
+    for (int a = 0; a < 3; ++a) {
+        s.lo[a] = std::min(p0[a], p1[a]) - s.r;
+        s.hi[a] = std::max(p0[a], p1[a]) + s.r;
+    }
+    return s;
+}
+
+// strictly inside the cylinder (open axial range) or the end sphere
+bool inside(const Shape &s, V3 pt)
+{
+    const V3 e = pt - s.p1;
+    if (dot(e, e) < s.r2)
+        return true;
+    const V3 v = pt - s.p0;
+    const double along = dot(v, s.axis);
+    if (!(along > 0.0 && along < s.len))
+        return false;
+    const V3 perp = v - along * s.axis;
+    return dot(perp, perp) < s.r2;
+}
+
+// first parameter t >= 0 at which o + t d is inside the shape (inf if never)
+double entry(const Shape &s, V3 o, V3 d)
+{
+    double best = std::numeric_limits<double>::infinity();
+    // sphere
+    {
+        const V3 w = o - s.p1;
+        const double A = dot(d, d), Bh = dot(w, d), C = dot(w, w) - s.r2;
+        const double disc = Bh * Bh - A * C;
+        if (disc > 0.0) {
+            const double sq = std::sqrt(disc);
+            const double t0 = (-Bh - sq) / A, t1 = (-Bh + sq) / A;
+            if (t1 > 0.0)
+                best = std::max(t0, 0.0);
+        }
+    }
+    // cylinder: slab along the axis intersected with the radial interval
+    {
+        const V3 w = o - s.p0;
+        const double wa = dot(w, s.axis), da = dot(d, s.axis);
+        double lo, hi;
+        if (da != 0.0) {
+            const double ta = -wa / da, tb = (s.len - wa) / da;
+            lo = std::min(ta, tb);
+            hi = std::max(ta, tb);
+        } else if (wa > 0.0 && wa < s.len) {
+            lo = -std::numeric_limits<double>::infinity();
+            hi = std::numeric_limits<double>::infinity();
+        } else {
+            return best;
+        }
+        const V3 r0 = w - wa * s.axis, r1 = d - da * s.axis;
+        const double A = dot(r1, r1), Bh = dot(r0, r1), C = dot(r0, r0) - s.r2;
+        double clo, chi;
+        if (A == 0.0) {
+            if (C >= 0.0)
+                return best;
+            clo = -std::numeric_limits<double>::infinity();
+            chi = std::numeric_limits<double>::infinity();
+        } else {
+            const double disc = Bh * Bh - A * C;
+            if (disc <= 0.0)
+                return best;
+            const double sq = std::sqrt(disc);
+            clo = (-Bh - sq) / A;
+            chi = (-Bh + sq) / A;
+        }
+        const double a = std::max(lo, clo), b = std::min(hi, chi);
+        if (a < b && b > 0.0)
+            best = std::min(best, std::max(a, 0.0));
+    }
+    return best;
+}
+
+}  // namespace
+
+// Exact extent of branch i along axis a: the cylinder's end discs reach
+// r sqrt(1 - axis_a^2) beyond the axis ends, the end sphere r beyond p1.
+static void branch_extent(const Shape &s, int a, double *lo, double *hi)
+{
+    const double p0[3] = {s.p0.x, s.p0.y, s.p0.z}, p1[3] = {s.p1.x, s.p1.y, s.p1.z};
+    const double ax[3] = {s.axis.x, s.axis.y, s.axis.z};
+    const double disc = s.r * std::sqrt(std::max(0.0, 1.0 - ax[a] * ax[a]));
+    *lo = std::min(std::min(p0[a], p1[a]) - disc, p1[a] - s.r);
+    *hi = std::max(std::max(p0[a], p1[a]) + disc, p1[a] + s.r);
+}
+
+bool tree_fits_box(const lbm_branch *b, int n, int nx, int ny, int nz, double margin)
+{
+    const double ext[3] = {(double)nx, (double)ny, (double)nz};
+    for (int i = 0; i < n; ++i) {
+        const Shape s = make_shape(b[i]);
+        for (int a = 0; a < 3; ++a) {
+            double lo, hi;
+            branch_extent(s, a, &lo, &hi);
+            if (lo < margin || hi > ext[a] - margin)
+                return false;
+        }
+    }
+    return true;
+}
+
+void voxelize(const lbm_branch *b, int n, int nx, int ny, int nz, std::vector<uint8_t> &solid)
+{
+    solid.assign((size_t)nx * ny * nz, 0);
+    for (int i = 0; i < n; ++i) {
+        const Shape s = make_shape(b[i]);
+        int lo[3], hi[3];
+        const int ext[3] = {nx, ny, nz};
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::max(0, (int)std::floor(s.lo[a] - 0.5));
+            hi[a] = std::min(ext[a] - 1, (int)std::ceil(s.hi[a] - 0.5));
+        }
+#pragma omp parallel for schedule(static)
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x) {
+                    uint8_t &c = solid[(size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z)];
+                    if (!c && inside(s, {x + 0.5, y + 0.5, z + 0.5}))
+                        c = 1;
+                }
+    }
+}
+
+int64_t build_links(const lbm_branch *b, int n, int nx, int ny, int nz, const std::vector<uint8_t> &solid,
+                    std::vector<HostLink> &links)
+{
+    std::vector<Shape> shapes;
+    shapes.reserve(n);
+    for (int i = 0; i < n; ++i)
+        shapes.push_back(make_shape(b[i]));
+    // coarse bins of 16 cells listing the shapes whose box reaches into them
+    const int BS = 16;
+    const int gx = (nx + BS - 1) / BS, gy = (ny + BS - 1) / BS, gz = (nz + BS - 1) / BS;
+    std::vector<std::vector<int>> bins((size_t)gx * gy * gz);
+    for (int i = 0; i < n; ++i) {
+        int lo[3], hi[3];
+        const int g[3] = {gx, gy, gz};
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::max(0, (int)std::floor((shapes[i].lo[a] - 2.0) / BS));
+            hi[a] = std::min(g[a] - 1, (int)std::floor((shapes[i].hi[a] + 2.0) / BS));
+        }
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x)
+                    bins[(size_t)x + (size_t)gx * ((size_t)y + (size_t)gy * z)].push_back(i);
+    }
+    links.clear();
+    const auto at = [&](int x, int y, int z) { return (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z); };
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t c = at(x, y, z);
+                if (solid[c])
+                    continue;
+                for (int i = 0; i < 27; ++i) {
+                    if (i == 13)
+                        continue;
+                    const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+                    const int sx = x + cx;
+                    if (sx < 0 || sx >= nx)
+                        continue;
+                    const int sy = (y + cy + ny) % ny, sz = (z + cz + nz) % nz;
+                    if (!solid[at(sx, sy, sz)])
+                        continue;
+                    HostLink L;
+                    L.cell = (int64_t)c;
+                    L.dir = (int8_t)i;
+                    const V3 o{x + 0.5, y + 0.5, z + 0.5}, d{(double)cx, (double)cy, (double)cz};
+                    double best = std::numeric_limits<double>::infinity();
+                    int bid = -1;
+                    const V3 mid = o + 0.5 * d;
+                    const int bxi = std::min(gx - 1, std::max(0, (int)(mid.x / BS)));
+                    const int byi = std::min(gy - 1, std::max(0, (int)(mid.y / BS)));
+                    const int bzi = std::min(gz - 1, std::max(0, (int)(mid.z / BS)));
+                    for (int si : bins[(size_t)bxi + (size_t)gx * ((size_t)byi + (size_t)gy * bzi)]) {
+                        const double t = entry(shapes[si], o, d);
+                        if (t < best || (t == best && shapes[si].id < bid)) {
+                            best = t;
+                            bid = shapes[si].id;
+                        }
+                    }
+                    if (!(best <= 1.0))
+                        best = 1.0;
+                    if (best <= 0.0)
+                        best = 1e-12;
+                    L.q = best;
+                    L.branch = bid;
+                    // upstream neighbour x - c_i fluid and inside the box
+                    const int ux = x - cx;
+                    L.up_fluid = (ux >= 0 && ux < nx) && !solid[at(ux, (y - cy + ny) % ny, (z - cz + nz) % nz)];
+                    links.push_back(L);
+                }
+            }
+    return (int64_t)links.size();
+}
+
+int64_t frontal_area(const std::vector<uint8_t> &solid, int nx, int ny, int nz)
+{
+    int64_t a = 0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y) {
+            const uint8_t *row = solid.data() + (size_t)nx * ((size_t)y + (size_t)ny * z);
+            a += std::any_of(row, row + nx, [](uint8_t v) { return v != 0; }) ? 1 : 0;
+        }
+    return a;
+}
+
+}  // namespace lbm

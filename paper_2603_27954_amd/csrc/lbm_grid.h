@@ -1,0 +1,77 @@
+// Grid handle of the C ABI (internal layout).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lbmtree.h"
+#include "lbm_geometry.h"
+#include "lbm_internal.h"
+#include "lbm_levels.h"
+
+using lbm::AmrPlan;
+using lbm::DevLevel;
+using lbm::HostLink;
+
+
+struct lbm_grid {
+    lbm_grid_desc d{};
+    std::string err;
+    int state = 0;  // 0 created, 1 geometry set
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int B = 16, L = 1;
+    double nu_f = 0.0, H = 0.0, area_x = 0.0;
+    std::vector<lbm_branch> branches;
+    std::vector<uint8_t> solid;
+    std::vector<HostLink> links;  // (cell, dir) order
+    std::vector<DevLevel> lv;
+    AmrPlan amr;
+    // device link table (sorted by branch)
+    uint32_t *d_af = nullptr, *d_ap = nullptr, *d_am = nullptr;
+    uint8_t *d_dir = nullptr;
+    float *d_q = nullptr;
+    int n_links = 0;
+    int *d_seg = nullptr;
+    int nseg = 0;
+    float *d_lforce = nullptr;
+    double *d_sample = nullptr, *d_acc_branch = nullptr, *d_acc_total = nullptr, *d_ring = nullptr;
+    unsigned *d_counter = nullptr;
+    double *d_mass = nullptr;
+    std::vector<int32_t> link_perm;  // device order -> (cell, dir) order
+    int64_t samples = 0, ring_count = 0;
+    int64_t coarse_steps = 0, finest_steps = 0;
+    int threads = 256, tile = 0;
+    size_t device_bytes = 0;
+    std::vector<void *> allocs;
+    hipGraphExec_t graph_exec = nullptr;
+    // per-kernel timing (event pairs, kind 0 collide, 1 links)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_pairs;  // (start index, kind)
+    int graph_period = 0;
+    int64_t graph_phase = -1;
+
+    ~lbm_grid()
+    {
+        if (graph_exec)
+            (void)hipGraphExecDestroy(graph_exec);
+        for (hipEvent_t e : ev_pool)
+            (void)hipEventDestroy(e);
+        for (void *p : allocs)
+            (void)hipFree(p);
+        if (own_stream && stream)
+            (void)hipStreamDestroy(stream);
+    }
+};
+
+
+namespace lbm {
+lbm_status grid_fail(lbm_grid *g, lbm_status st, const std::string &msg);
+CollideArgs grid_collide_args(lbm_grid *g, int l);
+lbm_status grid_coarse_step(lbm_grid *g);
+size_t grid_storage_bytes(int storage);
+// records an event on the grid stream when timing is on; returns its index or -1
+int grid_timing_mark(lbm_grid *g);
+}  // namespace lbm

@@ -1,0 +1,94 @@
+// Internal structures shared by the host runtime and the HIP kernels of
+// liblbmtree.so.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace lbm {
+
+// neighbour-table codes for block offsets that leave the box at level 0
+constexpr int NB_INLET = -2;   // x < 0: equilibrium ghost plane
+constexpr int NB_OUTLET = -3;  // x >= nx: zero-gradient ghost plane
+constexpr uint32_t FULL_MASK = 0xFFFFFFFFu;
+
+// Arguments of the collide-and-stream kernel of one level.
+struct CollideArgs {
+    void *pop[27];            // per-direction arrays (storage type), (nb+1)*B^3 each
+    const int *nbr;           // 27 neighbour block ids per block
+    const int *bxyz;          // block coordinates (3 per block)
+    const uint2 *work;        // (block, mask id or FULL_MASK)
+    const uint32_t *masks;    // B^3/32 words per masked block
+    int n_work;
+    int parts;                // work-groups per block
+    float om1, om2;
+    int galilean;
+    int faces;                // 1: this level owns the inlet/outlet planes
+    int nbx;                  // blocks along x (face detection)
+    int ny, nz;               // level box (transverse) in cells
+    float u_in;
+    const float *in_prev;     // inlet fluctuation plane used at t-1 (3*ny*nz) or null
+    const float *in_cur;      // inlet fluctuation plane used at t, or null
+    float *gbuf;              // outlet ghost copies, 27*ny*nz
+};
+
+// Arguments of the interpolated bounce-back kernel (finest level).
+struct LinkArgs {
+    char *pop;                // base of the direction arrays
+    size_t dir_bytes;         // bytes per direction array
+    const uint32_t *af, *ap, *am;  // cell addresses of x_f, x_f + c_j, x_f - c_j
+    const uint8_t *dir;       // j | 0x80 when x_f - c_j is fluid
+    const float *q;
+    int n;
+    float *lforce;            // 3 per link when sampling, else null
+};
+
+struct DevLevel {
+    int level;
+    int nb = 0;               // blocks (sink block has index nb)
+    int nbx = 0, nby = 0, nbz = 0;
+    int nx = 0, ny = 0, nz = 0;
+    size_t dir_elems = 0;     // (nb+1) * B^3
+    void *pop = nullptr;
+    int *nbr = nullptr;
+    int *bxyz = nullptr;
+    uint2 *work = nullptr;    // collide work list
+    int n_work = 0;
+    uint2 *leaf = nullptr;    // leaf-cell work list (mass, fields)
+    int n_leaf = 0;
+    uint32_t *masks = nullptr;
+    float *gbuf = nullptr;
+    double om1 = 1.0;
+    int64_t steps = 0;
+    int64_t updated_cells = 0;
+    int64_t leaf_cells = 0;
+    // host mirrors
+    std::vector<int> h_bxyz;          // 3 per block
+    std::vector<int> h_nbr;           // 27 per block
+    std::vector<int8_t> h_map;        // block map over the lattice (0 none, 1 leaf, 2 refined, 3 ghost)
+    std::vector<int> h_lattice_to_block;  // -1 when absent
+    std::vector<uint2> h_work, h_leaf;
+    std::vector<uint32_t> h_masks;
+};
+
+// launchers (lbm_kernels.hip)
+hipError_t launch_collide(int B, int storage, int odd, const CollideArgs &a, int threads,
+                          hipStream_t s);
+hipError_t launch_links(int storage, int odd_done, const LinkArgs &a, hipStream_t s);
+hipError_t launch_init(int B, int storage, void *pop, size_t dir_elems, const uint2 *leafwork,
+                       int n, const uint32_t *masks, float u_in, hipStream_t s);
+hipError_t launch_fill_sink_and_all(int storage, void *pop, size_t dir_elems, hipStream_t s);
+hipError_t launch_branch_reduce(const float *lforce, const int *seg, int nseg, double *sample,
+                                double *acc_branch, double *acc_total, double *ring, int ring_slot,
+                                unsigned *counter, hipStream_t s);
+hipError_t launch_gather(int B, int storage, int odd, const CollideArgs &a, const uint2 *cells,
+                         int n, double *out_f, size_t out_stride, hipStream_t s);
+hipError_t launch_scatter(int B, int storage, void *pop, size_t dir_elems, const uint2 *cells,
+                          int n, const double *in_f, size_t in_stride, hipStream_t s);
+hipError_t launch_mass(int B, int storage, int odd, const CollideArgs &a, const uint2 *leaf,
+                       int n_leaf, double cell_volume, double *out4, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,674 @@
+// HIP kernels for gfx950: collide-and-stream with in-place A-A streaming,
+// interpolated bounce-back with momentum exchange, FP64 force and mass
+// reductions, initialisation and state transfer (paper Sec. 2.2).
+//
+// Storage: per level, one array per direction i (structure of arrays), each
+// holding (nb + 1) cubic blocks of B^3 cells (block nb is a sink for absent
+// neighbours).  Cell c of block b lives at element b * B^3 + c, with
+// c = x + B (y + B z).  Values are deviations g = f - w.
+//
+// A-A pattern (one array, in place): an even step reads population i of cell
+// x from slot i of x and writes the post-collision f*_i to slot opp(i) of x; an
+// odd step reads population opp(k) of x from slot k of x + c_k and writes f*_k
+// to the same slot k of x + c_k.  Each cell touches a set of slots no other
+// cell touches, so a step needs no second array and no intra-step barrier.
+// After an even number of steps population i of x sits in slot i of x.
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+
+template <typename S>
+__device__ __forceinline__ float ldp(const void *base, uint32_t elem)
+{
+    return Store<S>::ld(reinterpret_cast<const S *>(base)[elem]);
+}
+template <typename S>
+__device__ __forceinline__ void stp(void *base, uint32_t elem, float v)
+{
+    reinterpret_cast<S *>(base)[elem] = Store<S>::st(v);
+}
+
+// Work-group id -> logical id so that consecutive logical ids run on the same
+// XCD (work-groups are dealt to the eight XCDs round-robin).
+__device__ __forceinline__ int xcd_remap(int i, int n)
+{
+    const int xcd = i & 7, idx = i >> 3;
+    const int per = n >> 3, rem = n & 7;
+    const int base = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+    return base + idx;
+}
+
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Per-lane neighbour addressing: for an offset s in {-1,0,1} along each axis
+// the local part of the neighbour's cell index and its contribution to the
+// 3x3x3 block-offset code.
+template <int B>
+struct NbrLane {
+    static constexpr int LB = B == 16 ? 4 : 3;
+    int lx[3], ly[3], lz[3], kx[3], ky[3], kz[3];
+    __device__ __forceinline__ NbrLane(int x, int y, int z)
+    {
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int xs = x + s - 1, ys = y + s - 1, zs = z + s - 1;
+            lx[s] = xs & (B - 1);
+            ly[s] = (ys & (B - 1)) << LB;
+            lz[s] = (zs & (B - 1)) << (2 * LB);
+            kx[s] = xs < 0 ? 0 : (xs >= B ? 2 : 1);
+            ky[s] = 3 * (ys < 0 ? 0 : (ys >= B ? 2 : 1));
+            kz[s] = 9 * (zs < 0 ? 0 : (zs >= B ? 2 : 1));
+        }
+    }
+    __device__ __forceinline__ int code(int sx, int sy, int sz) const { return kx[sx] + ky[sy] + kz[sz]; }
+    __device__ __forceinline__ int local(int sx, int sy, int sz) const { return lx[sx] + ly[sy] + lz[sz]; }
+};
+
+// ---------------------------------------------------------------------------
+// collide and stream
+// ---------------------------------------------------------------------------
+
+template <int B, typename S, bool ODD>
+__device__ __forceinline__ void cell_update(const CollideArgs &a, int blk, int c, const int *nb,
+                                            bool face_block, int bx, int by, int bz)
+{
+    constexpr int CELLS = B * B * B;
+    constexpr int LB = B == 16 ? 4 : 3;
+    const int x = c & (B - 1), y = (c >> LB) & (B - 1), z = c >> (2 * LB);
+    const uint32_t own = (uint32_t)blk * CELLS + c;
+    float g[NQ];
+
+    if (!ODD) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            g[k] = ldp<S>(a.pop[k], own);
+        collide(g, a.om1, a.om2, a.galilean != 0);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            stp<S>(a.pop[qopp(k)], own, g[k]);
+        if (face_block) {
+            const int gx = bx * B + x;
+            if (gx == a.nbx * B - 1) {
+                const int gy = by * B + y, gz = bz * B + z;
+                const size_t pl = (size_t)a.ny * a.nz;
+#pragma unroll
+                for (int i = 0; i < NQ; ++i)
+                    if (qcx(i) == -1)
+                        a.gbuf[i * pl + (size_t)gz * a.ny + gy] = g[i];
+            }
+        }
+        return;
+    }
+
+    const NbrLane<B> L(x, y, z);
+    uint32_t addr[NQ];
+    int nbk[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const int sx = qcx(k) + 1, sy = qcy(k) + 1, sz = qcz(k) + 1;
+        nbk[k] = nb[L.code(sx, sy, sz)];
+        const int b = nbk[k] < 0 ? blk : nbk[k];
+        addr[k] = (uint32_t)b * CELLS + L.local(sx, sy, sz);
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        g[qopp(k)] = ldp<S>(a.pop[k], addr[k]);
+
+    int gx = 0, gy = 0, gz = 0;
+    if (face_block) {
+        gx = bx * B + x;
+        gy = by * B + y;
+        gz = bz * B + z;
+        const size_t pl = (size_t)a.ny * a.nz;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            if (qcx(k) == 0)
+                continue;
+            if (nbk[k] == NB_INLET) {
+                // population opp(k) enters from the inlet ghost at (y + cy_k, z + cz_k)
+                const int ty = wrapi(gy + qcy(k), a.ny), tz = wrapi(gz + qcz(k), a.nz);
+                float ux = a.u_in, uy = 0.0f, uz = 0.0f;
+                if (a.in_prev) {
+                    const float *p = a.in_prev + 3 * ((size_t)tz * a.ny + ty);
+                    ux += p[0];
+                    uy = p[1];
+                    uz = p[2];
+                }
+                g[qopp(k)] = feq_dev(qopp(k), ux, uy, uz);
+            } else if (nbk[k] == NB_OUTLET) {
+                const int ty = wrapi(gy + qcy(k), a.ny), tz = wrapi(gz + qcz(k), a.nz);
+                g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)tz * a.ny + ty];
+            }
+        }
+    }
+
+    collide(g, a.om1, a.om2, a.galilean != 0);
+
+    if (!face_block) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            stp<S>(a.pop[k], addr[k], g[k]);
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        if (nbk[k] >= 0 || qcx(k) == 0)
+            stp<S>(a.pop[k], addr[k], g[k]);
+    const int lastx = a.nbx * B - 1;
+    if (gx == 0) {
+        // populations entering from the inlet ghost for the next (even) step
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            if (qcx(i) != 1)
+                continue;
+            const int ty = wrapi(gy - qcy(i), a.ny), tz = wrapi(gz - qcz(i), a.nz);
+            float ux = a.u_in, uy = 0.0f, uz = 0.0f;
+            if (a.in_cur) {
+                const float *p = a.in_cur + 3 * ((size_t)tz * a.ny + ty);
+                ux += p[0];
+                uy = p[1];
+                uz = p[2];
+            }
+            stp<S>(a.pop[i], own, feq_dev(i, ux, uy, uz));
+        }
+    }
+    if (gx == lastx) {
+        // the outlet ghost (nx, y, z) copies this cell; its populations with
+        // cx = -1 land on (nx - 1, y + cy, z + cz)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            if (qcx(i) != -1)
+                continue;
+            const int sy = qcy(i) + 1, sz = qcz(i) + 1;
+            const int b = nb[L.code(1, sy, sz)];
+            stp<S>(a.pop[i], (uint32_t)b * CELLS + L.local(1, sy, sz), g[i]);
+        }
+    }
+}
+
+template <int B, typename S, bool ODD>
+__global__ void __launch_bounds__(256) k_collide(const CollideArgs a)
+{
+    constexpr int CELLS = B * B * B;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int item = wg / a.parts, part = wg - item * a.parts;
+    if (item >= a.n_work)
+        return;
+    const uint2 w = a.work[item];
+    const int blk = (int)w.x;
+    __shared__ int nb[27];
+    if (threadIdx.x < 27)
+        nb[threadIdx.x] = a.nbr[(size_t)blk * 27 + threadIdx.x];
+    __syncthreads();
+    const int bx = a.bxyz[3 * blk], by = a.bxyz[3 * blk + 1], bz = a.bxyz[3 * blk + 2];
+    const bool face_block = a.faces && (bx == 0 || bx == a.nbx - 1);
+    const int tile = CELLS / a.parts;
+    const int c0 = part * tile;
+    const uint32_t *mask = w.y == FULL_MASK ? nullptr : a.masks + (size_t)w.y * (CELLS / 32);
+    for (int c = c0 + (int)threadIdx.x; c < c0 + tile; c += (int)blockDim.x) {
+        if (mask && !((mask[c >> 5] >> (c & 31)) & 1u))
+            continue;
+        cell_update<B, S, ODD>(a, blk, c, nb, face_block, bx, by, bz);
+    }
+}
+
+template <int B, typename S>
+static hipError_t launch_collide_t(int odd, const CollideArgs &a, int threads, hipStream_t s)
+{
+    const int grid = a.n_work * a.parts;
+    if (grid == 0)
+        return hipSuccess;
+    if (odd)
+        hipLaunchKernelGGL((k_collide<B, S, true>), dim3(grid), dim3(threads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_collide<B, S, false>), dim3(grid), dim3(threads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_collide(int B, int storage, int odd, const CollideArgs &a, int threads, hipStream_t s)
+{
+    if (B == 16) {
+        if (storage == 0) return launch_collide_t<16, float>(odd, a, threads, s);
+        if (storage == 1) return launch_collide_t<16, __half>(odd, a, threads, s);
+        return launch_collide_t<16, __hip_bfloat16>(odd, a, threads, s);
+    }
+    if (storage == 0) return launch_collide_t<8, float>(odd, a, threads, s);
+    if (storage == 1) return launch_collide_t<8, __half>(odd, a, threads, s);
+    return launch_collide_t<8, __hip_bfloat16>(odd, a, threads, s);
+}
+
+// ---------------------------------------------------------------------------
+// interpolated bounce-back (Bouzidi, linear) + momentum exchange
+// ---------------------------------------------------------------------------
+
+template <typename S, bool ODD_DONE>
+__global__ void __launch_bounds__(256) k_links(const LinkArgs a)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= a.n)
+        return;
+    const uint8_t dj = a.dir[l];
+    const int j = dj & 31, jb = 26 - j;
+    const bool up = (dj & 0x80) != 0;
+    const float q = a.q[l];
+    const uint32_t af = a.af[l], ap = a.ap[l], am = a.am[l];
+    const S *pj = reinterpret_cast<const S *>(a.pop + (size_t)j * a.dir_bytes);
+    const S *pjb = reinterpret_cast<const S *>(a.pop + (size_t)jb * a.dir_bytes);
+    float g1, g2, g3;  // f*_j(x_f), f*_j(x_f - c_j), f*_opp(j)(x_f)
+    if (!ODD_DONE) {
+        g1 = Store<S>::ld(pjb[af]);
+        g3 = Store<S>::ld(pj[af]);
+        g2 = up ? Store<S>::ld(pjb[am]) : 0.0f;
+    } else {
+        g1 = Store<S>::ld(pj[ap]);
+        g3 = Store<S>::ld(pjb[am]);
+        g2 = up ? Store<S>::ld(pj[af]) : 0.0f;
+    }
+    float gn;
+    if (q < 0.5f)
+        gn = up ? fmaf(2.0f * q, g1 - g2, g2) : g1;
+    else {
+        const float r = 0.5f / q;
+        gn = fmaf(r, g1 - g3, g3);
+    }
+    S *dst = reinterpret_cast<S *>(a.pop + (size_t)(ODD_DONE ? jb : j) * a.dir_bytes);
+    dst[ODD_DONE ? af : ap] = Store<S>::st(gn);
+    if (a.lforce) {
+        const float wj = w1d(qcx(j)) * w1d(qcy(j)) * w1d(qcz(j));
+        const float mom = 2.0f * wj + g1 + gn;
+        a.lforce[3 * (size_t)l + 0] = qcx(j) * mom;
+        a.lforce[3 * (size_t)l + 1] = qcy(j) * mom;
+        a.lforce[3 * (size_t)l + 2] = qcz(j) * mom;
+    }
+}
+
+hipError_t launch_links(int storage, int odd_done, const LinkArgs &a, hipStream_t s)
+{
+    if (a.n == 0)
+        return hipSuccess;
+    const dim3 grid((a.n + 255) / 256), blk(256);
+#define LBM_LINKS(T)                                                         \
+    if (odd_done)                                                            \
+        hipLaunchKernelGGL((k_links<T, true>), grid, blk, 0, s, a);          \
+    else                                                                     \
+        hipLaunchKernelGGL((k_links<T, false>), grid, blk, 0, s, a);
+    if (storage == 0) {
+        LBM_LINKS(float)
+    } else if (storage == 1) {
+        LBM_LINKS(__half)
+    } else {
+        LBM_LINKS(__hip_bfloat16)
+    }
+#undef LBM_LINKS
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Sum of a work-group's values in a fixed order (lane tree per wave, then
+// waves in order): the same inputs give the same bits on every run.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+        sh[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NT / 64; ++i)
+            t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+// One work-group per branch segment (links sorted by branch); the last
+// work-group to finish adds the per-branch sums in branch order into the total,
+// appends it to the sample ring and resets the counter.
+__global__ void __launch_bounds__(256) k_branch_reduce(const float *lforce, const int *seg, int nseg,
+                                                       double *sample, double *acc_branch,
+                                                       double *acc_total, double *ring, int ring_slot,
+                                                       unsigned *counter)
+{
+    __shared__ double sh[4];
+    __shared__ bool last;
+    const int b = blockIdx.x;
+    const int s0 = seg[b], s1 = seg[b + 1];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int l = s0 + (int)threadIdx.x; l < s1; l += 256) {
+        v[0] += (double)lforce[3 * (size_t)l];
+        v[1] += (double)lforce[3 * (size_t)l + 1];
+        v[2] += (double)lforce[3 * (size_t)l + 2];
+    }
+    for (int a = 0; a < 3; ++a) {
+        const double t = block_sum<256>(v[a], sh);
+        if (threadIdx.x == 0) {
+            sample[3 * b + a] = t;
+            acc_branch[3 * b + a] += t;
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(counter, 1u) == (unsigned)nseg - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        double t[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < nseg; ++i)
+            for (int a = 0; a < 3; ++a)
+                t[a] += __builtin_nontemporal_load(&sample[3 * i + a]);
+        for (int a = 0; a < 3; ++a) {
+            acc_total[a] += t[a];
+            ring[3 * ring_slot + a] = t[a];
+        }
+        *counter = 0u;
+    }
+}
+
+hipError_t launch_branch_reduce(const float *lforce, const int *seg, int nseg, double *sample,
+                                double *acc_branch, double *acc_total, double *ring, int ring_slot,
+                                unsigned *counter, hipStream_t s)
+{
+    if (nseg == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_branch_reduce, dim3(nseg), dim3(256), 0, s, lforce, seg, nseg, sample,
+                       acc_branch, acc_total, ring, ring_slot, counter);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// state transfer: pre-collision populations of listed cells (FP64, full f)
+// ---------------------------------------------------------------------------
+
+template <int B, typename S, bool ODD>
+__device__ __forceinline__ void load_pre(const CollideArgs &a, int blk, int c, float (&g)[NQ])
+{
+    constexpr int CELLS = B * B * B;
+    constexpr int LB = B == 16 ? 4 : 3;
+    const uint32_t own = (uint32_t)blk * CELLS + c;
+    if (!ODD) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            g[k] = ldp<S>(a.pop[k], own);
+        return;
+    }
+    const int x = c & (B - 1), y = (c >> LB) & (B - 1), z = c >> (2 * LB);
+    const NbrLane<B> L(x, y, z);
+    const int *nb = a.nbr + (size_t)blk * 27;
+    const int bx = a.bxyz[3 * blk], by = a.bxyz[3 * blk + 1], bz = a.bxyz[3 * blk + 2];
+    const int gy = by * B + y, gz = bz * B + z;
+    const size_t pl = (size_t)a.ny * a.nz;
+    (void)bx;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const int sx = qcx(k) + 1, sy = qcy(k) + 1, sz = qcz(k) + 1;
+        const int n = nb[L.code(sx, sy, sz)];
+        if (n == NB_INLET) {
+            const int ty = wrapi(gy + qcy(k), a.ny), tz = wrapi(gz + qcz(k), a.nz);
+            float ux = a.u_in, uy = 0.0f, uz = 0.0f;
+            if (a.in_prev) {
+                const float *p = a.in_prev + 3 * ((size_t)tz * a.ny + ty);
+                ux += p[0];
+                uy = p[1];
+                uz = p[2];
+            }
+            g[qopp(k)] = feq_dev(qopp(k), ux, uy, uz);
+        } else if (n == NB_OUTLET) {
+            const int ty = wrapi(gy + qcy(k), a.ny), tz = wrapi(gz + qcz(k), a.nz);
+            g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)tz * a.ny + ty];
+        } else {
+            g[qopp(k)] = ldp<S>(a.pop[k], (uint32_t)n * CELLS + L.local(sx, sy, sz));
+        }
+    }
+}
+
+template <int B, typename S, bool ODD>
+__global__ void __launch_bounds__(256) k_gather(const CollideArgs a, const uint2 *cells, int n,
+                                                double *out, size_t stride)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n)
+        return;
+    const uint2 cc = cells[t];
+    float g[NQ];
+    load_pre<B, S, ODD>(a, (int)cc.x, (int)cc.y, g);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+        out[i * stride + t] = (double)g[i] + (double)qw(i);
+}
+
+template <int B, typename S>
+static hipError_t launch_gather_t(int odd, const CollideArgs &a, const uint2 *cells, int n, double *out,
+                                  size_t stride, hipStream_t s)
+{
+    const dim3 grid((n + 255) / 256), blk(256);
+    if (odd)
+        hipLaunchKernelGGL((k_gather<B, S, true>), grid, blk, 0, s, a, cells, n, out, stride);
+    else
+        hipLaunchKernelGGL((k_gather<B, S, false>), grid, blk, 0, s, a, cells, n, out, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(int B, int storage, int odd, const CollideArgs &a, const uint2 *cells, int n,
+                         double *out, size_t stride, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    if (B == 16) {
+        if (storage == 0) return launch_gather_t<16, float>(odd, a, cells, n, out, stride, s);
+        if (storage == 1) return launch_gather_t<16, __half>(odd, a, cells, n, out, stride, s);
+        return launch_gather_t<16, __hip_bfloat16>(odd, a, cells, n, out, stride, s);
+    }
+    if (storage == 0) return launch_gather_t<8, float>(odd, a, cells, n, out, stride, s);
+    if (storage == 1) return launch_gather_t<8, __half>(odd, a, cells, n, out, stride, s);
+    return launch_gather_t<8, __hip_bfloat16>(odd, a, cells, n, out, stride, s);
+}
+
+// natural layout write (even parity): slot i of the cell holds population i
+template <int B, typename S>
+__global__ void __launch_bounds__(256) k_scatter(void *pop, size_t dir_elems, const uint2 *cells, int n,
+                                                 const double *in, size_t stride)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n)
+        return;
+    const uint2 cc = cells[t];
+    const size_t e = (size_t)cc.x * (B * B * B) + cc.y;
+    S *p = reinterpret_cast<S *>(pop);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+        p[i * dir_elems + e] = Store<S>::st((float)(in[i * stride + t] - (double)qw(i)));
+}
+
+hipError_t launch_scatter(int B, int storage, void *pop, size_t dir_elems, const uint2 *cells, int n,
+                          const double *in, size_t stride, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    const dim3 grid((n + 255) / 256), blk(256);
+#define LBM_SC(BB, T) hipLaunchKernelGGL((k_scatter<BB, T>), grid, blk, 0, s, pop, dir_elems, cells, n, in, stride)
+    if (B == 16) {
+        if (storage == 0) LBM_SC(16, float);
+        else if (storage == 1) LBM_SC(16, __half);
+        else LBM_SC(16, __hip_bfloat16);
+    } else {
+        if (storage == 0) LBM_SC(8, float);
+        else if (storage == 1) LBM_SC(8, __half);
+        else LBM_SC(8, __hip_bfloat16);
+    }
+#undef LBM_SC
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// initial state: f = f_eq(1, (u_in, 0, 0)) on the listed cells, natural layout
+// ---------------------------------------------------------------------------
+
+template <int B, typename S>
+__global__ void __launch_bounds__(256) k_init(void *pop, size_t dir_elems, const uint2 *work, int n,
+                                              const uint32_t *masks, float u_in)
+{
+    constexpr int CELLS = B * B * B;
+    const int item = blockIdx.x;
+    if (item >= n)
+        return;
+    const uint2 w = work[item];
+    const uint32_t *mask = w.y == FULL_MASK ? nullptr : masks + (size_t)w.y * (CELLS / 32);
+    S *p = reinterpret_cast<S *>(pop);
+    for (int c = threadIdx.x; c < CELLS; c += blockDim.x) {
+        const size_t e = (size_t)w.x * CELLS + c;
+        const bool fluid = !mask || ((mask[c >> 5] >> (c & 31)) & 1u);
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            p[i * dir_elems + e] = Store<S>::st(fluid ? feq_dev(i, u_in, 0.0f, 0.0f) : 0.0f);
+    }
+}
+
+hipError_t launch_init(int B, int storage, void *pop, size_t dir_elems, const uint2 *work, int n,
+                       const uint32_t *masks, float u_in, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+#define LBM_IN(BB, T) hipLaunchKernelGGL((k_init<BB, T>), dim3(n), dim3(256), 0, s, pop, dir_elems, work, n, masks, u_in)
+    if (B == 16) {
+        if (storage == 0) LBM_IN(16, float);
+        else if (storage == 1) LBM_IN(16, __half);
+        else LBM_IN(16, __hip_bfloat16);
+    } else {
+        if (storage == 0) LBM_IN(8, float);
+        else if (storage == 1) LBM_IN(8, __half);
+        else LBM_IN(8, __hip_bfloat16);
+    }
+#undef LBM_IN
+    return hipGetLastError();
+}
+
+// zero deviations everywhere (sink block included): weights = rest state
+template <typename S>
+__global__ void k_zero(S *p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = Store<S>::st(0.0f);
+}
+
+hipError_t launch_fill_sink_and_all(int storage, void *pop, size_t dir_elems, hipStream_t s)
+{
+    const size_t n = dir_elems * NQ;
+    const dim3 grid(2048), blk(256);
+    if (storage == 0) hipLaunchKernelGGL(k_zero<float>, grid, blk, 0, s, (float *)pop, n);
+    else if (storage == 1) hipLaunchKernelGGL(k_zero<__half>, grid, blk, 0, s, (__half *)pop, n);
+    else hipLaunchKernelGGL(k_zero<__hip_bfloat16>, grid, blk, 0, s, (__hip_bfloat16 *)pop, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 mass and health check over leaf fluid cells:
+// out4 = {sum rho * volume, min rho, max rho, count of non-finite}
+// ---------------------------------------------------------------------------
+
+template <int B, typename S, bool ODD>
+__global__ void __launch_bounds__(256) k_mass(const CollideArgs a, const uint2 *leaf, int n_leaf,
+                                              double vol, double *part)
+{
+    constexpr int CELLS = B * B * B;
+    __shared__ double sh[4];
+    double m = 0.0, mn = 1e300, mx = -1e300, bad = 0.0;
+    for (int item = blockIdx.x; item < n_leaf; item += gridDim.x) {
+        const uint2 w = leaf[item];
+        const uint32_t *mask = w.y == FULL_MASK ? nullptr : a.masks + (size_t)w.y * (CELLS / 32);
+        for (int c = threadIdx.x; c < CELLS; c += blockDim.x) {
+            if (mask && !((mask[c >> 5] >> (c & 31)) & 1u))
+                continue;
+            float g[NQ];
+            load_pre<B, S, ODD>(a, (int)w.x, c, g);
+            double r = 1.0;
+            for (int i = 0; i < NQ; ++i)
+                r += (double)g[i];
+            if (!(r == r) || r > 1e30 || r < -1e30) {
+                bad += 1.0;
+                continue;
+            }
+            m += r * vol;
+            mn = r < mn ? r : mn;
+            mx = r > mx ? r : mx;
+        }
+    }
+    const double tm = block_sum<256>(m, sh);
+    const double tb = block_sum<256>(bad, sh);
+    // min / max through the same tree
+    __shared__ double smn[256], smx[256];
+    smn[threadIdx.x] = mn;
+    smx[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            smn[threadIdx.x] = fmin(smn[threadIdx.x], smn[threadIdx.x + o]);
+            smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[4 * blockIdx.x + 0] = tm;
+        part[4 * blockIdx.x + 1] = smn[0];
+        part[4 * blockIdx.x + 2] = smx[0];
+        part[4 * blockIdx.x + 3] = tb;
+    }
+}
+
+__global__ void k_mass_final(const double *part, int n, double *out4)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    double m = 0.0, mn = 1e300, mx = -1e300, bad = 0.0;
+    for (int i = 0; i < n; ++i) {
+        m += part[4 * i];
+        mn = fmin(mn, part[4 * i + 1]);
+        mx = fmax(mx, part[4 * i + 2]);
+        bad += part[4 * i + 3];
+    }
+    out4[0] += m;
+    out4[1] = fmin(out4[1], mn);
+    out4[2] = fmax(out4[2], mx);
+    out4[3] += bad;
+}
+
+hipError_t launch_mass(int B, int storage, int odd, const CollideArgs &a, const uint2 *leaf, int n_leaf,
+                       double vol, double *out4, hipStream_t s)
+{
+    if (n_leaf == 0)
+        return hipSuccess;
+    const int nblk = n_leaf < 1024 ? n_leaf : 1024;
+    double *part = out4 + 4;  // caller provides 4 + 4*1024 doubles
+#define LBM_MS(BB, T)                                                                              \
+    if (odd)                                                                                       \
+        hipLaunchKernelGGL((k_mass<BB, T, true>), dim3(nblk), dim3(256), 0, s, a, leaf, n_leaf, vol, part); \
+    else                                                                                           \
+        hipLaunchKernelGGL((k_mass<BB, T, false>), dim3(nblk), dim3(256), 0, s, a, leaf, n_leaf, vol, part);
+    if (B == 16) {
+        if (storage == 0) { LBM_MS(16, float) }
+        else if (storage == 1) { LBM_MS(16, __half) }
+        else { LBM_MS(16, __hip_bfloat16) }
+    } else {
+        if (storage == 0) { LBM_MS(8, float) }
+        else if (storage == 1) { LBM_MS(8, __half) }
+        else { LBM_MS(8, __hip_bfloat16) }
+    }
+#undef LBM_MS
+    hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(64), 0, s, part, nblk, out4);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

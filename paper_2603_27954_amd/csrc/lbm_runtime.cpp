@@ -1,0 +1,805 @@
+// Host runtime and C ABI of liblbmtree (declared in include/lbmtree.h).
+//
+// Owns the grid description, the finest-level geometry (solid mask, links),
+// the block grid of every level, the device buffers and the step schedule.
+// Every device operation runs on the grid's stream; synchronising calls
+// (drag, state access) wait on it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/lbmtree.h"
+#include "lbm_geometry.h"
+#include "lbm_internal.h"
+#include "lbm_levels.h"
+#include "lbm_grid.h"
+
+using namespace lbm;
+
+static thread_local std::string g_thread_error;
+
+static const int RING = 65536;
+
+static lbm_status fail(lbm_grid *g, lbm_status st, const std::string &msg)
+{
+    if (g)
+        g->err = msg;
+    else
+        g_thread_error = msg;
+    return st;
+}
+
+#define HIPX(g, call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail((g), LBM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+static lbm_status dalloc(lbm_grid *g, T **p, size_t count)
+{
+    void *q = nullptr;
+    if (count == 0)
+        count = 1;
+    const hipError_t e = hipMalloc(&q, count * sizeof(T));
+    if (e != hipSuccess)
+        return fail(g, LBM_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    g->allocs.push_back(q);
+    g->device_bytes += count * sizeof(T);
+    *p = (T *)q;
+    return LBM_OK;
+}
+
+template <typename T>
+static lbm_status upload(lbm_grid *g, T **p, const std::vector<T> &h)
+{
+    lbm_status st = dalloc(g, p, h.size());
+    if (st != LBM_OK)
+        return st;
+    if (!h.empty())
+        HIPX(g, hipMemcpyAsync(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, g->stream));
+    return LBM_OK;
+}
+
+static size_t storage_bytes(int storage) { return storage == LBM_FP32 ? 4 : 2; }
+
+static int nu_to_level_omega(double nu_f, int L, int l, double *om)
+{
+    const double nu = nu_f / double(1 << (L - 1 - l));
+    *om = 1.0 / (3.0 * nu + 0.5);
+    return 0;
+}
+
+// kernel arguments of level l for the current state
+static CollideArgs collide_args(lbm_grid *g, int l)
+{
+    DevLevel &v = g->lv[l];
+    CollideArgs a{};
+    const size_t eb = storage_bytes(g->d.storage);
+    for (int k = 0; k < 27; ++k)
+        a.pop[k] = (char *)v.pop + (size_t)k * v.dir_elems * eb;
+    a.nbr = v.nbr;
+    a.bxyz = v.bxyz;
+    a.work = v.work;
+    a.masks = v.masks;
+    a.n_work = v.n_work;
+    const int cells = g->B * g->B * g->B;
+    a.parts = std::max(1, cells / std::max(1, g->tile));
+    a.om1 = (float)v.om1;
+    a.om2 = 1.0f;
+    a.galilean = (g->d.flags & LBM_F_NO_GALILEAN) ? 0 : 1;
+    a.faces = l == 0 ? 1 : 0;
+    a.nbx = v.nbx;
+    a.ny = v.ny;
+    a.nz = v.nz;
+    a.u_in = (float)g->d.u_in;
+    a.in_prev = nullptr;
+    a.in_cur = nullptr;
+    a.gbuf = v.gbuf;
+    return a;
+}
+
+static LinkArgs link_args(lbm_grid *g, bool sample)
+{
+    DevLevel &v = g->lv[g->L - 1];
+    LinkArgs a{};
+    a.pop = (char *)v.pop;
+    a.dir_bytes = v.dir_elems * storage_bytes(g->d.storage);
+    a.af = g->d_af;
+    a.ap = g->d_ap;
+    a.am = g->d_am;
+    a.dir = g->d_dir;
+    a.q = g->d_q;
+    a.n = g->n_links;
+    a.lforce = sample ? g->d_lforce : nullptr;
+    return a;
+}
+
+// ---------------------------------------------------------------------------
+// step schedule
+// ---------------------------------------------------------------------------
+
+static int timing_mark(lbm_grid *g)
+{
+    if (!g->timing)
+        return -1;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess)
+        return -1;
+    g->ev_pool.push_back(e);
+    (void)hipEventRecord(e, g->stream);
+    return (int)g->ev_pool.size() - 1;
+}
+
+static lbm_status level_collide(lbm_grid *g, int l)
+{
+    DevLevel &v = g->lv[l];
+    const int odd = (int)(v.steps & 1);
+    CollideArgs a = collide_args(g, l);
+    const int e0 = timing_mark(g);
+    HIPX(g, launch_collide(g->B, g->d.storage, odd, a, g->threads, g->stream));
+    const int e1 = timing_mark(g);
+    if (e0 >= 0 && e1 >= 0)
+        g->ev_pairs.push_back({e0, 0});
+    return LBM_OK;
+}
+
+static lbm_status finest_links(lbm_grid *g, int odd_done)
+{
+    const bool sample = (g->finest_steps % g->d.drag_every) == 0;
+    if (g->n_links > 0) {
+        LinkArgs a = link_args(g, sample);
+        const int e0 = timing_mark(g);
+        HIPX(g, launch_links(g->d.storage, odd_done, a, g->stream));
+        const int e1 = timing_mark(g);
+        if (e0 >= 0 && e1 >= 0)
+            g->ev_pairs.push_back({e0, 1});
+    }
+    if (sample) {
+        if (g->n_links > 0) {
+            HIPX(g, launch_branch_reduce(g->d_lforce, g->d_seg, g->nseg, g->d_sample, g->d_acc_branch,
+                                         g->d_acc_total, g->d_ring, (int)(g->ring_count % RING),
+                                         g->d_counter, g->stream));
+        }
+        g->samples++;
+        g->ring_count++;
+    }
+    return LBM_OK;
+}
+
+static lbm_status advance_level(lbm_grid *g, int l);
+
+static lbm_status advance_level(lbm_grid *g, int l)
+{
+    lbm_status st;
+    const bool finest = l == g->L - 1;
+    if (!finest) {
+        st = amr_moments(g->amr, g->lv, l, 0, g->d.storage, g->B, g->stream, &g->err);
+        if (st != LBM_OK)
+            return st;
+    }
+    DevLevel &v = g->lv[l];
+    const int odd = (int)(v.steps & 1);
+    st = level_collide(g, l);
+    if (st != LBM_OK)
+        return st;
+    v.steps++;
+    if (finest) {
+        g->finest_steps++;
+        st = finest_links(g, odd);
+        if (st != LBM_OK)
+            return st;
+        return LBM_OK;
+    }
+    for (int sub = 0; sub < 2; ++sub) {
+        if (sub == 1) {
+            st = amr_moments(g->amr, g->lv, l, 1, g->d.storage, g->B, g->stream, &g->err);
+            if (st != LBM_OK)
+                return st;
+        }
+        st = amr_prolong(g->amr, g->lv, l, sub, g->d.storage, g->B, g->d.flags, g->stream, &g->err);
+        if (st != LBM_OK)
+            return st;
+        st = advance_level(g, l + 1);
+        if (st != LBM_OK)
+            return st;
+    }
+    return amr_restrict(g->amr, g->lv, l, g->d.storage, g->B, g->d.flags, g->stream, &g->err);
+}
+
+static lbm_status coarse_step(lbm_grid *g)
+{
+    lbm_status st = advance_level(g, 0);
+    if (st == LBM_OK)
+        g->coarse_steps++;
+    return st;
+}
+
+namespace lbm {
+lbm_status grid_fail(lbm_grid *g, lbm_status st, const std::string &msg) { return fail(g, st, msg); }
+CollideArgs grid_collide_args(lbm_grid *g, int l) { return collide_args(g, l); }
+lbm_status grid_coarse_step(lbm_grid *g) { return coarse_step(g); }
+size_t grid_storage_bytes(int storage) { return storage_bytes(storage); }
+int grid_timing_mark(lbm_grid *g) { return timing_mark(g); }
+}  // namespace lbm
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *lbm_last_error(const lbm_grid *g)
+{
+    if (g)
+        return g->err.c_str();
+    return g_thread_error.c_str();
+}
+
+lbm_status lbm_create_grid(const lbm_grid_desc *d, lbm_grid **out)
+{
+    if (!d || !out)
+        return fail(nullptr, LBM_E_INVALID, "null argument");
+    *out = nullptr;
+    const int B = d->block_edge;
+    if (B != 8 && B != 16)
+        return fail(nullptr, LBM_E_INVALID, "block_edge must be 8 or 16");
+    if (d->levels < 1 || d->levels > 4)
+        return fail(nullptr, LBM_E_INVALID, "levels must be 1..4");
+    const int unit = B << (d->levels - 1);
+    if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0 || d->nx % unit || d->ny % unit || d->nz % unit)
+        return fail(nullptr, LBM_E_INVALID, "nx, ny, nz must be positive multiples of block_edge << (levels-1)");
+    if ((int64_t)(d->nx / unit) * (d->ny / unit) * (d->nz / unit) > (1 << 24))
+        return fail(nullptr, LBM_E_INVALID, "too many coarse blocks");
+    if (!(d->u_in >= 0.0) || std::sqrt(3.0) * d->u_in >= 0.3)
+        return fail(nullptr, LBM_E_INVALID, "u_in must satisfy 0 <= sqrt(3) u_in < 0.3");
+    if (!(d->nu > 0.0) && !(d->re_h > 0.0))
+        return fail(nullptr, LBM_E_INVALID, "need nu > 0 or re_h > 0");
+    if (d->storage < 0 || d->storage > 2)
+        return fail(nullptr, LBM_E_INVALID, "storage must be LBM_FP32, LBM_FP16_DEV or LBM_BF16_DEV");
+    if (d->periodic_yz != 1)
+        return fail(nullptr, LBM_E_INVALID, "only periodic lateral faces are supported (periodic_yz = 1)");
+    if (d->drag_every < 0)
+        return fail(nullptr, LBM_E_INVALID, "drag_every must be >= 1");
+    if (d->turb_intensity < 0.0 || d->turb_intensity > 0.5)
+        return fail(nullptr, LBM_E_INVALID, "turb_intensity must be in [0, 0.5]");
+    if (d->turb_intensity > 0.0 && !(d->turb_length > 0.0))
+        return fail(nullptr, LBM_E_INVALID, "turb_length must be > 0 with inflow turbulence");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return fail(nullptr, LBM_E_DEVICE, "no HIP device available");
+    if (d->device < 0 || d->device >= ndev)
+        return fail(nullptr, LBM_E_INVALID, "device ordinal out of range");
+    lbm_grid *g = new (std::nothrow) lbm_grid();
+    if (!g)
+        return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    g->d = *d;
+    if (g->d.drag_every == 0)
+        g->d.drag_every = 1;
+    if (g->d.turb_modes <= 0)
+        g->d.turb_modes = 200;
+    g->B = B;
+    g->L = d->levels;
+    g->tile = B * B * B;
+    if (hipSetDevice(d->device) != hipSuccess) {
+        delete g;
+        return fail(nullptr, LBM_E_DEVICE, "hipSetDevice failed");
+    }
+    if (d->stream) {
+        g->stream = (hipStream_t)d->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete g;
+            return fail(nullptr, LBM_E_DEVICE, "hipStreamCreate failed");
+        }
+        g->own_stream = true;
+    }
+    *out = g;
+    return LBM_OK;
+}
+
+void lbm_destroy_grid(lbm_grid *g)
+{
+    if (!g)
+        return;
+    if (g->stream)
+        (void)hipStreamSynchronize(g->stream);
+    delete g;
+}
+
+lbm_status lbm_tree_generate(const lbm_tree_params *p, lbm_branch *out, int32_t cap, int32_t *n)
+{
+    if (!p || !n)
+        return fail(nullptr, LBM_E_INVALID, "null argument");
+    if (p->m < 1 || p->m > 4 || p->order < 0 || p->order > 12 || !(p->s0 > 0) || !(p->w0 > 0))
+        return fail(nullptr, LBM_E_INVALID, "tree parameters out of range");
+    double total = 1, lvl = 1;
+    for (int k = 0; k < p->order; ++k) {
+        lvl *= p->m;
+        total += lvl;
+    }
+    if (total > 4.0e6)
+        return fail(nullptr, LBM_E_INVALID, "tree too large");
+    std::vector<lbm_branch> v;
+    tree_generate(*p, v);
+    *n = (int32_t)v.size();
+    if (out)
+        std::memcpy(out, v.data(), sizeof(lbm_branch) * std::min<size_t>(v.size(), cap > 0 ? cap : 0));
+    return LBM_OK;
+}
+
+lbm_status lbm_tree_place(lbm_branch *b, int32_t n, double target_h, const double com[3], double *height_out)
+{
+    if (!b || n <= 0 || !com)
+        return fail(nullptr, LBM_E_INVALID, "null argument or empty tree");
+    tree_place(b, n, target_h, com);
+    if (height_out)
+        *height_out = tree_height(b, n);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const lbm_refine_desc *refine,
+                            size_t *device_bytes_out)
+{
+    if (!g)
+        return fail(nullptr, LBM_E_INVALID, "null grid");
+    if (g->state != 0)
+        return fail(g, LBM_E_STATE, "geometry already set");
+    if (!b || n_b <= 0)
+        return fail(g, LBM_E_INVALID, "need at least one branch");
+    for (int i = 0; i < n_b; ++i) {
+        if (b[i].id != i)
+            return fail(g, LBM_E_INVALID, "branch ids must be 0 .. n_b-1 in order");
+        if (!(b[i].diameter > 0.0))
+            return fail(g, LBM_E_INVALID, "branch diameter must be > 0");
+        const double dx = b[i].p1[0] - b[i].p0[0], dy = b[i].p1[1] - b[i].p0[1], dz = b[i].p1[2] - b[i].p0[2];
+        if (!(dx * dx + dy * dy + dz * dz > 0.0))
+            return fail(g, LBM_E_INVALID, "branch of zero length");
+    }
+    const lbm_grid_desc &d = g->d;
+    const int margin = g->L == 1 ? 2 : g->B << (g->L - 1);
+    if (!tree_fits_box(b, n_b, d.nx, d.ny, d.nz, margin))
+        return fail(g, LBM_E_INVALID, "tree comes too close to the box faces");
+    if (g->L > 1 && !refine)
+        return fail(g, LBM_E_INVALID, "refinement bands required when levels > 1");
+    (void)hipSetDevice(d.device);
+    g->branches.assign(b, b + n_b);
+    g->H = tree_height(b, n_b);
+    g->nu_f = d.nu > 0.0 ? d.nu : d.u_in * g->H / d.re_h;
+    if (!(g->nu_f > 0.0) || !(g->nu_f < 10.0))
+        return fail(g, LBM_E_INVALID, "finest viscosity out of range");
+
+    voxelize(b, n_b, d.nx, d.ny, d.nz, g->solid);
+    build_links(b, n_b, d.nx, d.ny, d.nz, g->solid, g->links);
+    g->area_x = (double)frontal_area(g->solid, d.nx, d.ny, d.nz);
+
+    // block grid of every level
+    std::string msg;
+    lbm_status st = build_levels(d, g->B, g->L, b, n_b, refine, g->solid, g->lv, g->amr, &msg);
+    if (st != LBM_OK)
+        return fail(g, st, msg);
+    for (int l = 0; l < g->L; ++l)
+        nu_to_level_omega(g->nu_f, g->L, l, &g->lv[l].om1);
+
+    // device buffers of the levels
+    const size_t eb = storage_bytes(d.storage);
+    for (int l = 0; l < g->L; ++l) {
+        DevLevel &v = g->lv[l];
+        const size_t cells = (size_t)g->B * g->B * g->B;
+        v.dir_elems = (size_t)(v.nb + 1) * cells;
+        if (v.dir_elems > (size_t)UINT32_MAX / 2)
+            return fail(g, LBM_E_INVALID, "level too large for 32-bit cell addressing");
+        char *pop = nullptr;
+        if ((st = dalloc(g, &pop, v.dir_elems * 27 * eb)) != LBM_OK)
+            return st;
+        v.pop = pop;
+        if ((st = upload(g, &v.nbr, v.h_nbr)) != LBM_OK || (st = upload(g, &v.bxyz, v.h_bxyz)) != LBM_OK ||
+            (st = upload(g, &v.work, v.h_work)) != LBM_OK || (st = upload(g, &v.leaf, v.h_leaf)) != LBM_OK ||
+            (st = upload(g, &v.masks, v.h_masks)) != LBM_OK)
+            return st;
+        v.n_work = (int)v.h_work.size();
+        v.n_leaf = (int)v.h_leaf.size();
+        if (l == 0) {
+            if ((st = dalloc(g, &v.gbuf, (size_t)27 * v.ny * v.nz)) != LBM_OK)
+                return st;
+            HIPX(g, hipMemsetAsync(v.gbuf, 0, sizeof(float) * 27 * (size_t)v.ny * v.nz, g->stream));
+        }
+        HIPX(g, launch_fill_sink_and_all(d.storage, v.pop, v.dir_elems, g->stream));
+        HIPX(g, launch_init(g->B, d.storage, v.pop, v.dir_elems, v.leaf, v.n_leaf, v.masks, (float)d.u_in,
+                            g->stream));
+        // ghost / band cells start from the same uniform state
+        HIPX(g, launch_init(g->B, d.storage, v.pop, v.dir_elems, v.work, v.n_work, v.masks, (float)d.u_in,
+                            g->stream));
+    }
+    if ((st = amr_upload(g->amr, g->lv, g->B, [&](void **p, size_t bytes) -> lbm_status {
+             char *q = nullptr;
+             lbm_status s2 = dalloc(g, &q, bytes);
+             *p = q;
+             return s2;
+         }, g->stream, &g->err)) != LBM_OK)
+        return st;
+
+    // links on the finest level, sorted by branch (segments for the reduction)
+    {
+        const DevLevel &fv = g->lv[g->L - 1];
+        const int nl = (int)g->links.size();
+        std::vector<int32_t> perm(nl);
+        std::iota(perm.begin(), perm.end(), 0);
+        std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) {
+            const int ba = g->links[a].branch < 0 ? n_b : g->links[a].branch;
+            const int bc = g->links[c].branch < 0 ? n_b : g->links[c].branch;
+            return ba < bc;
+        });
+        g->link_perm = perm;
+        std::vector<uint32_t> af(nl), ap(nl), am(nl);
+        std::vector<uint8_t> dr(nl);
+        std::vector<float> q(nl);
+        g->nseg = n_b + 1;
+        std::vector<int> seg(g->nseg + 1, 0);
+        const int fx = d.nx, fy = d.ny;
+        for (int t = 0; t < nl; ++t) {
+            const HostLink &Lk = g->links[perm[t]];
+            const int x = (int)(Lk.cell % fx), y = (int)((Lk.cell / fx) % fy), z = (int)(Lk.cell / ((int64_t)fx * fy));
+            const int i = Lk.dir, cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+            const int64_t a0 = level_cell_address(fv, g->B, x, y, z);
+            const int64_t a1 = level_cell_address(fv, g->B, x + cx, y + cy, z + cz);
+            const int64_t a2 = level_cell_address(fv, g->B, x - cx, y - cy, z - cz);
+            if (a0 < 0 || a1 < 0 || a2 < 0)
+                return fail(g, LBM_E_INVALID, "boundary link outside the finest level");
+            af[t] = (uint32_t)a0;
+            ap[t] = (uint32_t)a1;
+            am[t] = (uint32_t)a2;
+            dr[t] = (uint8_t)(i | (Lk.up_fluid ? 0x80 : 0));
+            q[t] = (float)Lk.q;
+            seg[(Lk.branch < 0 ? n_b : Lk.branch) + 1]++;
+        }
+        for (int s = 0; s < g->nseg; ++s)
+            seg[s + 1] += seg[s];
+        g->n_links = nl;
+        if ((st = upload(g, &g->d_af, af)) != LBM_OK || (st = upload(g, &g->d_ap, ap)) != LBM_OK ||
+            (st = upload(g, &g->d_am, am)) != LBM_OK || (st = upload(g, &g->d_dir, dr)) != LBM_OK ||
+            (st = upload(g, &g->d_q, q)) != LBM_OK || (st = upload(g, &g->d_seg, seg)) != LBM_OK)
+            return st;
+        if ((st = dalloc(g, &g->d_lforce, (size_t)3 * std::max(nl, 1))) != LBM_OK ||
+            (st = dalloc(g, &g->d_sample, (size_t)3 * g->nseg)) != LBM_OK ||
+            (st = dalloc(g, &g->d_acc_branch, (size_t)3 * g->nseg)) != LBM_OK ||
+            (st = dalloc(g, &g->d_acc_total, 3)) != LBM_OK || (st = dalloc(g, &g->d_ring, (size_t)3 * RING)) != LBM_OK ||
+            (st = dalloc(g, &g->d_counter, 1)) != LBM_OK || (st = dalloc(g, &g->d_mass, 4 + 4 * 1024)) != LBM_OK)
+            return st;
+        HIPX(g, hipMemsetAsync(g->d_acc_branch, 0, sizeof(double) * 3 * g->nseg, g->stream));
+        HIPX(g, hipMemsetAsync(g->d_acc_total, 0, sizeof(double) * 3, g->stream));
+        HIPX(g, hipMemsetAsync(g->d_ring, 0, sizeof(double) * 3 * RING, g->stream));
+        HIPX(g, hipMemsetAsync(g->d_counter, 0, sizeof(unsigned), g->stream));
+    }
+    HIPX(g, hipStreamSynchronize(g->stream));
+    g->state = 1;
+    if (device_bytes_out)
+        *device_bytes_out = g->device_bytes;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_grid *g, int32_t n)
+{
+    if (!g)
+        return fail(nullptr, LBM_E_INVALID, "null grid");
+    if (g->state != 1)
+        return fail(g, LBM_E_STATE, "set_geometry first");
+    if (n < 0)
+        return fail(g, LBM_E_INVALID, "negative step count");
+    for (int s = 0; s < n; ++s) {
+        lbm_status st = coarse_step(g);
+        if (st != LBM_OK)
+            return st;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_mass(lbm_grid *g, double *mass)
+{
+    if (!g || !mass)
+        return fail(g, LBM_E_INVALID, "null argument");
+    if (g->state != 1)
+        return fail(g, LBM_E_STATE, "set_geometry first");
+    double init[4] = {0.0, 1e300, -1e300, 0.0};
+    HIPX(g, hipMemcpyAsync(g->d_mass, init, sizeof init, hipMemcpyHostToDevice, g->stream));
+    for (int l = 0; l < g->L; ++l) {
+        DevLevel &v = g->lv[l];
+        CollideArgs a = collide_args(g, l);
+        const double h = double(1 << (g->L - 1 - l));
+        HIPX(g, launch_mass(g->B, g->d.storage, (int)(v.steps & 1), a, v.leaf, v.n_leaf, h * h * h, g->d_mass,
+                            g->stream));
+    }
+    double out[4];
+    HIPX(g, hipMemcpyAsync(out, g->d_mass, sizeof out, hipMemcpyDeviceToHost, g->stream));
+    HIPX(g, hipStreamSynchronize(g->stream));
+    *mass = out[0];
+    if (out[3] > 0.0 || out[1] < 0.5 || out[2] > 1.5)
+        return fail(g, LBM_E_UNSTABLE, "non-finite or out-of-range density detected");
+    return LBM_OK;
+}
+
+lbm_status lbm_drag(lbm_grid *g, lbm_drag_result *out, double *per_branch)
+{
+    if (!g || !out)
+        return fail(g, LBM_E_INVALID, "null argument");
+    if (g->state != 1)
+        return fail(g, LBM_E_STATE, "set_geometry first");
+    std::memset(out, 0, sizeof *out);
+    const int nb = (int)g->branches.size();
+    std::vector<double> acc(3 * g->nseg, 0.0);
+    double tot[3] = {0, 0, 0};
+    HIPX(g, hipMemcpyAsync(acc.data(), g->d_acc_branch, sizeof(double) * acc.size(), hipMemcpyDeviceToHost, g->stream));
+    HIPX(g, hipMemcpyAsync(tot, g->d_acc_total, sizeof tot, hipMemcpyDeviceToHost, g->stream));
+    HIPX(g, hipStreamSynchronize(g->stream));
+    HIPX(g, hipMemsetAsync(g->d_acc_branch, 0, sizeof(double) * acc.size(), g->stream));
+    HIPX(g, hipMemsetAsync(g->d_acc_total, 0, sizeof tot, g->stream));
+    const double ns = (double)std::max<int64_t>(g->samples, 1);
+    for (int a = 0; a < 3; ++a)
+        out->force[a] = tot[a] / ns;
+    if (per_branch)
+        for (int i = 0; i < nb; ++i)
+            for (int a = 0; a < 3; ++a)
+                per_branch[3 * i + a] = acc[3 * i + a] / ns;
+    out->samples = g->samples;
+    g->samples = 0;
+    out->area_x = g->area_x;
+    out->height = g->H;
+    out->cd = g->area_x > 0 && g->d.u_in > 0 ? out->force[0] / (0.5 * g->d.u_in * g->d.u_in * g->area_x) : 0.0;
+    out->step = g->coarse_steps;
+    return lbm_mass(g, &out->mass);
+}
+
+lbm_status lbm_drag_series(lbm_grid *g, double *out, int64_t cap, int64_t *n)
+{
+    if (!g || !n || (!out && cap > 0))
+        return fail(g, LBM_E_INVALID, "null argument");
+    if (g->state != 1)
+        return fail(g, LBM_E_STATE, "set_geometry first");
+    std::vector<double> ring(3 * (size_t)RING);
+    HIPX(g, hipMemcpyAsync(ring.data(), g->d_ring, sizeof(double) * ring.size(), hipMemcpyDeviceToHost, g->stream));
+    HIPX(g, hipStreamSynchronize(g->stream));
+    const int64_t have = std::min<int64_t>(g->ring_count, RING);
+    const int64_t m = std::min(have, cap);
+    const int64_t first = g->ring_count - m;
+    for (int64_t s = 0; s < m; ++s)
+        for (int a = 0; a < 3; ++a)
+            out[3 * s + a] = ring[3 * ((first + s) % RING) + a];
+    *n = m;
+    return LBM_OK;
+}
+
+lbm_status lbm_timing_enable(lbm_grid *g, int32_t enable)
+{
+    if (!g)
+        return fail(nullptr, LBM_E_INVALID, "null grid");
+    HIPX(g, hipStreamSynchronize(g->stream));
+    for (hipEvent_t e : g->ev_pool)
+        (void)hipEventDestroy(e);
+    g->ev_pool.clear();
+    g->ev_pairs.clear();
+    g->timing = enable != 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_timing_read(lbm_grid *g, double *collide_ms, int64_t *collide_n, double *links_ms, int64_t *links_n)
+{
+    if (!g)
+        return fail(nullptr, LBM_E_INVALID, "null grid");
+    HIPX(g, hipStreamSynchronize(g->stream));
+    double t[2] = {0.0, 0.0};
+    int64_t n[2] = {0, 0};
+    for (const auto &pr : g->ev_pairs) {
+        float ms = 0.0f;
+        HIPX(g, hipEventElapsedTime(&ms, g->ev_pool[pr.first], g->ev_pool[pr.first + 1]));
+        t[pr.second] += ms;
+        n[pr.second]++;
+    }
+    if (collide_ms) *collide_ms = t[0];
+    if (collide_n) *collide_n = n[0];
+    if (links_ms) *links_ms = t[1];
+    if (links_n) *links_n = n[1];
+    return LBM_OK;
+}
+
+lbm_status lbm_get_info(const lbm_grid *g, lbm_info *out)
+{
+    if (!g || !out)
+        return fail(const_cast<lbm_grid *>(g), LBM_E_INVALID, "null argument");
+    std::memset(out, 0, sizeof *out);
+    out->levels = g->L;
+    out->block_edge = g->B;
+    out->storage = g->d.storage;
+    for (int l = 0; l < (int)g->lv.size(); ++l) {
+        out->blocks[l] = g->lv[l].nb;
+        out->active_cells[l] = g->lv[l].leaf_cells;
+        out->updated_cells[l] = g->lv[l].updated_cells;
+        out->omega1[l] = g->lv[l].om1;
+    }
+    out->links = g->n_links;
+    out->branches = (int32_t)g->branches.size();
+    out->height = g->H;
+    out->area_x = g->area_x;
+    out->nu_finest = g->nu_f;
+    out->device_bytes = g->device_bytes;
+    out->tile_cells = g->tile;
+    return LBM_OK;
+}
+
+// dense per-level cell lists (block, local) in box order, for state transfer
+static void level_dense_cells(const lbm_grid *g, int l, std::vector<uint2> &cells, std::vector<int64_t> &pos)
+{
+    const DevLevel &v = g->lv[l];
+    const int B = g->B;
+    cells.clear();
+    pos.clear();
+    for (int z = 0; z < v.nz; ++z)
+        for (int y = 0; y < v.ny; ++y)
+            for (int x = 0; x < v.nx; ++x) {
+                const int bx = x / B, by = y / B, bz = z / B;
+                const int bi = v.h_lattice_to_block[(size_t)bx + (size_t)v.nbx * ((size_t)by + (size_t)v.nby * bz)];
+                if (bi < 0)
+                    continue;
+                const int8_t kind = v.h_map[(size_t)bx + (size_t)v.nbx * ((size_t)by + (size_t)v.nby * bz)];
+                if (kind != 1 && kind != 2)
+                    continue;
+                cells.push_back(make_uint2((unsigned)bi, (unsigned)((x % B) + B * ((y % B) + B * (z % B)))));
+                pos.push_back((int64_t)x + (int64_t)v.nx * ((int64_t)y + (int64_t)v.ny * z));
+            }
+}
+
+static lbm_status with_cells(lbm_grid *g, int l, std::vector<uint2> &cells, std::vector<int64_t> &pos,
+                             uint2 **d_cells)
+{
+    level_dense_cells(g, l, cells, pos);
+    void *p = nullptr;
+    HIPX(g, hipMalloc(&p, sizeof(uint2) * std::max<size_t>(cells.size(), 1)));
+    *d_cells = (uint2 *)p;
+    HIPX(g, hipMemcpy(p, cells.data(), sizeof(uint2) * cells.size(), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_grid *g, int32_t level, double *f)
+{
+    if (!g || !f)
+        return fail(g, LBM_E_INVALID, "null argument");
+    if (g->state != 1)
+        return fail(g, LBM_E_STATE, "set_geometry first");
+    if (level < 0 || level >= g->L)
+        return fail(g, LBM_E_INVALID, "level out of range");
+    HIPX(g, hipStreamSynchronize(g->stream));
+    std::vector<uint2> cells;
+    std::vector<int64_t> pos;
+    uint2 *dc = nullptr;
+    lbm_status st = with_cells(g, level, cells, pos, &dc);
+    if (st != LBM_OK)
+        return st;
+    const size_t n = cells.size();
+    double *dout = nullptr;
+    HIPX(g, hipMalloc((void **)&dout, sizeof(double) * 27 * std::max<size_t>(n, 1)));
+    DevLevel &v = g->lv[level];
+    CollideArgs a = collide_args(g, level);
+    HIPX(g, launch_gather(g->B, g->d.storage, (int)(v.steps & 1), a, dc, (int)n, dout, n, g->stream));
+    std::vector<double> h(27 * n);
+    HIPX(g, hipMemcpyAsync(h.data(), dout, sizeof(double) * h.size(), hipMemcpyDeviceToHost, g->stream));
+    HIPX(g, hipStreamSynchronize(g->stream));
+    (void)hipFree(dout);
+    (void)hipFree(dc);
+    const size_t N = (size_t)v.nx * v.ny * v.nz;
+    for (size_t i = 0; i < 27 * N; ++i)
+        f[i] = NAN;
+    for (size_t t = 0; t < n; ++t)
+        for (int i = 0; i < 27; ++i)
+            f[i * N + pos[t]] = h[i * n + t];
+    return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_grid *g, int32_t level, const double *f)
+{
+    if (!g || !f)
+        return fail(g, LBM_E_INVALID, "null argument");
+    if (g->state != 1)
+        return fail(g, LBM_E_STATE, "set_geometry first");
+    if (level < 0 || level >= g->L)
+        return fail(g, LBM_E_INVALID, "level out of range");
+    DevLevel &v = g->lv[level];
+    if (v.steps & 1)
+        return fail(g, LBM_E_STATE, "populations can be set only after an even number of level steps");
+    HIPX(g, hipStreamSynchronize(g->stream));
+    std::vector<uint2> cells;
+    std::vector<int64_t> pos;
+    uint2 *dc = nullptr;
+    lbm_status st = with_cells(g, level, cells, pos, &dc);
+    if (st != LBM_OK)
+        return st;
+    const size_t n = cells.size();
+    const size_t N = (size_t)v.nx * v.ny * v.nz;
+    std::vector<double> h(27 * n);
+    for (size_t t = 0; t < n; ++t)
+        for (int i = 0; i < 27; ++i)
+            h[i * n + t] = f[i * N + pos[t]];
+    double *din = nullptr;
+    HIPX(g, hipMalloc((void **)&din, sizeof(double) * std::max<size_t>(h.size(), 1)));
+    HIPX(g, hipMemcpy(din, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+    HIPX(g, launch_scatter(g->B, g->d.storage, v.pop, v.dir_elems, dc, (int)n, din, n, g->stream));
+    HIPX(g, hipStreamSynchronize(g->stream));
+    (void)hipFree(din);
+    (void)hipFree(dc);
+    return LBM_OK;
+}
+
+lbm_status lbm_get_fields(lbm_grid *g, int32_t level, double *rho, double *u)
+{
+    if (!g || !rho || !u)
+        return fail(g, LBM_E_INVALID, "null argument");
+    if (level < 0 || level >= g->L)
+        return fail(g, LBM_E_INVALID, "level out of range");
+    const DevLevel &v = g->lv[level];
+    const size_t N = (size_t)v.nx * v.ny * v.nz;
+    std::vector<double> f(27 * N);
+    lbm_status st = lbm_get_populations(g, level, f.data());
+    if (st != LBM_OK)
+        return st;
+    for (size_t c = 0; c < N; ++c) {
+        double r = 0, j[3] = {0, 0, 0};
+        for (int i = 0; i < 27; ++i) {
+            const double val = f[i * N + c];
+            r += val;
+            j[0] += (i % 3 - 1) * val;
+            j[1] += ((i / 3) % 3 - 1) * val;
+            j[2] += (i / 9 - 1) * val;
+        }
+        rho[c] = r;
+        for (int a = 0; a < 3; ++a)
+            u[3 * c + a] = j[a] / r;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_get_solid(lbm_grid *g, uint8_t *solid)
+{
+    if (!g || !solid)
+        return fail(g, LBM_E_INVALID, "null argument");
+    if (g->state != 1)
+        return fail(g, LBM_E_STATE, "set_geometry first");
+    std::memcpy(solid, g->solid.data(), g->solid.size());
+    return LBM_OK;
+}
+
+lbm_status lbm_get_links(lbm_grid *g, int64_t cap, int64_t *cell, int8_t *dir, double *q, int32_t *branch,
+                         int64_t *n)
+{
+    if (!g || !n)
+        return fail(g, LBM_E_INVALID, "null argument");
+    if (g->state != 1)
+        return fail(g, LBM_E_STATE, "set_geometry first");
+    *n = (int64_t)g->links.size();
+    const int64_t m = std::min<int64_t>(cap, *n);
+    for (int64_t t = 0; t < m; ++t) {
+        if (cell) cell[t] = g->links[t].cell;
+        if (dir) dir[t] = g->links[t].dir;
+        if (q) q[t] = g->links[t].q;
+        if (branch) branch[t] = g->links[t].branch;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_get_block_map(lbm_grid *g, int32_t level, int8_t *map)
+{
+    if (!g || !map)
+        return fail(g, LBM_E_INVALID, "null argument");
+    if (g->state != 1)
+        return fail(g, LBM_E_STATE, "set_geometry first");
+    if (level < 0 || level >= g->L)
+        return fail(g, LBM_E_INVALID, "level out of range");
+    std::memcpy(map, g->lv[level].h_map.data(), g->lv[level].h_map.size());
+    return LBM_OK;
+}
+
+}  // extern "C"
