@@ -16,14 +16,18 @@ constexpr int NB_OUTLET = -3;  // x >= nx: zero-gradient ghost plane
 constexpr uint32_t FULL_MASK = 0xFFFFFFFFu;
 
 // Arguments of the collide-and-stream kernel of one level.
+constexpr int DENSE_TILE = 256;  // cells per work item of a dense level
+
 struct CollideArgs {
-    void *pop[27];            // per-direction arrays (storage type), (nb+1)*B^3 each
+    void *pop[27];            // per-direction arrays (storage type)
     const int *nbr;           // 27 neighbour block ids per block
     const int *bxyz;          // block coordinates (3 per block)
     const uint2 *work;        // (block, mask id or FULL_MASK)
     const uint32_t *masks;    // B^3/32 words per masked block
     int n_work;
-    int parts;                // work-groups per block
+    int parts;                // work-groups per block (block layout)
+    int dense;                // 1: level stored as x-pencils over its whole box
+    int nx;                   // level box along x (cells)
     float om1, om2;
     int galilean;
     int faces;                // 1: this level owns the inlet/outlet planes
@@ -48,14 +52,15 @@ struct LinkArgs {
 
 struct DevLevel {
     int level;
+    bool dense = false;       // x-pencil layout over the whole box (no blocks)
     int nb = 0;               // blocks (sink block has index nb)
     int nbx = 0, nby = 0, nbz = 0;
     int nx = 0, ny = 0, nz = 0;
-    size_t dir_elems = 0;     // (nb+1) * B^3
+    size_t dir_elems = 0;     // dense: nx*ny*nz; blocks: (nb+1) * B^3
     void *pop = nullptr;
     int *nbr = nullptr;
     int *bxyz = nullptr;
-    uint2 *work = nullptr;    // collide work list
+    uint2 *work = nullptr;    // collide work list (unit, mask id): dense tiles or blocks
     int n_work = 0;
     uint2 *leaf = nullptr;    // leaf-cell work list (mass, fields)
     int n_leaf = 0;
@@ -78,15 +83,16 @@ struct DevLevel {
 hipError_t launch_collide(int B, int storage, int odd, const CollideArgs &a, int threads,
                           hipStream_t s);
 hipError_t launch_links(int storage, int odd_done, const LinkArgs &a, hipStream_t s);
-hipError_t launch_init(int B, int storage, void *pop, size_t dir_elems, const uint2 *leafwork,
+hipError_t launch_init(int unit, int storage, void *pop, size_t dir_elems, const uint2 *work,
                        int n, const uint32_t *masks, float u_in, hipStream_t s);
 hipError_t launch_fill_sink_and_all(int storage, void *pop, size_t dir_elems, hipStream_t s);
 hipError_t launch_branch_reduce(const float *lforce, const int *seg, int nseg, double *sample,
                                 double *acc_branch, double *acc_total, double *ring, int ring_slot,
                                 unsigned *counter, hipStream_t s);
-hipError_t launch_gather(int B, int storage, int odd, const CollideArgs &a, const uint2 *cells,
+// element addresses (dense: x + nx (y + ny z); blocks: block * B^3 + local)
+hipError_t launch_gather(int B, int storage, int odd, const CollideArgs &a, const uint32_t *cells,
                          int n, double *out_f, size_t out_stride, hipStream_t s);
-hipError_t launch_scatter(int B, int storage, void *pop, size_t dir_elems, const uint2 *cells,
+hipError_t launch_scatter(int storage, void *pop, size_t dir_elems, const uint32_t *cells,
                           int n, const double *in_f, size_t in_stride, hipStream_t s);
 hipError_t launch_mass(int B, int storage, int odd, const CollideArgs &a, const uint2 *leaf,
                        int n_leaf, double cell_volume, double *out4, hipStream_t s);

@@ -2,10 +2,15 @@
 // interpolated bounce-back with momentum exchange, FP64 force and mass
 // reductions, initialisation and state transfer (paper Sec. 2.2).
 //
-// Storage: per level, one array per direction i (structure of arrays), each
-// holding (nb + 1) cubic blocks of B^3 cells (block nb is a sink for absent
-// neighbours).  Cell c of block b lives at element b * B^3 + c, with
-// c = x + B (y + B z).  Values are deviations g = f - w.
+// Storage: per level, one array per direction i (structure of arrays).  A
+// level that covers its whole box (the uniform grid, the coarsest level) is
+// stored as x-pencils: cell (x, y, z) at element x + nx (y + ny z), so x
+// neighbours stay contiguous across the whole row.  A sparse (refined) level
+// holds (nb + 1) cubic blocks of B^3 cells, block nb being a sink for absent
+// neighbours: cell c = x + B (y + B z) of block b at element b * B^3 + c.
+// Values are deviations g = f - w.  Even steps use non-temporal loads and
+// stores (pure streaming); odd steps keep the caches, which merge the
+// neighbour-shifted partial lines.
 //
 // A-A pattern (one array, in place): an even step reads population i of cell
 // x from slot i of x and writes the post-collision f*_i to slot opp(i) of x; an
@@ -29,14 +34,38 @@ __device__ __forceinline__ void stp(void *base, uint32_t elem, float v)
     reinterpret_cast<S *>(base)[elem] = Store<S>::st(v);
 }
 
-// Work-group id -> logical id so that consecutive logical ids run on the same
-// XCD (work-groups are dealt to the eight XCDs round-robin).
-__device__ __forceinline__ int xcd_remap(int i, int n)
+template <typename S>
+__device__ __forceinline__ float ldp_nt(const void *base, uint32_t elem)
 {
-    const int xcd = i & 7, idx = i >> 3;
-    const int per = n >> 3, rem = n & 7;
-    const int base = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
-    return base + idx;
+    if constexpr (sizeof(S) == 4) {
+        return __builtin_nontemporal_load(reinterpret_cast<const float *>(base) + elem);
+    } else {
+        const unsigned short bits = __builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(base) + elem);
+        return Store<S>::ld(__builtin_bit_cast(S, bits));
+    }
+}
+template <typename S>
+__device__ __forceinline__ void stp_nt(void *base, uint32_t elem, float v)
+{
+    if constexpr (sizeof(S) == 4) {
+        __builtin_nontemporal_store(v, reinterpret_cast<float *>(base) + elem);
+    } else {
+        const S h = Store<S>::st(v);
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, h), reinterpret_cast<unsigned short *>(base) + elem);
+    }
+}
+
+// equilibrium deviation of direction i in the inlet ghost cell at (ty, tz)
+__device__ __forceinline__ float inlet_dev(const CollideArgs &a, const float *plane, int i, int ty, int tz)
+{
+    float ux = a.u_in, uy = 0.0f, uz = 0.0f;
+    if (plane) {
+        const float *p = plane + 3 * ((size_t)tz * a.ny + ty);
+        ux += p[0];
+        uy = p[1];
+        uz = p[2];
+    }
+    return feq_dev(i, ux, uy, uz);
 }
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
@@ -66,132 +95,138 @@ struct NbrLane {
 };
 
 // ---------------------------------------------------------------------------
-// collide and stream
+// collide and stream: dense (x-pencil) levels
+// ---------------------------------------------------------------------------
+
+template <typename S, bool ODD>
+__global__ void __launch_bounds__(256) k_collide_dense(const CollideArgs a)
+{
+    const int item = blockIdx.x;
+    if (item >= a.n_work)
+        return;
+    const uint2 w = a.work[item];
+    const int t = threadIdx.x;
+    if (w.y != FULL_MASK) {
+        const uint32_t *m = a.masks + (size_t)w.y * (DENSE_TILE / 32);
+        if (!((m[t >> 5] >> (t & 31)) & 1u))
+            return;
+    }
+    const uint32_t own = w.x * DENSE_TILE + t;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int x = (int)(own % (uint32_t)nx);
+    const uint32_t yz = own / (uint32_t)nx;
+    const int y = (int)(yz % (uint32_t)ny), z = (int)(yz / (uint32_t)ny);
+    const bool at_in = a.faces && x == 0, at_out = a.faces && x == nx - 1;
+    float g[NQ];
+
+    if (!ODD) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            g[k] = ldp_nt<S>(a.pop[k], own);
+        collide(g, a.om1, a.om2, a.galilean != 0);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            stp_nt<S>(a.pop[qopp(k)], own, g[k]);
+        if (at_out) {
+            const size_t pl = (size_t)ny * nz;
+#pragma unroll
+            for (int i = 0; i < NQ; ++i)
+                if (qcx(i) == -1)
+                    a.gbuf[i * pl + (size_t)z * ny + y] = g[i];
+        }
+        return;
+    }
+
+    // odd: population opp(k) comes from slot k of x + c_k, f*_k goes back there
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ys[3] = {ym, y, yp}, zs[3] = {zm, z, zp}, xs[3] = {xm, x, xp};
+    uint32_t addr[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        addr[k] = (uint32_t)xs[qcx(k) + 1] + (uint32_t)nx * ((uint32_t)ys[qcy(k) + 1] + (uint32_t)ny * zs[qcz(k) + 1]);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        g[qopp(k)] = ldp<S>(a.pop[k], addr[k]);
+    if (at_in || at_out) {
+        const size_t pl = (size_t)ny * nz;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int ty = ys[qcy(k) + 1], tz = zs[qcz(k) + 1];
+            if (at_in && qcx(k) == -1)  // enters from the inlet ghost at (y + cy_k, z + cz_k)
+                g[qopp(k)] = inlet_dev(a, a.in_prev, qopp(k), ty, tz);
+            if (at_out && qcx(k) == 1)  // enters from the outlet ghost, a copy of plane nx-1
+                g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)tz * ny + ty];
+        }
+    }
+    collide(g, a.om1, a.om2, a.galilean != 0);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const bool leaves = (at_in && qcx(k) == -1) || (at_out && qcx(k) == 1);
+        if (!leaves)
+            stp<S>(a.pop[k], addr[k], g[k]);
+    }
+    if (at_in) {
+        // populations entering from the inlet ghost for the next (even) step
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            if (qcx(i) == 1)
+                stp<S>(a.pop[i], own, inlet_dev(a, a.in_cur, i, ys[1 - qcy(i)], zs[1 - qcz(i)]));
+    }
+    if (at_out) {
+        // the outlet ghost (nx, y, z) copies this cell; its populations with
+        // cx = -1 land on (nx - 1, y + cy, z + cz)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            if (qcx(i) == -1)
+                stp<S>(a.pop[i], (uint32_t)x + (uint32_t)nx * ((uint32_t)ys[qcy(i) + 1] + (uint32_t)ny * zs[qcz(i) + 1]), g[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// collide and stream: block levels (refined, sparse)
 // ---------------------------------------------------------------------------
 
 template <int B, typename S, bool ODD>
-__device__ __forceinline__ void cell_update(const CollideArgs &a, int blk, int c, const int *nb,
-                                            bool face_block, int bx, int by, int bz)
+__device__ __forceinline__ void cell_update_block(const CollideArgs &a, int blk, int c, const int *nb)
 {
     constexpr int CELLS = B * B * B;
     constexpr int LB = B == 16 ? 4 : 3;
     const int x = c & (B - 1), y = (c >> LB) & (B - 1), z = c >> (2 * LB);
     const uint32_t own = (uint32_t)blk * CELLS + c;
     float g[NQ];
-
     if (!ODD) {
 #pragma unroll
         for (int k = 0; k < NQ; ++k)
-            g[k] = ldp<S>(a.pop[k], own);
+            g[k] = ldp_nt<S>(a.pop[k], own);
         collide(g, a.om1, a.om2, a.galilean != 0);
 #pragma unroll
         for (int k = 0; k < NQ; ++k)
-            stp<S>(a.pop[qopp(k)], own, g[k]);
-        if (face_block) {
-            const int gx = bx * B + x;
-            if (gx == a.nbx * B - 1) {
-                const int gy = by * B + y, gz = bz * B + z;
-                const size_t pl = (size_t)a.ny * a.nz;
-#pragma unroll
-                for (int i = 0; i < NQ; ++i)
-                    if (qcx(i) == -1)
-                        a.gbuf[i * pl + (size_t)gz * a.ny + gy] = g[i];
-            }
-        }
+            stp_nt<S>(a.pop[qopp(k)], own, g[k]);
         return;
     }
-
     const NbrLane<B> L(x, y, z);
     uint32_t addr[NQ];
-    int nbk[NQ];
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
         const int sx = qcx(k) + 1, sy = qcy(k) + 1, sz = qcz(k) + 1;
-        nbk[k] = nb[L.code(sx, sy, sz)];
-        const int b = nbk[k] < 0 ? blk : nbk[k];
-        addr[k] = (uint32_t)b * CELLS + L.local(sx, sy, sz);
+        addr[k] = (uint32_t)nb[L.code(sx, sy, sz)] * CELLS + L.local(sx, sy, sz);
     }
 #pragma unroll
     for (int k = 0; k < NQ; ++k)
         g[qopp(k)] = ldp<S>(a.pop[k], addr[k]);
-
-    int gx = 0, gy = 0, gz = 0;
-    if (face_block) {
-        gx = bx * B + x;
-        gy = by * B + y;
-        gz = bz * B + z;
-        const size_t pl = (size_t)a.ny * a.nz;
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-            if (qcx(k) == 0)
-                continue;
-            if (nbk[k] == NB_INLET) {
-                // population opp(k) enters from the inlet ghost at (y + cy_k, z + cz_k)
-                const int ty = wrapi(gy + qcy(k), a.ny), tz = wrapi(gz + qcz(k), a.nz);
-                float ux = a.u_in, uy = 0.0f, uz = 0.0f;
-                if (a.in_prev) {
-                    const float *p = a.in_prev + 3 * ((size_t)tz * a.ny + ty);
-                    ux += p[0];
-                    uy = p[1];
-                    uz = p[2];
-                }
-                g[qopp(k)] = feq_dev(qopp(k), ux, uy, uz);
-            } else if (nbk[k] == NB_OUTLET) {
-                const int ty = wrapi(gy + qcy(k), a.ny), tz = wrapi(gz + qcz(k), a.nz);
-                g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)tz * a.ny + ty];
-            }
-        }
-    }
-
     collide(g, a.om1, a.om2, a.galilean != 0);
-
-    if (!face_block) {
-#pragma unroll
-        for (int k = 0; k < NQ; ++k)
-            stp<S>(a.pop[k], addr[k], g[k]);
-        return;
-    }
 #pragma unroll
     for (int k = 0; k < NQ; ++k)
-        if (nbk[k] >= 0 || qcx(k) == 0)
-            stp<S>(a.pop[k], addr[k], g[k]);
-    const int lastx = a.nbx * B - 1;
-    if (gx == 0) {
-        // populations entering from the inlet ghost for the next (even) step
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            if (qcx(i) != 1)
-                continue;
-            const int ty = wrapi(gy - qcy(i), a.ny), tz = wrapi(gz - qcz(i), a.nz);
-            float ux = a.u_in, uy = 0.0f, uz = 0.0f;
-            if (a.in_cur) {
-                const float *p = a.in_cur + 3 * ((size_t)tz * a.ny + ty);
-                ux += p[0];
-                uy = p[1];
-                uz = p[2];
-            }
-            stp<S>(a.pop[i], own, feq_dev(i, ux, uy, uz));
-        }
-    }
-    if (gx == lastx) {
-        // the outlet ghost (nx, y, z) copies this cell; its populations with
-        // cx = -1 land on (nx - 1, y + cy, z + cz)
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            if (qcx(i) != -1)
-                continue;
-            const int sy = qcy(i) + 1, sz = qcz(i) + 1;
-            const int b = nb[L.code(1, sy, sz)];
-            stp<S>(a.pop[i], (uint32_t)b * CELLS + L.local(1, sy, sz), g[i]);
-        }
-    }
+        stp<S>(a.pop[k], addr[k], g[k]);
 }
 
 template <int B, typename S, bool ODD>
-__global__ void __launch_bounds__(256) k_collide(const CollideArgs a)
+__global__ void __launch_bounds__(256) k_collide_block(const CollideArgs a)
 {
     constexpr int CELLS = B * B * B;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int wg = blockIdx.x;
     const int item = wg / a.parts, part = wg - item * a.parts;
     if (item >= a.n_work)
         return;
@@ -201,41 +236,50 @@ __global__ void __launch_bounds__(256) k_collide(const CollideArgs a)
     if (threadIdx.x < 27)
         nb[threadIdx.x] = a.nbr[(size_t)blk * 27 + threadIdx.x];
     __syncthreads();
-    const int bx = a.bxyz[3 * blk], by = a.bxyz[3 * blk + 1], bz = a.bxyz[3 * blk + 2];
-    const bool face_block = a.faces && (bx == 0 || bx == a.nbx - 1);
     const int tile = CELLS / a.parts;
     const int c0 = part * tile;
     const uint32_t *mask = w.y == FULL_MASK ? nullptr : a.masks + (size_t)w.y * (CELLS / 32);
     for (int c = c0 + (int)threadIdx.x; c < c0 + tile; c += (int)blockDim.x) {
         if (mask && !((mask[c >> 5] >> (c & 31)) & 1u))
             continue;
-        cell_update<B, S, ODD>(a, blk, c, nb, face_block, bx, by, bz);
+        cell_update_block<B, S, ODD>(a, blk, c, nb);
     }
 }
 
-template <int B, typename S>
-static hipError_t launch_collide_t(int odd, const CollideArgs &a, int threads, hipStream_t s)
+template <typename S>
+static hipError_t launch_collide_s(int B, int odd, const CollideArgs &a, int threads, hipStream_t s)
 {
-    const int grid = a.n_work * a.parts;
-    if (grid == 0)
+    if (a.n_work == 0)
         return hipSuccess;
-    if (odd)
-        hipLaunchKernelGGL((k_collide<B, S, true>), dim3(grid), dim3(threads), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_collide<B, S, false>), dim3(grid), dim3(threads), 0, s, a);
+    if (a.dense) {
+        if (odd)
+            hipLaunchKernelGGL((k_collide_dense<S, true>), dim3(a.n_work), dim3(DENSE_TILE), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_collide_dense<S, false>), dim3(a.n_work), dim3(DENSE_TILE), 0, s, a);
+        return hipGetLastError();
+    }
+    const dim3 grid(a.n_work * a.parts), blk(threads);
+    if (B == 16) {
+        if (odd)
+            hipLaunchKernelGGL((k_collide_block<16, S, true>), grid, blk, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_collide_block<16, S, false>), grid, blk, 0, s, a);
+    } else {
+        if (odd)
+            hipLaunchKernelGGL((k_collide_block<8, S, true>), grid, blk, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_collide_block<8, S, false>), grid, blk, 0, s, a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_collide(int B, int storage, int odd, const CollideArgs &a, int threads, hipStream_t s)
 {
-    if (B == 16) {
-        if (storage == 0) return launch_collide_t<16, float>(odd, a, threads, s);
-        if (storage == 1) return launch_collide_t<16, __half>(odd, a, threads, s);
-        return launch_collide_t<16, __hip_bfloat16>(odd, a, threads, s);
-    }
-    if (storage == 0) return launch_collide_t<8, float>(odd, a, threads, s);
-    if (storage == 1) return launch_collide_t<8, __half>(odd, a, threads, s);
-    return launch_collide_t<8, __hip_bfloat16>(odd, a, threads, s);
+    if (storage == 0)
+        return launch_collide_s<float>(B, odd, a, threads, s);
+    if (storage == 1)
+        return launch_collide_s<__half>(B, odd, a, threads, s);
+    return launch_collide_s<__hip_bfloat16>(B, odd, a, threads, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -393,65 +437,68 @@ hipError_t launch_branch_reduce(const float *lforce, const int *seg, int nseg, d
 // state transfer: pre-collision populations of listed cells (FP64, full f)
 // ---------------------------------------------------------------------------
 
+// Pre-collision populations of the cell at element address elem for the next
+// step of the level (its read positions, with the inlet and outlet ghosts).
 template <int B, typename S, bool ODD>
-__device__ __forceinline__ void load_pre(const CollideArgs &a, int blk, int c, float (&g)[NQ])
+__device__ __forceinline__ void load_pre(const CollideArgs &a, uint32_t elem, float (&g)[NQ])
 {
-    constexpr int CELLS = B * B * B;
-    constexpr int LB = B == 16 ? 4 : 3;
-    const uint32_t own = (uint32_t)blk * CELLS + c;
     if (!ODD) {
 #pragma unroll
         for (int k = 0; k < NQ; ++k)
-            g[k] = ldp<S>(a.pop[k], own);
+            g[k] = ldp<S>(a.pop[k], elem);
         return;
     }
+    const size_t pl = (size_t)a.ny * a.nz;
+    if (a.dense) {
+        const int nx = a.nx, ny = a.ny, nz = a.nz;
+        const int x = (int)(elem % (uint32_t)nx);
+        const uint32_t yz = elem / (uint32_t)nx;
+        const int y = (int)(yz % (uint32_t)ny), z = (int)(yz / (uint32_t)ny);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            int xs = x + qcx(k);
+            const int ys = wrapi(y + qcy(k), ny), zs = wrapi(z + qcz(k), nz);
+            if (a.faces && xs < 0) {
+                g[qopp(k)] = inlet_dev(a, a.in_prev, qopp(k), ys, zs);
+            } else if (a.faces && xs >= nx) {
+                g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)zs * ny + ys];
+            } else {
+                xs = wrapi(xs, nx);
+                g[qopp(k)] = ldp<S>(a.pop[k], (uint32_t)xs + (uint32_t)nx * ((uint32_t)ys + (uint32_t)ny * zs));
+            }
+        }
+        return;
+    }
+    constexpr int CELLS = B * B * B;
+    constexpr int LB = B == 16 ? 4 : 3;
+    const int blk = (int)(elem / CELLS), c = (int)(elem % CELLS);
     const int x = c & (B - 1), y = (c >> LB) & (B - 1), z = c >> (2 * LB);
     const NbrLane<B> L(x, y, z);
     const int *nb = a.nbr + (size_t)blk * 27;
-    const int bx = a.bxyz[3 * blk], by = a.bxyz[3 * blk + 1], bz = a.bxyz[3 * blk + 2];
-    const int gy = by * B + y, gz = bz * B + z;
-    const size_t pl = (size_t)a.ny * a.nz;
-    (void)bx;
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
         const int sx = qcx(k) + 1, sy = qcy(k) + 1, sz = qcz(k) + 1;
         const int n = nb[L.code(sx, sy, sz)];
-        if (n == NB_INLET) {
-            const int ty = wrapi(gy + qcy(k), a.ny), tz = wrapi(gz + qcz(k), a.nz);
-            float ux = a.u_in, uy = 0.0f, uz = 0.0f;
-            if (a.in_prev) {
-                const float *p = a.in_prev + 3 * ((size_t)tz * a.ny + ty);
-                ux += p[0];
-                uy = p[1];
-                uz = p[2];
-            }
-            g[qopp(k)] = feq_dev(qopp(k), ux, uy, uz);
-        } else if (n == NB_OUTLET) {
-            const int ty = wrapi(gy + qcy(k), a.ny), tz = wrapi(gz + qcz(k), a.nz);
-            g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)tz * a.ny + ty];
-        } else {
-            g[qopp(k)] = ldp<S>(a.pop[k], (uint32_t)n * CELLS + L.local(sx, sy, sz));
-        }
+        g[qopp(k)] = ldp<S>(a.pop[k], (uint32_t)n * CELLS + L.local(sx, sy, sz));
     }
 }
 
 template <int B, typename S, bool ODD>
-__global__ void __launch_bounds__(256) k_gather(const CollideArgs a, const uint2 *cells, int n,
-                                                double *out, size_t stride)
+__global__ void __launch_bounds__(256) k_gather(const CollideArgs a, const uint32_t *cells, int n, double *out,
+                                                size_t stride)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n)
         return;
-    const uint2 cc = cells[t];
     float g[NQ];
-    load_pre<B, S, ODD>(a, (int)cc.x, (int)cc.y, g);
+    load_pre<B, S, ODD>(a, cells[t], g);
 #pragma unroll
     for (int i = 0; i < NQ; ++i)
         out[i * stride + t] = (double)g[i] + (double)qw(i);
 }
 
 template <int B, typename S>
-static hipError_t launch_gather_t(int odd, const CollideArgs &a, const uint2 *cells, int n, double *out,
+static hipError_t launch_gather_t(int odd, const CollideArgs &a, const uint32_t *cells, int n, double *out,
                                   size_t stride, hipStream_t s)
 {
     const dim3 grid((n + 255) / 256), blk(256);
@@ -462,7 +509,7 @@ static hipError_t launch_gather_t(int odd, const CollideArgs &a, const uint2 *ce
     return hipGetLastError();
 }
 
-hipError_t launch_gather(int B, int storage, int odd, const CollideArgs &a, const uint2 *cells, int n,
+hipError_t launch_gather(int B, int storage, int odd, const CollideArgs &a, const uint32_t *cells, int n,
                          double *out, size_t stride, hipStream_t s)
 {
     if (n == 0)
@@ -478,38 +525,29 @@ hipError_t launch_gather(int B, int storage, int odd, const CollideArgs &a, cons
 }
 
 // natural layout write (even parity): slot i of the cell holds population i
-template <int B, typename S>
-__global__ void __launch_bounds__(256) k_scatter(void *pop, size_t dir_elems, const uint2 *cells, int n,
+template <typename S>
+__global__ void __launch_bounds__(256) k_scatter(void *pop, size_t dir_elems, const uint32_t *cells, int n,
                                                  const double *in, size_t stride)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n)
         return;
-    const uint2 cc = cells[t];
-    const size_t e = (size_t)cc.x * (B * B * B) + cc.y;
+    const size_t e = cells[t];
     S *p = reinterpret_cast<S *>(pop);
 #pragma unroll
     for (int i = 0; i < NQ; ++i)
         p[i * dir_elems + e] = Store<S>::st((float)(in[i * stride + t] - (double)qw(i)));
 }
 
-hipError_t launch_scatter(int B, int storage, void *pop, size_t dir_elems, const uint2 *cells, int n,
-                          const double *in, size_t stride, hipStream_t s)
+hipError_t launch_scatter(int storage, void *pop, size_t dir_elems, const uint32_t *cells, int n, const double *in,
+                          size_t stride, hipStream_t s)
 {
     if (n == 0)
         return hipSuccess;
     const dim3 grid((n + 255) / 256), blk(256);
-#define LBM_SC(BB, T) hipLaunchKernelGGL((k_scatter<BB, T>), grid, blk, 0, s, pop, dir_elems, cells, n, in, stride)
-    if (B == 16) {
-        if (storage == 0) LBM_SC(16, float);
-        else if (storage == 1) LBM_SC(16, __half);
-        else LBM_SC(16, __hip_bfloat16);
-    } else {
-        if (storage == 0) LBM_SC(8, float);
-        else if (storage == 1) LBM_SC(8, __half);
-        else LBM_SC(8, __hip_bfloat16);
-    }
-#undef LBM_SC
+    if (storage == 0) hipLaunchKernelGGL(k_scatter<float>, grid, blk, 0, s, pop, dir_elems, cells, n, in, stride);
+    else if (storage == 1) hipLaunchKernelGGL(k_scatter<__half>, grid, blk, 0, s, pop, dir_elems, cells, n, in, stride);
+    else hipLaunchKernelGGL(k_scatter<__hip_bfloat16>, grid, blk, 0, s, pop, dir_elems, cells, n, in, stride);
     return hipGetLastError();
 }
 
@@ -517,19 +555,18 @@ hipError_t launch_scatter(int B, int storage, void *pop, size_t dir_elems, const
 // initial state: f = f_eq(1, (u_in, 0, 0)) on the listed cells, natural layout
 // ---------------------------------------------------------------------------
 
-template <int B, typename S>
+template <typename S>
 __global__ void __launch_bounds__(256) k_init(void *pop, size_t dir_elems, const uint2 *work, int n,
-                                              const uint32_t *masks, float u_in)
+                                              const uint32_t *masks, int unit, float u_in)
 {
-    constexpr int CELLS = B * B * B;
     const int item = blockIdx.x;
     if (item >= n)
         return;
     const uint2 w = work[item];
-    const uint32_t *mask = w.y == FULL_MASK ? nullptr : masks + (size_t)w.y * (CELLS / 32);
+    const uint32_t *mask = w.y == FULL_MASK ? nullptr : masks + (size_t)w.y * (unit / 32);
     S *p = reinterpret_cast<S *>(pop);
-    for (int c = threadIdx.x; c < CELLS; c += blockDim.x) {
-        const size_t e = (size_t)w.x * CELLS + c;
+    for (int c = threadIdx.x; c < unit; c += blockDim.x) {
+        const size_t e = (size_t)w.x * unit + c;
         const bool fluid = !mask || ((mask[c >> 5] >> (c & 31)) & 1u);
 #pragma unroll
         for (int i = 0; i < NQ; ++i)
@@ -537,22 +574,14 @@ __global__ void __launch_bounds__(256) k_init(void *pop, size_t dir_elems, const
     }
 }
 
-hipError_t launch_init(int B, int storage, void *pop, size_t dir_elems, const uint2 *work, int n,
+hipError_t launch_init(int unit, int storage, void *pop, size_t dir_elems, const uint2 *work, int n,
                        const uint32_t *masks, float u_in, hipStream_t s)
 {
     if (n == 0)
         return hipSuccess;
-#define LBM_IN(BB, T) hipLaunchKernelGGL((k_init<BB, T>), dim3(n), dim3(256), 0, s, pop, dir_elems, work, n, masks, u_in)
-    if (B == 16) {
-        if (storage == 0) LBM_IN(16, float);
-        else if (storage == 1) LBM_IN(16, __half);
-        else LBM_IN(16, __hip_bfloat16);
-    } else {
-        if (storage == 0) LBM_IN(8, float);
-        else if (storage == 1) LBM_IN(8, __half);
-        else LBM_IN(8, __hip_bfloat16);
-    }
-#undef LBM_IN
+    if (storage == 0) hipLaunchKernelGGL(k_init<float>, dim3(n), dim3(256), 0, s, pop, dir_elems, work, n, masks, unit, u_in);
+    else if (storage == 1) hipLaunchKernelGGL(k_init<__half>, dim3(n), dim3(256), 0, s, pop, dir_elems, work, n, masks, unit, u_in);
+    else hipLaunchKernelGGL(k_init<__hip_bfloat16>, dim3(n), dim3(256), 0, s, pop, dir_elems, work, n, masks, unit, u_in);
     return hipGetLastError();
 }
 
@@ -583,17 +612,17 @@ template <int B, typename S, bool ODD>
 __global__ void __launch_bounds__(256) k_mass(const CollideArgs a, const uint2 *leaf, int n_leaf,
                                               double vol, double *part)
 {
-    constexpr int CELLS = B * B * B;
+    const int unit = a.dense ? DENSE_TILE : B * B * B;
     __shared__ double sh[4];
     double m = 0.0, mn = 1e300, mx = -1e300, bad = 0.0;
     for (int item = blockIdx.x; item < n_leaf; item += gridDim.x) {
         const uint2 w = leaf[item];
-        const uint32_t *mask = w.y == FULL_MASK ? nullptr : a.masks + (size_t)w.y * (CELLS / 32);
-        for (int c = threadIdx.x; c < CELLS; c += blockDim.x) {
+        const uint32_t *mask = w.y == FULL_MASK ? nullptr : a.masks + (size_t)w.y * (unit / 32);
+        for (int c = threadIdx.x; c < unit; c += blockDim.x) {
             if (mask && !((mask[c >> 5] >> (c & 31)) & 1u))
                 continue;
             float g[NQ];
-            load_pre<B, S, ODD>(a, (int)w.x, c, g);
+            load_pre<B, S, ODD>(a, w.x * unit + c, g);
             double r = 1.0;
             for (int i = 0; i < NQ; ++i)
                 r += (double)g[i];

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 
 namespace lbm {
 
@@ -27,6 +28,8 @@ int64_t level_cell_address(const DevLevel &v, int B, int x, int y, int z)
         return -1;
     y = (y % v.ny + v.ny) % v.ny;
     z = (z % v.nz + v.nz) % v.nz;
+    if (v.dense)
+        return (int64_t)x + (int64_t)v.nx * ((int64_t)y + (int64_t)v.ny * z);
     const int bi = v.h_lattice_to_block[(size_t)(x / B) + (size_t)v.nbx * ((size_t)(y / B) + (size_t)v.nby * (z / B))];
     if (bi < 0)
         return -1;
@@ -85,6 +88,36 @@ static void index_level(DevLevel &v, int level)
     }
 }
 
+// Work list of a dense level: 256-cell tiles in element order holding at
+// least one selected cell; partly selected tiles carry a bit mask.
+static void dense_tiles(DevLevel &v, const std::function<bool(int64_t)> &sel, std::vector<uint2> &work,
+                        int64_t *count)
+{
+    const int64_t N = (int64_t)v.nx * v.ny * v.nz;
+    const int64_t ntile = N / DENSE_TILE;
+    work.clear();
+    *count = 0;
+    std::vector<uint32_t> m(DENSE_TILE / 32);
+    for (int64_t t = 0; t < ntile; ++t) {
+        std::fill(m.begin(), m.end(), 0u);
+        int n = 0;
+        for (int c = 0; c < DENSE_TILE; ++c)
+            if (sel(t * DENSE_TILE + c)) {
+                m[c >> 5] |= 1u << (c & 31);
+                ++n;
+            }
+        *count += n;
+        if (n == 0)
+            continue;
+        uint32_t mid = FULL_MASK;
+        if (n != DENSE_TILE) {
+            mid = (uint32_t)(v.h_masks.size() / (DENSE_TILE / 32));
+            v.h_masks.insert(v.h_masks.end(), m.begin(), m.end());
+        }
+        work.push_back(make_uint2((unsigned)t, mid));
+    }
+}
+
 lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *b, int n_b,
                         const lbm_refine_desc *refine, const std::vector<uint8_t> &solid,
                         std::vector<DevLevel> &lv, AmrPlan &plan, std::string *msg)
@@ -100,6 +133,7 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
     }
     DevLevel &v = lv[0];
     v.level = 0;
+    v.dense = true;
     v.nx = d.nx;
     v.ny = d.ny;
     v.nz = d.nz;
@@ -107,31 +141,8 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
     v.nby = d.ny / B;
     v.nbz = d.nz / B;
     v.h_map.assign((size_t)v.nbx * v.nby * v.nbz, 1);
-    index_level(v, 0);
-    const int cells = B * B * B;
     v.leaf_cells = (int64_t)d.nx * d.ny * d.nz;
-    v.updated_cells = 0;
-    for (int i = 0; i < v.nb; ++i) {
-        const int bx = v.h_bxyz[3 * i], by = v.h_bxyz[3 * i + 1], bz = v.h_bxyz[3 * i + 2];
-        std::vector<uint32_t> m(cells / 32, 0u);
-        int fluid = 0;
-        for (int c = 0; c < cells; ++c) {
-            const int x = bx * B + c % B, y = by * B + (c / B) % B, z = bz * B + c / (B * B);
-            if (!solid[(size_t)x + (size_t)d.nx * ((size_t)y + (size_t)d.ny * z)]) {
-                m[c >> 5] |= 1u << (c & 31);
-                ++fluid;
-            }
-        }
-        v.updated_cells += fluid;
-        if (fluid == 0)
-            continue;
-        uint32_t mid = FULL_MASK;
-        if (fluid != cells) {
-            mid = (uint32_t)(v.h_masks.size() / (cells / 32));
-            v.h_masks.insert(v.h_masks.end(), m.begin(), m.end());
-        }
-        v.h_work.push_back(make_uint2((unsigned)i, mid));
-    }
+    dense_tiles(v, [&](int64_t c) { return solid[(size_t)c] == 0; }, v.h_work, &v.updated_cells);
     v.h_leaf = v.h_work;
     return LBM_OK;
 }

@@ -90,6 +90,8 @@ static CollideArgs collide_args(lbm_grid *g, int l)
     a.work = v.work;
     a.masks = v.masks;
     a.n_work = v.n_work;
+    a.dense = v.dense ? 1 : 0;
+    a.nx = v.nx;
     const int cells = g->B * g->B * g->B;
     a.parts = std::max(1, cells / std::max(1, g->tile));
     a.om1 = (float)v.om1;
@@ -393,13 +395,15 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
     for (int l = 0; l < g->L; ++l) {
         DevLevel &v = g->lv[l];
         const size_t cells = (size_t)g->B * g->B * g->B;
-        v.dir_elems = (size_t)(v.nb + 1) * cells;
+        v.dir_elems = v.dense ? (size_t)v.nx * v.ny * v.nz : (size_t)(v.nb + 1) * cells;
         if (v.dir_elems > (size_t)UINT32_MAX / 2)
             return fail(g, LBM_E_INVALID, "level too large for 32-bit cell addressing");
         char *pop = nullptr;
         if ((st = dalloc(g, &pop, v.dir_elems * 27 * eb)) != LBM_OK)
             return st;
         v.pop = pop;
+        if (v.dense && v.h_nbr.empty())
+            v.h_nbr.assign(27, 0);
         if ((st = upload(g, &v.nbr, v.h_nbr)) != LBM_OK || (st = upload(g, &v.bxyz, v.h_bxyz)) != LBM_OK ||
             (st = upload(g, &v.work, v.h_work)) != LBM_OK || (st = upload(g, &v.leaf, v.h_leaf)) != LBM_OK ||
             (st = upload(g, &v.masks, v.h_masks)) != LBM_OK)
@@ -411,11 +415,12 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
                 return st;
             HIPX(g, hipMemsetAsync(v.gbuf, 0, sizeof(float) * 27 * (size_t)v.ny * v.nz, g->stream));
         }
+        const int unit = v.dense ? DENSE_TILE : g->B * g->B * g->B;
         HIPX(g, launch_fill_sink_and_all(d.storage, v.pop, v.dir_elems, g->stream));
-        HIPX(g, launch_init(g->B, d.storage, v.pop, v.dir_elems, v.leaf, v.n_leaf, v.masks, (float)d.u_in,
+        HIPX(g, launch_init(unit, d.storage, v.pop, v.dir_elems, v.leaf, v.n_leaf, v.masks, (float)d.u_in,
                             g->stream));
         // ghost / band cells start from the same uniform state
-        HIPX(g, launch_init(g->B, d.storage, v.pop, v.dir_elems, v.work, v.n_work, v.masks, (float)d.u_in,
+        HIPX(g, launch_init(unit, d.storage, v.pop, v.dir_elems, v.work, v.n_work, v.masks, (float)d.u_in,
                             g->stream));
     }
     if ((st = amr_upload(g->amr, g->lv, g->B, [&](void **p, size_t bytes) -> lbm_status {
@@ -632,8 +637,9 @@ lbm_status lbm_get_info(const lbm_grid *g, lbm_info *out)
     return LBM_OK;
 }
 
-// dense per-level cell lists (block, local) in box order, for state transfer
-static void level_dense_cells(const lbm_grid *g, int l, std::vector<uint2> &cells, std::vector<int64_t> &pos)
+// element addresses of the cells a level holds (leaf and refined blocks), in
+// box order, with their box positions, for state transfer
+static void level_dense_cells(const lbm_grid *g, int l, std::vector<uint32_t> &cells, std::vector<int64_t> &pos)
 {
     const DevLevel &v = g->lv[l];
     const int B = g->B;
@@ -643,25 +649,22 @@ static void level_dense_cells(const lbm_grid *g, int l, std::vector<uint2> &cell
         for (int y = 0; y < v.ny; ++y)
             for (int x = 0; x < v.nx; ++x) {
                 const int bx = x / B, by = y / B, bz = z / B;
-                const int bi = v.h_lattice_to_block[(size_t)bx + (size_t)v.nbx * ((size_t)by + (size_t)v.nby * bz)];
-                if (bi < 0)
-                    continue;
                 const int8_t kind = v.h_map[(size_t)bx + (size_t)v.nbx * ((size_t)by + (size_t)v.nby * bz)];
                 if (kind != 1 && kind != 2)
                     continue;
-                cells.push_back(make_uint2((unsigned)bi, (unsigned)((x % B) + B * ((y % B) + B * (z % B)))));
+                cells.push_back((uint32_t)level_cell_address(v, B, x, y, z));
                 pos.push_back((int64_t)x + (int64_t)v.nx * ((int64_t)y + (int64_t)v.ny * z));
             }
 }
 
-static lbm_status with_cells(lbm_grid *g, int l, std::vector<uint2> &cells, std::vector<int64_t> &pos,
-                             uint2 **d_cells)
+static lbm_status with_cells(lbm_grid *g, int l, std::vector<uint32_t> &cells, std::vector<int64_t> &pos,
+                             uint32_t **d_cells)
 {
     level_dense_cells(g, l, cells, pos);
     void *p = nullptr;
-    HIPX(g, hipMalloc(&p, sizeof(uint2) * std::max<size_t>(cells.size(), 1)));
-    *d_cells = (uint2 *)p;
-    HIPX(g, hipMemcpy(p, cells.data(), sizeof(uint2) * cells.size(), hipMemcpyHostToDevice));
+    HIPX(g, hipMalloc(&p, sizeof(uint32_t) * std::max<size_t>(cells.size(), 1)));
+    *d_cells = (uint32_t *)p;
+    HIPX(g, hipMemcpy(p, cells.data(), sizeof(uint32_t) * cells.size(), hipMemcpyHostToDevice));
     return LBM_OK;
 }
 
@@ -674,9 +677,9 @@ lbm_status lbm_get_populations(lbm_grid *g, int32_t level, double *f)
     if (level < 0 || level >= g->L)
         return fail(g, LBM_E_INVALID, "level out of range");
     HIPX(g, hipStreamSynchronize(g->stream));
-    std::vector<uint2> cells;
+    std::vector<uint32_t> cells;
     std::vector<int64_t> pos;
-    uint2 *dc = nullptr;
+    uint32_t *dc = nullptr;
     lbm_status st = with_cells(g, level, cells, pos, &dc);
     if (st != LBM_OK)
         return st;
@@ -712,9 +715,9 @@ lbm_status lbm_set_populations(lbm_grid *g, int32_t level, const double *f)
     if (v.steps & 1)
         return fail(g, LBM_E_STATE, "populations can be set only after an even number of level steps");
     HIPX(g, hipStreamSynchronize(g->stream));
-    std::vector<uint2> cells;
+    std::vector<uint32_t> cells;
     std::vector<int64_t> pos;
-    uint2 *dc = nullptr;
+    uint32_t *dc = nullptr;
     lbm_status st = with_cells(g, level, cells, pos, &dc);
     if (st != LBM_OK)
         return st;
@@ -727,7 +730,7 @@ lbm_status lbm_set_populations(lbm_grid *g, int32_t level, const double *f)
     double *din = nullptr;
     HIPX(g, hipMalloc((void **)&din, sizeof(double) * std::max<size_t>(h.size(), 1)));
     HIPX(g, hipMemcpy(din, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
-    HIPX(g, launch_scatter(g->B, g->d.storage, v.pop, v.dir_elems, dc, (int)n, din, n, g->stream));
+    HIPX(g, launch_scatter(g->d.storage, v.pop, v.dir_elems, dc, (int)n, din, n, g->stream));
     HIPX(g, hipStreamSynchronize(g->stream));
     (void)hipFree(din);
     (void)hipFree(dc);
