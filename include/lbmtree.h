@@ -138,7 +138,9 @@ typedef struct {
     double omega1[4];
     double height, area_x, nu_finest;
     size_t device_bytes;
-    int32_t tile_cells;       /* cells per work-group iteration of the collide kernel */
+    int32_t tile_cells;       /* cells per work-group of the block-level collide kernel */
+    int32_t threads;          /* work-group size of the block-level collide kernel */
+    int32_t occ_even, occ_odd;/* resident-wave caps per SIMD of the collide kernel (0 = none) */
 } lbm_info;
 
 /* ---- lifecycle ------------------------------------------------------------ */

@@ -64,7 +64,8 @@ class Info(C.Structure):
                 ("blocks", C.c_int64 * 4), ("active_cells", C.c_int64 * 4),
                 ("updated_cells", C.c_int64 * 4), ("links", C.c_int64), ("branches", C.c_int32),
                 ("omega1", C.c_double * 4), ("height", C.c_double), ("area_x", C.c_double),
-                ("nu_finest", C.c_double), ("device_bytes", C.c_size_t), ("tile_cells", C.c_int32)]
+                ("nu_finest", C.c_double), ("device_bytes", C.c_size_t), ("tile_cells", C.c_int32),
+                ("threads", C.c_int32), ("occ_even", C.c_int32), ("occ_odd", C.c_int32)]
 
 
 _lib = None
@@ -287,7 +288,8 @@ class Grid:
                 "blocks": list(i.blocks), "active_cells": list(i.active_cells),
                 "updated_cells": list(i.updated_cells), "links": i.links, "branches": i.branches,
                 "omega1": list(i.omega1), "height": i.height, "area_x": i.area_x,
-                "nu_finest": i.nu_finest, "device_bytes": i.device_bytes, "tile_cells": i.tile_cells}
+                "nu_finest": i.nu_finest, "device_bytes": i.device_bytes, "tile_cells": i.tile_cells,
+                "threads": i.threads, "occ_even": i.occ_even, "occ_odd": i.occ_odd}
 
     def get_populations(self, level=0):
         nx, ny, nz = self.level_shape(level)

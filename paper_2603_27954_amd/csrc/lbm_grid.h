@@ -43,6 +43,7 @@ struct lbm_grid {
     int64_t samples = 0, ring_count = 0;
     int64_t coarse_steps = 0, finest_steps = 0;
     int threads = 256, tile = 0;
+    int occ_even = 0, occ_odd = 0;  // waves per SIMD cap of the collide kernel (0 = none)
     size_t device_bytes = 0;
     std::vector<void *> allocs;
     hipGraphExec_t graph_exec = nullptr;

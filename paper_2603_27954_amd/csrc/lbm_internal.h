@@ -80,8 +80,13 @@ struct DevLevel {
 };
 
 // launchers (lbm_kernels.hip)
-hipError_t launch_collide(int B, int storage, int odd, const CollideArgs &a, int threads,
+// lds_bytes: dynamic LDS reserved per work-group to cap the number of
+// resident work-groups per CU (160 KiB of LDS per CU on gfx950)
+hipError_t launch_collide(int B, int storage, int odd, const CollideArgs &a, int threads, int lds_bytes,
                           hipStream_t s);
+constexpr int LDS_PER_CU = 160 * 1024;
+// dynamic LDS that limits a 256-thread work-group kernel to occ waves per SIMD
+inline int lds_for_occupancy(int occ) { return occ <= 0 ? 0 : LDS_PER_CU / occ - 1024; }
 hipError_t launch_links(int storage, int odd_done, const LinkArgs &a, hipStream_t s);
 hipError_t launch_init(int unit, int storage, void *pop, size_t dir_elems, const uint2 *work,
                        int n, const uint32_t *masks, float u_in, hipStream_t s);

@@ -23,24 +23,36 @@
 
 namespace lbm {
 
+// Accessors: a uniform (scalar) base pointer plus a 32-bit byte offset per
+// lane, the form that lowers to global loads/stores with an SGPR base and a
+// single VGPR offset (per-direction arrays stay below 4 GiB).
+template <typename S>
+__device__ __forceinline__ const S *at(const void *base, uint32_t elem)
+{
+    return reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + elem * (uint32_t)sizeof(S));
+}
+template <typename S>
+__device__ __forceinline__ S *at(void *base, uint32_t elem)
+{
+    return reinterpret_cast<S *>(reinterpret_cast<char *>(base) + elem * (uint32_t)sizeof(S));
+}
 template <typename S>
 __device__ __forceinline__ float ldp(const void *base, uint32_t elem)
 {
-    return Store<S>::ld(reinterpret_cast<const S *>(base)[elem]);
+    return Store<S>::ld(*at<S>(base, elem));
 }
 template <typename S>
 __device__ __forceinline__ void stp(void *base, uint32_t elem, float v)
 {
-    reinterpret_cast<S *>(base)[elem] = Store<S>::st(v);
+    *at<S>(base, elem) = Store<S>::st(v);
 }
-
 template <typename S>
 __device__ __forceinline__ float ldp_nt(const void *base, uint32_t elem)
 {
     if constexpr (sizeof(S) == 4) {
-        return __builtin_nontemporal_load(reinterpret_cast<const float *>(base) + elem);
+        return __builtin_nontemporal_load(reinterpret_cast<const float *>(at<S>(base, elem)));
     } else {
-        const unsigned short bits = __builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(base) + elem);
+        const unsigned short bits = __builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(at<S>(base, elem)));
         return Store<S>::ld(__builtin_bit_cast(S, bits));
     }
 }
@@ -48,10 +60,10 @@ template <typename S>
 __device__ __forceinline__ void stp_nt(void *base, uint32_t elem, float v)
 {
     if constexpr (sizeof(S) == 4) {
-        __builtin_nontemporal_store(v, reinterpret_cast<float *>(base) + elem);
+        __builtin_nontemporal_store(v, reinterpret_cast<float *>(at<S>(base, elem)));
     } else {
         const S h = Store<S>::st(v);
-        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, h), reinterpret_cast<unsigned short *>(base) + elem);
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, h), reinterpret_cast<unsigned short *>(at<S>(base, elem)));
     }
 }
 
@@ -98,7 +110,66 @@ struct NbrLane {
 // collide and stream: dense (x-pencil) levels
 // ---------------------------------------------------------------------------
 
-template <typename S, bool ODD>
+// Odd step when every wavefront lies in one x-row (nx a multiple of 64): y and
+// z are wave-uniform, so the eight neighbour-row offsets live in scalar
+// registers and each direction addresses (scalar base + row offset) + one of
+// three lane offsets (x-1, x, x+1; wrapped inside the row so every address
+// stays in the level).
+template <typename S>
+__device__ __forceinline__ void dense_odd_rowwave(const CollideArgs &a, uint32_t own, int x, bool at_in,
+                                                  bool at_out)
+{
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const uint32_t first = __builtin_amdgcn_readfirstlane(own - (uint32_t)x);  // row start, uniform
+    const uint32_t row = first / (uint32_t)nx;
+    const int y = (int)(row % (uint32_t)ny), z = (int)(row / (uint32_t)ny);
+    const int ys[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
+    const int zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
+    const uint32_t vx[3] = {x == 0 ? own + (uint32_t)nx - 1u : own - 1u, own,
+                            x == nx - 1 ? own + 1u - (uint32_t)nx : own + 1u};
+    float g[NQ];
+    const S *bk[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const int64_t roff = ((int64_t)ys[qcy(k) + 1] + (int64_t)ny * zs[qcz(k) + 1] - ((int64_t)y + (int64_t)ny * z)) * nx;
+        bk[k] = reinterpret_cast<const S *>(a.pop[k]) + roff;
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        g[qopp(k)] = ldp<S>(bk[k], vx[qcx(k) + 1]);
+    if (at_in || at_out) {
+        const size_t pl = (size_t)ny * nz;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int ty = ys[qcy(k) + 1], tz = zs[qcz(k) + 1];
+            if (at_in && qcx(k) == -1)
+                g[qopp(k)] = inlet_dev(a, a.in_prev, qopp(k), ty, tz);
+            if (at_out && qcx(k) == 1)
+                g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)tz * ny + ty];
+        }
+    }
+    collide(g, a.om1, a.om2, a.galilean != 0);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const bool leaves = (at_in && qcx(k) == -1) || (at_out && qcx(k) == 1);
+        if (!leaves)
+            stp<S>(const_cast<S *>(bk[k]), vx[qcx(k) + 1], g[k]);
+    }
+    if (at_in) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            if (qcx(i) == 1)
+                stp<S>(a.pop[i], own, inlet_dev(a, a.in_cur, i, ys[1 - qcy(i)], zs[1 - qcz(i)]));
+    }
+    if (at_out) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            if (qcx(i) == -1)
+                stp<S>(a.pop[i], (uint32_t)x + (uint32_t)nx * ((uint32_t)ys[qcy(i) + 1] + (uint32_t)ny * zs[qcz(i) + 1]), g[i]);
+    }
+}
+
+template <typename S, bool ODD, bool ROWWAVE>
 __global__ void __launch_bounds__(256) k_collide_dense(const CollideArgs a)
 {
     const int item = blockIdx.x;
@@ -137,6 +208,10 @@ __global__ void __launch_bounds__(256) k_collide_dense(const CollideArgs a)
         return;
     }
 
+    if (ROWWAVE) {
+        dense_odd_rowwave<S>(a, own, x, at_in, at_out);
+        return;
+    }
     // odd: population opp(k) comes from slot k of x + c_k, f*_k goes back there
     const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
     const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
@@ -247,39 +322,41 @@ __global__ void __launch_bounds__(256) k_collide_block(const CollideArgs a)
 }
 
 template <typename S>
-static hipError_t launch_collide_s(int B, int odd, const CollideArgs &a, int threads, hipStream_t s)
+static hipError_t launch_collide_s(int B, int odd, const CollideArgs &a, int threads, int lds, hipStream_t s)
 {
     if (a.n_work == 0)
         return hipSuccess;
     if (a.dense) {
-        if (odd)
-            hipLaunchKernelGGL((k_collide_dense<S, true>), dim3(a.n_work), dim3(DENSE_TILE), 0, s, a);
+        if (!odd)
+            hipLaunchKernelGGL((k_collide_dense<S, false, false>), dim3(a.n_work), dim3(DENSE_TILE), lds, s, a);
+        else if (a.nx % 64 == 0)
+            hipLaunchKernelGGL((k_collide_dense<S, true, true>), dim3(a.n_work), dim3(DENSE_TILE), lds, s, a);
         else
-            hipLaunchKernelGGL((k_collide_dense<S, false>), dim3(a.n_work), dim3(DENSE_TILE), 0, s, a);
+            hipLaunchKernelGGL((k_collide_dense<S, true, false>), dim3(a.n_work), dim3(DENSE_TILE), lds, s, a);
         return hipGetLastError();
     }
     const dim3 grid(a.n_work * a.parts), blk(threads);
     if (B == 16) {
         if (odd)
-            hipLaunchKernelGGL((k_collide_block<16, S, true>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((k_collide_block<16, S, true>), grid, blk, lds, s, a);
         else
-            hipLaunchKernelGGL((k_collide_block<16, S, false>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((k_collide_block<16, S, false>), grid, blk, lds, s, a);
     } else {
         if (odd)
-            hipLaunchKernelGGL((k_collide_block<8, S, true>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((k_collide_block<8, S, true>), grid, blk, lds, s, a);
         else
-            hipLaunchKernelGGL((k_collide_block<8, S, false>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((k_collide_block<8, S, false>), grid, blk, lds, s, a);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_collide(int B, int storage, int odd, const CollideArgs &a, int threads, hipStream_t s)
+hipError_t launch_collide(int B, int storage, int odd, const CollideArgs &a, int threads, int lds, hipStream_t s)
 {
     if (storage == 0)
-        return launch_collide_s<float>(B, odd, a, threads, s);
+        return launch_collide_s<float>(B, odd, a, threads, lds, s);
     if (storage == 1)
-        return launch_collide_s<__half>(B, odd, a, threads, s);
-    return launch_collide_s<__hip_bfloat16>(B, odd, a, threads, s);
+        return launch_collide_s<__half>(B, odd, a, threads, lds, s);
+    return launch_collide_s<__hip_bfloat16>(B, odd, a, threads, lds, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -146,7 +146,8 @@ static lbm_status level_collide(lbm_grid *g, int l)
     const int odd = (int)(v.steps & 1);
     CollideArgs a = collide_args(g, l);
     const int e0 = timing_mark(g);
-    HIPX(g, launch_collide(g->B, g->d.storage, odd, a, g->threads, g->stream));
+    HIPX(g, launch_collide(g->B, g->d.storage, odd, a, g->threads,
+                           lds_for_occupancy(odd ? g->occ_odd : g->occ_even), g->stream));
     const int e1 = timing_mark(g);
     if (e0 >= 0 && e1 >= 0)
         g->ev_pairs.push_back({e0, 0});
@@ -289,7 +290,11 @@ lbm_status lbm_create_grid(const lbm_grid_desc *d, lbm_grid **out)
         g->d.turb_modes = 200;
     g->B = B;
     g->L = d->levels;
-    g->tile = B * B * B;
+    g->tile = B * B;  // one z-slice of a block per work-group
+    // measured defaults (uniform 512x256x256): streaming even steps run best
+    // with 3 (FP32) or 4 (16-bit) waves per SIMD; odd steps are register-bound
+    g->occ_even = d->storage == LBM_FP32 ? 3 : 4;
+    g->occ_odd = 0;
     if (hipSetDevice(d->device) != hipSuccess) {
         delete g;
         return fail(nullptr, LBM_E_DEVICE, "hipSetDevice failed");
@@ -634,6 +639,9 @@ lbm_status lbm_get_info(const lbm_grid *g, lbm_info *out)
     out->nu_finest = g->nu_f;
     out->device_bytes = g->device_bytes;
     out->tile_cells = g->tile;
+    out->threads = g->threads;
+    out->occ_even = g->occ_even;
+    out->occ_odd = g->occ_odd;
     return LBM_OK;
 }
 

@@ -1,7 +1,9 @@
-// Tile autotuner of the collide kernel: times each (threads, cells per
-// work-group) candidate over whole coarse steps on the live grid, keeps the
-// fastest and restores the grid state afterwards.  Choices are cached in a
-// text file keyed by the grid shape.
+// Autotuner of the collide kernel: times candidate launch shapes over whole
+// coarse steps on the live grid -- work-group size and cells per work-group of
+// the block levels, and a cap on resident waves per SIMD (through reserved
+// LDS) for the even and the odd step -- keeps the fastest and restores the
+// grid state afterwards.  Choices are cached in a text file keyed by the grid
+// shape.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -23,7 +25,11 @@ std::string tune_key(const lbm_grid *g)
     return k;
 }
 
-bool cache_lookup(const char *path, const std::string &key, int *threads, int *tile)
+struct Choice {
+    int threads, tile, occ_even, occ_odd;
+};
+
+bool cache_lookup(const char *path, const std::string &key, Choice *c)
 {
     if (!path)
         return false;
@@ -31,12 +37,11 @@ bool cache_lookup(const char *path, const std::string &key, int *threads, int *t
     if (!f)
         return false;
     char k[200];
-    int t, c;
+    Choice v{};
     bool hit = false;
-    while (std::fscanf(f, "%199s %d %d", k, &t, &c) == 3)
+    while (std::fscanf(f, "%199s %d %d %d %d", k, &v.threads, &v.tile, &v.occ_even, &v.occ_odd) == 5)
         if (key == k) {
-            *threads = t;
-            *tile = c;
+            *c = v;
             hit = true;
         }
     std::fclose(f);
@@ -52,10 +57,12 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     if (g->state != 1)
         return grid_fail(g, LBM_E_STATE, "set_geometry first");
     const std::string key = tune_key(g);
-    int bt = 0, bc = 0;
-    if (cache_lookup(cache_path, key, &bt, &bc)) {
-        g->threads = bt;
-        g->tile = bc;
+    Choice cached{};
+    if (cache_lookup(cache_path, key, &cached)) {
+        g->threads = cached.threads;
+        g->tile = cached.tile;
+        g->occ_even = cached.occ_even;
+        g->occ_odd = cached.occ_odd;
         return LBM_OK;
     }
     const size_t eb = grid_storage_bytes(g->d.storage);
@@ -78,40 +85,61 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     for (int l = 0; l < g->L; ++l)
         steps[l] = g->lv[l].steps;
     const int64_t cs = g->coarse_steps, fs = g->finest_steps, sm = g->samples, rc = g->ring_count;
-    const int old_threads = g->threads, old_tile = g->tile;
+    const Choice old{g->threads, g->tile, g->occ_even, g->occ_odd};
 
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    const int cells = g->B * g->B * g->B;
-    float best = 1e30f;
-    int best_t = old_threads, best_c = old_tile;
     lbm_status st = LBM_OK;
-    for (int threads : {64, 128, 256}) {
-        for (int tile = cells; tile >= threads && tile >= cells / 16; tile /= 2) {
-            g->threads = threads;
-            g->tile = tile;
-            const int reps = 4;
-            st = grid_coarse_step(g);  // warm-up (and even/odd balance with reps even)
-            if (st == LBM_OK)
-                st = grid_coarse_step(g);
-            (void)hipEventRecord(e0, g->stream);
-            for (int r = 0; r < reps && st == LBM_OK; ++r)
-                st = grid_coarse_step(g);
-            (void)hipEventRecord(e1, g->stream);
-            (void)hipEventSynchronize(e1);
+    // times whole coarse steps (both parities) of candidate c
+    auto time_choice = [&](const Choice &c, float *ms) -> lbm_status {
+        g->threads = c.threads;
+        g->tile = c.tile;
+        g->occ_even = c.occ_even;
+        g->occ_odd = c.occ_odd;
+        lbm_status s2 = grid_coarse_step(g);
+        if (s2 == LBM_OK)
+            s2 = grid_coarse_step(g);
+        (void)hipEventRecord(e0, g->stream);
+        for (int r = 0; r < 4 && s2 == LBM_OK; ++r)
+            s2 = grid_coarse_step(g);
+        (void)hipEventRecord(e1, g->stream);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(ms, e0, e1);
+        return s2;
+    };
+    Choice best = old;
+    float best_ms = 1e30f;
+    // coordinate search: block tiles (refined levels), then the occupancy caps
+    // of the even and of the odd collide kernels
+    const int cells = g->B * g->B * g->B;
+    std::vector<Choice> cand;
+    if (g->L > 1)
+        for (int threads : {64, 128, 256})
+            for (int tile = cells; tile >= threads && tile >= cells / 16; tile /= 2)
+                cand.push_back({threads, tile, best.occ_even, best.occ_odd});
+    else
+        cand.push_back(best);
+    for (int pass = 0; pass < 3 && st == LBM_OK; ++pass) {
+        if (pass == 1) {
+            cand.clear();
+            for (int occ : {0, 2, 3, 4, 6})
+                cand.push_back({best.threads, best.tile, occ, best.occ_odd});
+        } else if (pass == 2) {
+            cand.clear();
+            for (int occ : {0, 2, 3, 4})
+                cand.push_back({best.threads, best.tile, best.occ_even, occ});
+        }
+        for (const Choice &c : cand) {
             float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
+            st = time_choice(c, &ms);
             if (st != LBM_OK)
                 break;
-            if (ms < best) {
-                best = ms;
-                best_t = threads;
-                best_c = tile;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
             }
         }
-        if (st != LBM_OK)
-            break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -129,17 +157,17 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     g->finest_steps = fs;
     g->samples = sm;
     g->ring_count = rc;
-    if (st != LBM_OK) {
-        g->threads = old_threads;
-        g->tile = old_tile;
+    const Choice use = st == LBM_OK ? best : old;
+    g->threads = use.threads;
+    g->tile = use.tile;
+    g->occ_even = use.occ_even;
+    g->occ_odd = use.occ_odd;
+    if (st != LBM_OK)
         return st;
-    }
-    g->threads = best_t;
-    g->tile = best_c;
     if (cache_path) {
         FILE *f = std::fopen(cache_path, "a");
         if (f) {
-            std::fprintf(f, "%s %d %d\n", key.c_str(), best_t, best_c);
+            std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), use.threads, use.tile, use.occ_even, use.occ_odd);
             std::fclose(f);
         }
     }
