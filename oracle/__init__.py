@@ -314,6 +314,106 @@ class UniformSim:
 
 
 # --------------------------------------------------------------------------
+# multi-level (octree block) simulation
+# --------------------------------------------------------------------------
+
+CLS_NONE, CLS_ACTIVE, CLS_BAND, CLS_DEEP, CLS_GHOST = 0, 1, 2, 3, 4
+
+
+class AmrSim:
+    """FP64 multi-level stepping (coarse-first recursion, moment-space transfer)."""
+
+    def __init__(self, L, B, nx, ny, nz, u_in, nu_f, branches, band, wake, solid=None, link=None,
+                 n_branch=0, galilean=True, periodic_x=False):
+        self.L, self.B = L, B
+        b = np.ascontiguousarray(branches, dtype=np.float64)
+        band = (C.c_int * 4)(*[int(v) for v in (list(band) + [0] * 4)[:4]])
+        wake = (C.c_int * 4)(*[int(v) for v in (list(wake) + [0] * 4)[:4]])
+        self.solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
+        if link is None:
+            link = {"cell": np.zeros(0, np.int64), "dir": np.zeros(0, np.int8), "q": np.zeros(0),
+                    "branch": np.zeros(0, np.int32)}
+        self.link = {k: np.ascontiguousarray(v) for k, v in link.items()}
+        Lb = lib()
+        self.h = Lb.or_amr_create(L, B, nx, ny, nz, u_in, nu_f, int(galilean), int(periodic_x), _ptr(b), len(b),
+                                  band, wake, _ptr(self.solid, _u8p), len(self.link["cell"]),
+                                  _ptr(self.link["cell"], _i64p), _ptr(self.link["dir"], _i8p),
+                                  _ptr(self.link["q"]), _ptr(self.link["branch"], _i32p), n_branch)
+        self.n_branch = n_branch
+        if Lb.or_amr_error(self.h) == 2:
+            Lb.or_amr_destroy(self.h)
+            self.h = None
+            raise ValueError("invalid refinement: a refined region comes too close to the box faces")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().or_amr_destroy(self.h)
+            self.h = None
+
+    def shape(self, l):
+        out = (C.c_int * 6)()
+        lib().or_amr_level_shape(self.h, l, out)
+        return tuple(out)
+
+    def block_map(self, l):
+        s = self.shape(l)
+        m = np.zeros(s[3] * s[4] * s[5], np.uint8)
+        lib().or_amr_block_map(self.h, l, _ptr(m, _u8p))
+        return m
+
+    def classes(self, l):
+        s = self.shape(l)
+        m = np.zeros(s[0] * s[1] * s[2], np.uint8)
+        lib().or_amr_classes(self.h, l, _ptr(m, _u8p))
+        return m
+
+    def get_f(self, l):
+        s = self.shape(l)
+        f = np.empty((Q, s[0] * s[1] * s[2]))
+        lib().or_amr_get_f(self.h, l, _ptr(f))
+        return f
+
+    def set_f(self, l, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        lib().or_amr_set_f(self.h, l, _ptr(f))
+
+    def step(self, n=1):
+        lib().or_amr_step(self.h, n)
+        return self
+
+    def force_log(self):
+        n = lib().or_amr_force_log(self.h, None, 0)
+        out = np.zeros(3 * max(n, 1))
+        lib().or_amr_force_log(self.h, _ptr(out), n)
+        return out[: 3 * n].reshape(-1, 3)
+
+    def branch_force(self):
+        out = np.zeros(3 * max(self.n_branch, 1))
+        lib().or_amr_branch_force(self.h, _ptr(out))
+        return out.reshape(-1, 3)[: self.n_branch]
+
+    def fields(self, l):
+        f = self.get_f(l)
+        rho = f.sum(0)
+        u = (f.T @ CVEC) / rho[:, None]
+        return rho, u
+
+
+def cell_transfer(f, omega1, dt):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.empty(10)
+    lib().or_cell_transfer(_ptr(f), omega1, dt, _ptr(out))
+    return out
+
+
+def cell_rebuild(v, omega1, dt):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.empty(Q)
+    lib().or_cell_rebuild(_ptr(v), omega1, dt, _ptr(out))
+    return out
+
+
+# --------------------------------------------------------------------------
 # tree presets (parameter sets; the generator above does the arithmetic)
 # --------------------------------------------------------------------------
 

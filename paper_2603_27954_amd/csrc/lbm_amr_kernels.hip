@@ -1,0 +1,200 @@
+// Coarse/fine coupling kernels of the octree levels (paper Sec. 2.2: the LBM
+// runs on leaf blocks of several resolutions).  Transfer runs in moment space:
+//  - k_amr_moments: (density, velocity, strain rate) of listed cells of the
+//    coarse level from their pre-collision populations;
+//  - k_amr_prolong: each fine ghost cell interpolates those quantities
+//    trilinearly (3/4 and 1/4 per axis) from its 2x2x2 coarse stencil, at the
+//    fine time level (the coarse values at T, or the mean of T and T+1), and
+//    its pre-collision populations are rebuilt with the fine rate and step
+//    (all cumulants above the second order zero);
+//  - k_amr_restrict: each coarse band cell averages its eight fine children
+//    (mean density, mass-weighted velocity, mean strain rate) and is rebuilt
+//    with the coarse rate and step.
+// Rebuilt populations are written to the read positions of the level's next
+// step (A-A parity aware).
+#include "lbm_access.h"
+
+namespace lbm {
+
+template <int B, typename S, bool ODD>
+__global__ void __launch_bounds__(256) k_amr_moments(const CollideArgs a, const uint32_t *cells, int n, float om1,
+                                                     float dt, float *out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n)
+        return;
+    float g[NQ];
+    load_pre<B, S, ODD>(a, cells[t], g);
+    const Transfer tr = to_transfer(forward_moments(g), om1, dt);
+    out[0 * (size_t)n + t] = tr.drho;
+    out[1 * (size_t)n + t] = tr.ux;
+    out[2 * (size_t)n + t] = tr.uy;
+    out[3 * (size_t)n + t] = tr.uz;
+#pragma unroll
+    for (int v = 0; v < 6; ++v)
+        out[(4 + v) * (size_t)n + t] = tr.d[v];
+}
+
+template <int B, typename S, bool ODD>
+__global__ void __launch_bounds__(256) k_amr_prolong(const CollideArgs fine, const uint32_t *ghosts,
+                                                     const int32_t *src, int n, int nsrc, const float *m0,
+                                                     const float *m1, float om1, float dt)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n)
+        return;
+    float v[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k)
+        v[k] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const float w = ((q & 1) ? 0.25f : 0.75f) * ((q & 2) ? 0.25f : 0.75f) * ((q & 4) ? 0.25f : 0.75f);
+        const int s = src[8 * (size_t)t + q];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            const float x0 = m0[k * (size_t)nsrc + s];
+            const float x = m1 ? 0.5f * (x0 + m1[k * (size_t)nsrc + s]) : x0;
+            v[k] = fmaf(w, x, v[k]);
+        }
+    }
+    Transfer tr;
+    tr.drho = v[0];
+    tr.ux = v[1];
+    tr.uy = v[2];
+    tr.uz = v[3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        tr.d[k] = v[4 + k];
+    float g[NQ];
+    back_transform(from_transfer(tr, om1, dt), g);
+    store_pre<B, S, ODD>(fine, ghosts[t], g);
+}
+
+template <int B, typename S, bool ODD_C, bool ODD_F>
+__global__ void __launch_bounds__(256) k_amr_restrict(const CollideArgs coarse, const CollideArgs fine,
+                                                      const uint32_t *band, const uint32_t *child, int n, float om_c,
+                                                      float dt_c, float om_f, float dt_f)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n)
+        return;
+    float drho = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f, d[6] = {0, 0, 0, 0, 0, 0};
+    int cnt = 0;
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t c = child[8 * (size_t)t + q];
+        if (c == FULL_MASK)
+            continue;
+        float g[NQ];
+        load_pre<B, S, ODD_F>(fine, c, g);
+        const Transfer tr = to_transfer(forward_moments(g), om_f, dt_f);
+        const float rho = 1.0f + tr.drho;
+        drho += tr.drho;
+        mx = fmaf(rho, tr.ux, mx);
+        my = fmaf(rho, tr.uy, my);
+        mz = fmaf(rho, tr.uz, mz);
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            d[k] += tr.d[k];
+        ++cnt;
+    }
+    if (cnt == 0)
+        return;
+    const float ic = 1.0f / (float)cnt;
+    Transfer tr;
+    tr.drho = drho * ic;
+    const float irho = 1.0f / (float)cnt / (1.0f + tr.drho);
+    tr.ux = mx * irho;
+    tr.uy = my * irho;
+    tr.uz = mz * irho;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        tr.d[k] = d[k] * ic;
+    float g[NQ];
+    back_transform(from_transfer(tr, om_c, dt_c), g);
+    store_pre<B, S, ODD_C>(coarse, band[t], g);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <int B, typename S>
+static void moments_t(int odd, const CollideArgs &a, const uint32_t *cells, int n, float om1, float dt, float *out,
+                      hipStream_t s)
+{
+    const dim3 grid((n + 255) / 256), blk(256);
+    if (odd)
+        hipLaunchKernelGGL((k_amr_moments<B, S, true>), grid, blk, 0, s, a, cells, n, om1, dt, out);
+    else
+        hipLaunchKernelGGL((k_amr_moments<B, S, false>), grid, blk, 0, s, a, cells, n, om1, dt, out);
+}
+
+template <int B, typename S>
+static void prolong_t(int odd, const CollideArgs &f, const uint32_t *ghosts, const int32_t *src, int n, int nsrc,
+                      const float *m0, const float *m1, float om1, float dt, hipStream_t s)
+{
+    const dim3 grid((n + 255) / 256), blk(256);
+    if (odd)
+        hipLaunchKernelGGL((k_amr_prolong<B, S, true>), grid, blk, 0, s, f, ghosts, src, n, nsrc, m0, m1, om1, dt);
+    else
+        hipLaunchKernelGGL((k_amr_prolong<B, S, false>), grid, blk, 0, s, f, ghosts, src, n, nsrc, m0, m1, om1, dt);
+}
+
+template <int B, typename S>
+static void restrict_t(int odd_c, int odd_f, const CollideArgs &c, const CollideArgs &f, const uint32_t *band,
+                       const uint32_t *child, int n, float om_c, float dt_c, float om_f, float dt_f, hipStream_t s)
+{
+    const dim3 grid((n + 255) / 256), blk(256);
+#define LBM_RS(OC, OF) \
+    hipLaunchKernelGGL((k_amr_restrict<B, S, OC, OF>), grid, blk, 0, s, c, f, band, child, n, om_c, dt_c, om_f, dt_f)
+    if (odd_c && odd_f) LBM_RS(true, true);
+    else if (odd_c) LBM_RS(true, false);
+    else if (odd_f) LBM_RS(false, true);
+    else LBM_RS(false, false);
+#undef LBM_RS
+}
+
+#define LBM_DISPATCH(FN, ...)                                            \
+    do {                                                                 \
+        if (B == 16) {                                                   \
+            if (storage == 0) FN<16, float>(__VA_ARGS__);                \
+            else if (storage == 1) FN<16, __half>(__VA_ARGS__);          \
+            else FN<16, __hip_bfloat16>(__VA_ARGS__);                    \
+        } else {                                                         \
+            if (storage == 0) FN<8, float>(__VA_ARGS__);                 \
+            else if (storage == 1) FN<8, __half>(__VA_ARGS__);           \
+            else FN<8, __hip_bfloat16>(__VA_ARGS__);                     \
+        }                                                                \
+    } while (0)
+
+hipError_t launch_amr_moments(int B, int storage, int odd, const CollideArgs &a, const uint32_t *cells, int n,
+                              float om1, float dt, float *out, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    LBM_DISPATCH(moments_t, odd, a, cells, n, om1, dt, out, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_amr_prolong(int B, int storage, int odd, const CollideArgs &fine, const uint32_t *ghosts,
+                              const int32_t *src, int n, int nsrc, const float *m0, const float *m1, float om1,
+                              float dt, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    LBM_DISPATCH(prolong_t, odd, fine, ghosts, src, n, nsrc, m0, m1, om1, dt, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_amr_restrict(int B, int storage, int odd_c, int odd_f, const CollideArgs &coarse,
+                               const CollideArgs &fine, const uint32_t *band, const uint32_t *child, int n,
+                               float om_c, float dt_c, float om_f, float dt_f, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    LBM_DISPATCH(restrict_t, odd_c, odd_f, coarse, fine, band, child, n, om_c, dt_c, om_f, dt_f, s);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

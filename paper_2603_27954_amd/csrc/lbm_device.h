@@ -222,6 +222,56 @@ __host__ __device__ __forceinline__ void back_transform(const Moments &m, float 
         g[i] = D[i];
 }
 
+// Coarse/fine transfer quantities of a cell: density deviation, velocity and
+// the strain-rate tensor in finest time units (xx, yy, zz, xy, xz, yz).  From
+// the pre-collision non-equilibrium moments N the lattice strain rate is
+// S = -3/(2 rho) (omega1 dev N + omega2 tr(N)/3 I) per level step dt (finest
+// steps); rebuilding at another level inverts this with that level's rate
+// and step.  The bulk rate omega2 is 1 on every level.
+struct Transfer {
+    float drho, ux, uy, uz;
+    float d[6];
+};
+
+__host__ __device__ __forceinline__ Transfer to_transfer(const Moments &m, float om1, float dt)
+{
+    Transfer t;
+    const float rho = 1.0f + m.drho;
+    const float c = -1.5f / (rho * dt);
+    const float t3 = (m.nxx + m.nyy + m.nzz) * (1.0f / 3.0f);
+    t.drho = m.drho;
+    t.ux = m.ux;
+    t.uy = m.uy;
+    t.uz = m.uz;
+    t.d[0] = c * (om1 * (m.nxx - t3) + t3);
+    t.d[1] = c * (om1 * (m.nyy - t3) + t3);
+    t.d[2] = c * (om1 * (m.nzz - t3) + t3);
+    t.d[3] = c * om1 * m.nxy;
+    t.d[4] = c * om1 * m.nxz;
+    t.d[5] = c * om1 * m.nyz;
+    return t;
+}
+
+__host__ __device__ __forceinline__ Moments from_transfer(const Transfer &t, float om1, float dt)
+{
+    Moments m;
+    const float rho = 1.0f + t.drho;
+    const float c = -2.0f * rho * dt / 3.0f;
+    const float s3 = (t.d[0] + t.d[1] + t.d[2]) * (1.0f / 3.0f);
+    const float iw = 1.0f / om1;
+    m.drho = t.drho;
+    m.ux = t.ux;
+    m.uy = t.uy;
+    m.uz = t.uz;
+    m.nxx = c * ((t.d[0] - s3) * iw + s3);
+    m.nyy = c * ((t.d[1] - s3) * iw + s3);
+    m.nzz = c * ((t.d[2] - s3) * iw + s3);
+    m.nxy = c * t.d[3] * iw;
+    m.nxz = c * t.d[4] * iw;
+    m.nyz = c * t.d[5] * iw;
+    return m;
+}
+
 __host__ __device__ __forceinline__ void collide(float (&g)[NQ], float om1, float om2, bool galilean)
 {
     Moments m = forward_moments(g);

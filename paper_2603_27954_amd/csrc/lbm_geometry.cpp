@@ -329,9 +329,19 @@ int64_t build_links(const lbm_branch *b, int n, int nx, int ny, int nz, const st
     }
     links.clear();
     const auto at = [&](int x, int y, int z) { return (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z); };
-    for (int z = 0; z < nz; ++z)
-        for (int y = 0; y < ny; ++y)
-            for (int x = 0; x < nx; ++x) {
+    // only cells within two cells of the tree's bounding box can have links
+    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+    {
+        const int ext[3] = {nx, ny, nz};
+        for (const Shape &sh : shapes)
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], std::max(0, (int)std::floor(sh.lo[a]) - 2));
+                hi[a] = std::max(hi[a], std::min(ext[a] - 1, (int)std::ceil(sh.hi[a]) + 2));
+            }
+    }
+    for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+            for (int x = lo[0]; x <= hi[0]; ++x) {
                 const size_t c = at(x, y, z);
                 if (solid[c])
                     continue;

@@ -102,4 +102,16 @@ hipError_t launch_scatter(int storage, void *pop, size_t dir_elems, const uint32
 hipError_t launch_mass(int B, int storage, int odd, const CollideArgs &a, const uint2 *leaf,
                        int n_leaf, double cell_volume, double *out4, hipStream_t s);
 
+// coarse/fine transfer (lbm_amr_kernels.hip); moments are written SoA
+// (10 arrays of n floats), stencils hold 8 source indices per ghost and
+// 8 child addresses per band cell (FULL_MASK = skip)
+hipError_t launch_amr_moments(int B, int storage, int odd, const CollideArgs &a, const uint32_t *cells, int n,
+                              float om1, float dt, float *out, hipStream_t s);
+hipError_t launch_amr_prolong(int B, int storage, int odd, const CollideArgs &fine, const uint32_t *ghosts,
+                              const int32_t *src, int n, int nsrc, const float *m0, const float *m1, float om1,
+                              float dt, hipStream_t s);
+hipError_t launch_amr_restrict(int B, int storage, int odd_c, int odd_f, const CollideArgs &coarse,
+                               const CollideArgs &fine, const uint32_t *band, const uint32_t *child, int n,
+                               float om_c, float dt_c, float om_f, float dt_f, hipStream_t s);
+
 }  // namespace lbm

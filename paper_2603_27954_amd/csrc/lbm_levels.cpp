@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <unordered_map>
+#include <array>
 
 namespace lbm {
 
@@ -118,32 +120,369 @@ static void dense_tiles(DevLevel &v, const std::function<bool(int64_t)> &sel, st
     }
 }
 
+namespace {
+
+// Refinement rule, computed on block lattices.  A level-(l-1) block that
+// exists is refined when a branch axis segment meets its box grown by
+// R + band[l] on every side, or when its box overlaps the wake box.
+struct RefineRule {
+    const lbm_branch *b;
+    int n;
+    const lbm_refine_desc *r;
+    double tree_lo[3], tree_hi[3];
+
+    RefineRule(const lbm_branch *b_, int n_, const lbm_refine_desc *r_) : b(b_), n(n_), r(r_)
+    {
+        for (int k = 0; k < 3; ++k) {
+            tree_lo[k] = 1e300;
+            tree_hi[k] = -1e300;
+        }
+        for (int i = 0; i < n; ++i) {
+            const double rad = 0.5 * b[i].diameter;
+            for (int k = 0; k < 3; ++k) {
+                tree_lo[k] = std::min(tree_lo[k], std::min(b[i].p0[k], b[i].p1[k]) - rad);
+                tree_hi[k] = std::max(tree_hi[k], std::max(b[i].p0[k], b[i].p1[k]) + rad);
+            }
+        }
+    }
+
+    // closed-box slab test of the axis segment of branch br against [lo, hi]
+    static bool axis_hits(const lbm_branch &br, const double lo[3], const double hi[3])
+    {
+        double enter = 0.0, leave = 1.0;
+        for (int k = 0; k < 3; ++k) {
+            const double d = br.p1[k] - br.p0[k];
+            if (d == 0.0) {
+                if (br.p0[k] < lo[k] || br.p0[k] > hi[k])
+                    return false;
+                continue;
+            }
+            const double a = (lo[k] - br.p0[k]) / d, c = (hi[k] - br.p0[k]) / d;
+            enter = std::max(enter, std::min(a, c));
+            leave = std::min(leave, std::max(a, c));
+            if (enter > leave)
+                return false;
+        }
+        return true;
+    }
+
+    // block (bx, by, bz) of edge bf finest cells, refined towards level l?
+    bool wants(int l, int bx, int by, int bz, double bf) const
+    {
+        for (int i = 0; i < n; ++i) {
+            const double e = 0.5 * b[i].diameter + r->band[l];
+            const double lo[3] = {bx * bf - e, by * bf - e, bz * bf - e};
+            const double hi[3] = {(bx + 1) * bf + e, (by + 1) * bf + e, (bz + 1) * bf + e};
+            if (axis_hits(b[i], lo, hi))
+                return true;
+        }
+        if (r->wake[l] > 0) {
+            const double lo[3] = {bx * bf, by * bf, bz * bf};
+            const double w0[3] = {tree_lo[0], tree_lo[1] - r->band[l], tree_lo[2] - r->band[l]};
+            const double w1[3] = {tree_hi[0] + r->wake[l], tree_hi[1] + r->band[l], tree_hi[2] + r->band[l]};
+            for (int k = 0; k < 3; ++k)
+                if (!(lo[k] < w1[k] && lo[k] + bf > w0[k]))
+                    return false;
+            return true;
+        }
+        return false;
+    }
+};
+
+struct Lattice {
+    int nx, ny, nz;
+    std::vector<int8_t> m;  // 0 none, 1 leaf, 2 refined, 3 ghost storage
+    int8_t &at(int x, int y, int z) { return m[(size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z)]; }
+    int8_t get(int x, int y, int z) const
+    {
+        if (x < 0 || y < 0 || z < 0 || x >= nx || y >= ny || z >= nz)
+            return -1;
+        return m[(size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z)];
+    }
+};
+
+// refine (bx,by,bz) at level l, bringing it (and its ancestors) into existence
+bool make_refined(std::vector<Lattice> &lat, int l, int bx, int by, int bz)
+{
+    if (lat[l].get(bx, by, bz) < 0)
+        return false;
+    if (lat[l].at(bx, by, bz) == 0) {
+        if (l == 0 || !make_refined(lat, l - 1, bx >> 1, by >> 1, bz >> 1))
+            return false;
+    }
+    lat[l].at(bx, by, bz) = 2;
+    for (int s = 0; s < 8; ++s) {
+        int8_t &c = lat[l + 1].at(2 * bx + (s & 1), 2 * by + ((s >> 1) & 1), 2 * bz + (s >> 2));
+        if (c == 0)
+            c = 1;
+    }
+    return true;
+}
+
+}  // namespace
+
 lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *b, int n_b,
                         const lbm_refine_desc *refine, const std::vector<uint8_t> &solid,
                         std::vector<DevLevel> &lv, AmrPlan &plan, std::string *msg)
 {
-    (void)b;
-    (void)n_b;
-    (void)refine;
     plan.pairs.clear();
     lv.assign(L, DevLevel{});
-    if (L != 1) {
-        *msg = "multi-level grids are built by build_levels_amr";
-        return LBM_E_INVALID;
+    for (int l = 0; l < L; ++l) {
+        DevLevel &v = lv[l];
+        const int h = 1 << (L - 1 - l);
+        v.level = l;
+        v.dense = l == 0;
+        v.nx = d.nx / h;
+        v.ny = d.ny / h;
+        v.nz = d.nz / h;
+        v.nbx = v.nx / B;
+        v.nby = v.ny / B;
+        v.nbz = v.nz / B;
     }
-    DevLevel &v = lv[0];
-    v.level = 0;
-    v.dense = true;
-    v.nx = d.nx;
-    v.ny = d.ny;
-    v.nz = d.nz;
-    v.nbx = d.nx / B;
-    v.nby = d.ny / B;
-    v.nbz = d.nz / B;
-    v.h_map.assign((size_t)v.nbx * v.nby * v.nbz, 1);
-    v.leaf_cells = (int64_t)d.nx * d.ny * d.nz;
-    dense_tiles(v, [&](int64_t c) { return solid[(size_t)c] == 0; }, v.h_work, &v.updated_cells);
-    v.h_leaf = v.h_work;
+    if (L == 1) {
+        DevLevel &v = lv[0];
+        v.h_map.assign((size_t)v.nbx * v.nby * v.nbz, 1);
+        v.leaf_cells = (int64_t)d.nx * d.ny * d.nz;
+        dense_tiles(v, [&](int64_t c) { return solid[(size_t)c] == 0; }, v.h_work, &v.updated_cells);
+        v.h_leaf = v.h_work;
+        return LBM_OK;
+    }
+
+    // ---- block maps ----------------------------------------------------------
+    std::vector<Lattice> lat(L);
+    for (int l = 0; l < L; ++l) {
+        lat[l].nx = lv[l].nbx;
+        lat[l].ny = lv[l].nby;
+        lat[l].nz = lv[l].nbz;
+        lat[l].m.assign((size_t)lv[l].nbx * lv[l].nby * lv[l].nbz, (int8_t)(l == 0 ? 1 : 0));
+    }
+    RefineRule rule(b, n_b, refine);
+    for (int l = 1; l < L; ++l) {
+        Lattice &P = lat[l - 1];
+        const double bf = (double)B * (double)(1 << (L - l));
+        for (int z = 0; z < P.nz; ++z)
+            for (int y = 0; y < P.ny; ++y)
+                for (int x = 0; x < P.nx; ++x)
+                    if (P.at(x, y, z) != 0 && rule.wants(l, x, y, z, bf)) {
+                        P.at(x, y, z) = 2;
+                        for (int s = 0; s < 8; ++s)
+                            lat[l].at(2 * x + (s & 1), 2 * y + ((s >> 1) & 1), 2 * z + (s >> 2)) = 1;
+                    }
+    }
+    for (bool changed = true; changed;) {
+        changed = false;
+        for (int l = L - 2; l >= 1; --l) {
+            Lattice &T = lat[l];
+            for (int z = 0; z < T.nz; ++z)
+                for (int y = 0; y < T.ny; ++y)
+                    for (int x = 0; x < T.nx; ++x) {
+                        if (T.at(x, y, z) != 2)
+                            continue;
+                        for (int k = 0; k < 27; ++k) {
+                            const int X = x + k % 3 - 1, Y = y + (k / 3) % 3 - 1, Z = z + k / 9 - 1;
+                            const int8_t v = T.get(X, Y, Z);
+                            if (v < 0) {
+                                *msg = "a refined region reaches the box faces";
+                                return LBM_E_INVALID;
+                            }
+                            if (v == 0) {
+                                if (!make_refined(lat, l - 1, X >> 1, Y >> 1, Z >> 1)) {
+                                    *msg = "refinement closure failed";
+                                    return LBM_E_INVALID;
+                                }
+                                changed = true;
+                            }
+                        }
+                    }
+        }
+    }
+    for (int l = 0; l < L - 1; ++l) {
+        const Lattice &T = lat[l];
+        for (int z = 0; z < T.nz; ++z)
+            for (int y = 0; y < T.ny; ++y)
+                for (int x = 0; x < T.nx; ++x)
+                    if (T.m[(size_t)x + (size_t)T.nx * ((size_t)y + (size_t)T.ny * z)] == 2 &&
+                        (x < 1 || y < 1 || z < 1 || x > T.nx - 2 || y > T.ny - 2 || z > T.nz - 2)) {
+                        *msg = "a refined region comes within one block of the box faces";
+                        return LBM_E_INVALID;
+                    }
+    }
+    for (int l = 1; l < L; ++l) {
+        Lattice &T = lat[l];
+        std::vector<int8_t> add(T.m.size(), 0);
+        for (int z = 0; z < T.nz; ++z)
+            for (int y = 0; y < T.ny; ++y)
+                for (int x = 0; x < T.nx; ++x) {
+                    if (T.at(x, y, z) != 0)
+                        continue;
+                    for (int k = 0; k < 27; ++k) {
+                        const int8_t v = T.get(x + k % 3 - 1, y + (k / 3) % 3 - 1, z + k / 9 - 1);
+                        if (v == 1 || v == 2) {
+                            add[(size_t)x + (size_t)T.nx * ((size_t)y + (size_t)T.ny * z)] = 1;
+                            break;
+                        }
+                    }
+                }
+        for (size_t i = 0; i < T.m.size(); ++i)
+            if (add[i])
+                T.m[i] = 3;
+    }
+    for (int l = 0; l < L; ++l) {
+        lv[l].h_map = lat[l].m;
+        if (l > 0)
+            index_level(lv[l], l);
+    }
+
+    // ---- cell classes ------------------------------------------------------
+    // 1 active, 2 band (refined, <= 2 cells from active), 3 deep, 4 ghost, 0 none
+    auto block_of = [&](int l, int x, int y, int z) -> int8_t {
+        if (x < 0 || y < 0 || z < 0 || x >= lv[l].nx || y >= lv[l].ny || z >= lv[l].nz)
+            return -1;
+        return lat[l].get(x / B, y / B, z / B);
+    };
+    auto cell_class = [&](int l, int x, int y, int z) -> int {
+        const int8_t m = block_of(l, x, y, z);
+        if (m == 1)
+            return 1;
+        if (m == 2) {
+            for (int dz = -2; dz <= 2; ++dz)
+                for (int dy = -2; dy <= 2; ++dy)
+                    for (int dx = -2; dx <= 2; ++dx)
+                        if (block_of(l, x + dx, y + dy, z + dz) == 1)
+                            return 2;
+            return 3;
+        }
+        if (m == 3) {
+            for (int k = 0; k < 27; ++k) {
+                const int8_t v = block_of(l, x + k % 3 - 1, y + (k / 3) % 3 - 1, z + k / 9 - 1);
+                if (v == 1 || v == 2)
+                    return 4;
+            }
+        }
+        return 0;
+    };
+    const int cells = B * B * B;
+    auto finest_solid = [&](int x, int y, int z) {
+        return solid[(size_t)x + (size_t)d.nx * ((size_t)y + (size_t)d.ny * z)] != 0;
+    };
+    for (int l = 0; l < L; ++l) {
+        DevLevel &v = lv[l];
+        const bool finest = l == L - 1;
+        v.leaf_cells = 0;
+        v.updated_cells = 0;
+        if (v.dense) {
+            // level 0: collide active and band cells; leaf = active
+            std::vector<uint8_t> cls((size_t)v.nx * v.ny * v.nz);
+            for (int z = 0; z < v.nz; ++z)
+                for (int y = 0; y < v.ny; ++y)
+                    for (int x = 0; x < v.nx; ++x)
+                        cls[(size_t)x + (size_t)v.nx * ((size_t)y + (size_t)v.ny * z)] = (uint8_t)cell_class(l, x, y, z);
+            int64_t dummy = 0;
+            dense_tiles(v, [&](int64_t c) { return cls[c] == 1 || cls[c] == 2; }, v.h_work, &dummy);
+            dense_tiles(v, [&](int64_t c) { return cls[c] == 1; }, v.h_leaf, &v.updated_cells);
+            v.leaf_cells = v.updated_cells;
+            continue;
+        }
+        for (int bi = 0; bi < v.nb; ++bi) {
+            const int bx = v.h_bxyz[3 * bi], by = v.h_bxyz[3 * bi + 1], bz = v.h_bxyz[3 * bi + 2];
+            std::vector<uint32_t> mw(cells / 32, 0u), ml(cells / 32, 0u);
+            int nw = 0, nl = 0;
+            for (int c = 0; c < cells; ++c) {
+                const int x = bx * B + c % B, y = by * B + (c / B) % B, z = bz * B + c / (B * B);
+                const int k = cell_class(l, x, y, z);
+                const bool sol = finest && (k == 1 || k == 2) && finest_solid(x, y, z);
+                if (k == 1 || k == 2)
+                    v.leaf_cells += k == 1;
+                if ((k == 1 || k == 2 || k == 4) && !sol) {
+                    mw[c >> 5] |= 1u << (c & 31);
+                    ++nw;
+                }
+                if (k == 1 && !sol) {
+                    ml[c >> 5] |= 1u << (c & 31);
+                    ++nl;
+                }
+            }
+            v.updated_cells += nl;
+            auto push = [&](std::vector<uint2> &list, const std::vector<uint32_t> &m, int cnt) {
+                if (cnt == 0)
+                    return;
+                uint32_t mid = FULL_MASK;
+                if (cnt != cells) {
+                    mid = (uint32_t)(v.h_masks.size() / (cells / 32));
+                    v.h_masks.insert(v.h_masks.end(), m.begin(), m.end());
+                }
+                list.push_back(make_uint2((unsigned)bi, mid));
+            };
+            push(v.h_work, mw, nw);
+            push(v.h_leaf, ml, nl);
+        }
+    }
+
+    // ---- coarse/fine plans -------------------------------------------------
+    plan.pairs.resize(L - 1);
+    for (int l = 0; l < L - 1; ++l) {
+        AmrPair &pr = plan.pairs[l];
+        const DevLevel &C = lv[l], &F = lv[l + 1];
+        std::unordered_map<uint32_t, int32_t> src_index;
+        bool bad = false;
+        auto addr_of = [&](const DevLevel &v, int x, int y, int z) -> uint32_t {
+            const int64_t e = level_cell_address(v, B, x, y, z);
+            if (e < 0)
+                bad = true;
+            return (uint32_t)std::max<int64_t>(e, 0);
+        };
+        auto src_of = [&](int x, int y, int z) -> int32_t {
+            const uint32_t e = addr_of(C, x, y, z);
+            auto it = src_index.find(e);
+            if (it != src_index.end())
+                return it->second;
+            const int32_t id = (int32_t)pr.h_src.size();
+            src_index.emplace(e, id);
+            pr.h_src.push_back(e);
+            return id;
+        };
+        // fine ghost cells, in block order
+        for (int bi = 0; bi < F.nb; ++bi) {
+            if (lat[l + 1].get(F.h_bxyz[3 * bi], F.h_bxyz[3 * bi + 1], F.h_bxyz[3 * bi + 2]) != 3)
+                continue;
+            const int bx = F.h_bxyz[3 * bi], by = F.h_bxyz[3 * bi + 1], bz = F.h_bxyz[3 * bi + 2];
+            for (int c = 0; c < cells; ++c) {
+                const int x = bx * B + c % B, y = by * B + (c / B) % B, z = bz * B + c / (B * B);
+                if (cell_class(l + 1, x, y, z) != 4)
+                    continue;
+                pr.h_ghost.push_back((uint32_t)bi * cells + c);
+                const int P[3] = {x >> 1, y >> 1, z >> 1};
+                const int s[3] = {(x & 1) ? 1 : -1, (y & 1) ? 1 : -1, (z & 1) ? 1 : -1};
+                for (int q = 0; q < 8; ++q)
+                    pr.h_ghost_src.push_back(src_of(P[0] + (q & 1) * s[0], P[1] + ((q >> 1) & 1) * s[1],
+                                                    P[2] + ((q >> 2) & 1) * s[2]));
+            }
+        }
+        // coarse band cells and their children
+        auto band_cell = [&](int x, int y, int z) {
+            pr.h_band.push_back(addr_of(C, x, y, z));
+            for (int q = 0; q < 8; ++q) {
+                const int fx = 2 * x + (q & 1), fy = 2 * y + ((q >> 1) & 1), fz = 2 * z + ((q >> 2) & 1);
+                const bool sol = (l + 1 == L - 1) && finest_solid(fx, fy, fz);
+                pr.h_band_child.push_back(sol ? FULL_MASK : addr_of(F, fx, fy, fz));
+            }
+        };
+        for (int bz = 0; bz < C.nbz; ++bz)
+            for (int by = 0; by < C.nby; ++by)
+                for (int bx = 0; bx < C.nbx; ++bx) {
+                    if (lat[l].get(bx, by, bz) != 2)
+                        continue;
+                    for (int c = 0; c < cells; ++c) {
+                        const int x = bx * B + c % B, y = by * B + (c / B) % B, z = bz * B + c / (B * B);
+                        if (cell_class(l, x, y, z) == 2)
+                            band_cell(x, y, z);
+                    }
+                }
+        if (bad) {
+            *msg = "internal: a coarse/fine stencil cell is not held by its level";
+            return LBM_E_INVALID;
+        }
+    }
     return LBM_OK;
 }
 
@@ -152,34 +491,29 @@ lbm_status amr_upload(AmrPlan &plan, std::vector<DevLevel> &lv, int B, const All
 {
     (void)lv;
     (void)B;
-    (void)alloc;
-    (void)s;
-    (void)msg;
-    if (!plan.pairs.empty()) {
-        *msg = "coarse/fine coupling not available";
-        return LBM_E_INVALID;
+    for (AmrPair &pr : plan.pairs) {
+        auto put = [&](void **dst, const void *src, size_t bytes) -> lbm_status {
+            lbm_status st = alloc(dst, std::max<size_t>(bytes, 16));
+            if (st != LBM_OK)
+                return st;
+            if (bytes && hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess) {
+                *msg = "hipMemcpyAsync of the coupling plan failed";
+                return LBM_E_DEVICE;
+            }
+            return LBM_OK;
+        };
+        lbm_status st;
+        if ((st = put((void **)&pr.d_src, pr.h_src.data(), pr.h_src.size() * 4)) != LBM_OK ||
+            (st = put((void **)&pr.d_ghost, pr.h_ghost.data(), pr.h_ghost.size() * 4)) != LBM_OK ||
+            (st = put((void **)&pr.d_ghost_src, pr.h_ghost_src.data(), pr.h_ghost_src.size() * 4)) != LBM_OK ||
+            (st = put((void **)&pr.d_band, pr.h_band.data(), pr.h_band.size() * 4)) != LBM_OK ||
+            (st = put((void **)&pr.d_band_child, pr.h_band_child.data(), pr.h_band_child.size() * 4)) != LBM_OK)
+            return st;
+        for (int k = 0; k < 2; ++k)
+            if ((st = alloc((void **)&pr.d_mom[k], std::max<size_t>(pr.h_src.size() * 10 * sizeof(float), 16))) != LBM_OK)
+                return st;
     }
     return LBM_OK;
-}
-
-lbm_status amr_moments(AmrPlan &, std::vector<DevLevel> &, int, int, int, int, hipStream_t, std::string *msg)
-{
-    *msg = "coarse/fine coupling not available";
-    return LBM_E_INVALID;
-}
-
-lbm_status amr_prolong(AmrPlan &, std::vector<DevLevel> &, int, int, int, int, uint32_t, hipStream_t,
-                       std::string *msg)
-{
-    *msg = "coarse/fine coupling not available";
-    return LBM_E_INVALID;
-}
-
-lbm_status amr_restrict(AmrPlan &, std::vector<DevLevel> &, int, int, int, uint32_t, hipStream_t,
-                        std::string *msg)
-{
-    *msg = "coarse/fine coupling not available";
-    return LBM_E_INVALID;
 }
 
 }  // namespace lbm

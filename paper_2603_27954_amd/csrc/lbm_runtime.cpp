@@ -177,44 +177,73 @@ static lbm_status finest_links(lbm_grid *g, int odd_done)
     return LBM_OK;
 }
 
-static lbm_status advance_level(lbm_grid *g, int l);
+// level step in finest time units
+static float level_dt(const lbm_grid *g, int l) { return (float)(1 << (g->L - 1 - l)); }
 
+// transfer quantities of the coarse source cells of pair l into slot 0 (time
+// T, before the coarse step) or 1 (T + 1, after it)
+static lbm_status amr_moments(lbm_grid *g, int l, int slot)
+{
+    AmrPair &pr = g->amr.pairs[l];
+    DevLevel &v = g->lv[l];
+    CollideArgs a = collide_args(g, l);
+    HIPX(g, launch_amr_moments(g->B, g->d.storage, (int)(v.steps & 1), a, pr.d_src, (int)pr.h_src.size(),
+                               (float)v.om1, level_dt(g, l), pr.d_mom[slot], g->stream));
+    return LBM_OK;
+}
+
+// pre-collision state of the ghost cells of level l + 1 for its next sub-step
+static lbm_status amr_prolong(lbm_grid *g, int l, int sub)
+{
+    AmrPair &pr = g->amr.pairs[l];
+    DevLevel &f = g->lv[l + 1];
+    CollideArgs a = collide_args(g, l + 1);
+    HIPX(g, launch_amr_prolong(g->B, g->d.storage, (int)(f.steps & 1), a, pr.d_ghost, pr.d_ghost_src,
+                               (int)pr.h_ghost.size(), (int)pr.h_src.size(), pr.d_mom[0],
+                               sub ? pr.d_mom[1] : nullptr, (float)f.om1, level_dt(g, l + 1), g->stream));
+    return LBM_OK;
+}
+
+// pre-collision state of the band cells of level l from level l + 1
+static lbm_status amr_restrict(lbm_grid *g, int l)
+{
+    AmrPair &pr = g->amr.pairs[l];
+    DevLevel &c = g->lv[l], &f = g->lv[l + 1];
+    CollideArgs ac = collide_args(g, l), af = collide_args(g, l + 1);
+    HIPX(g, launch_amr_restrict(g->B, g->d.storage, (int)(c.steps & 1), (int)(f.steps & 1), ac, af, pr.d_band,
+                                pr.d_band_child, (int)pr.h_band.size(), (float)c.om1, level_dt(g, l),
+                                (float)f.om1, level_dt(g, l + 1), g->stream));
+    return LBM_OK;
+}
+
+// One step of level l and, recursively, the two sub-steps of each finer
+// level (coarse first): moments at T, coarse step, fine ghosts from T, fine
+// sub-step, moments at T+1, fine ghosts from the mean, fine sub-step,
+// restriction into the coarse band.
 static lbm_status advance_level(lbm_grid *g, int l)
 {
     lbm_status st;
     const bool finest = l == g->L - 1;
-    if (!finest) {
-        st = amr_moments(g->amr, g->lv, l, 0, g->d.storage, g->B, g->stream, &g->err);
-        if (st != LBM_OK)
-            return st;
-    }
+    if (!finest && (st = amr_moments(g, l, 0)) != LBM_OK)
+        return st;
     DevLevel &v = g->lv[l];
     const int odd = (int)(v.steps & 1);
-    st = level_collide(g, l);
-    if (st != LBM_OK)
+    if ((st = level_collide(g, l)) != LBM_OK)
         return st;
     v.steps++;
     if (finest) {
         g->finest_steps++;
-        st = finest_links(g, odd);
-        if (st != LBM_OK)
-            return st;
-        return LBM_OK;
+        return finest_links(g, odd);
     }
     for (int sub = 0; sub < 2; ++sub) {
-        if (sub == 1) {
-            st = amr_moments(g->amr, g->lv, l, 1, g->d.storage, g->B, g->stream, &g->err);
-            if (st != LBM_OK)
-                return st;
-        }
-        st = amr_prolong(g->amr, g->lv, l, sub, g->d.storage, g->B, g->d.flags, g->stream, &g->err);
-        if (st != LBM_OK)
+        if (sub == 1 && (st = amr_moments(g, l, 1)) != LBM_OK)
             return st;
-        st = advance_level(g, l + 1);
-        if (st != LBM_OK)
+        if ((st = amr_prolong(g, l, sub)) != LBM_OK)
+            return st;
+        if ((st = advance_level(g, l + 1)) != LBM_OK)
             return st;
     }
-    return amr_restrict(g->amr, g->lv, l, g->d.storage, g->B, g->d.flags, g->stream, &g->err);
+    return amr_restrict(g, l);
 }
 
 static lbm_status coarse_step(lbm_grid *g)

@@ -1,0 +1,136 @@
+"""Pins of the oracle's multi-level (octree block) stepping (paper Sec. 2.2):
+uniform flow stays uniform through every interface, a two-level grid without
+refinement is the uniform coarse run bit for bit, the moment-space transfer
+round-trips, the block maps obey nesting and the 26-neighbour closure, and a
+partially refined run agrees with the uniform-finest run within the
+discretisation tolerance."""
+import numpy as np
+import pytest
+
+import oracle as O
+
+NX, NY, NZ, B = 96, 96, 96, 8
+U = 0.05
+
+
+def _tree(com=(40.0, 48.0, 48.0)):
+    return O.build_tree(O.cfg1_tree_params(), 0.0, list(com))
+
+
+def _nu(b, re=100.0):
+    return U * O.tree_height(b) / re
+
+
+def test_transfer_round_trip():
+    """Rebuilding a cell from its (rho, u, D) at the same level and step gives
+    back rho, u and the second-order central moments; at another level the
+    strain rate D is preserved."""
+    rng = np.random.default_rng(4)
+    for _ in range(10):
+        u = rng.uniform(-0.05, 0.05, 3)
+        f = O.equilibrium(rng.uniform(0.98, 1.02), u) * (1 + 0.01 * rng.standard_normal(27))
+        w, dt = rng.uniform(1.2, 1.9), 2.0
+        t = O.cell_transfer(f, w, dt)
+        g = O.cell_rebuild(t, w, dt)
+        assert np.isclose(g.sum(), f.sum(), rtol=1e-14)
+        assert np.allclose(g @ O.CVEC, f @ O.CVEC, atol=1e-15)
+        k_f = O.chimera_forward(f, t[1:4])
+        k_g = O.chimera_forward(g, t[1:4])
+        for idx in (2, 6, 18, 4, 10, 12):
+            assert np.isclose(k_f[idx], k_g[idx], atol=1e-15)
+        g2 = O.cell_rebuild(t, 1.5, 1.0)
+        assert np.allclose(O.cell_transfer(g2, 1.5, 1.0), t, atol=1e-15)
+    feq = O.equilibrium(1.01, [0.03, -0.01, 0.02])
+    assert np.allclose(O.cell_transfer(feq, 1.7, 4.0)[4:], 0.0, atol=1e-16)
+
+
+def test_block_maps_nesting_and_closure():
+    b = _tree((96.0, 64.0, 64.0))
+    sim = O.AmrSim(3, B, 256, 128, 128, U, _nu(b), b, band=[0, 2, 0], wake=[0, 0, 0])
+    for l in range(3):
+        s = sim.shape(l)
+        m = sim.block_map(l).reshape(s[5], s[4], s[3])
+        if l == 0:
+            assert np.all((m == 1) | (m == 2))
+        if l < 2:
+            # every refined block has its 26 neighbours at its level
+            for z, y, x in zip(*np.nonzero(m == 2)):
+                nb = m[z - 1:z + 2, y - 1:y + 2, x - 1:x + 2]
+                assert nb.shape == (3, 3, 3) and np.all((nb == 1) | (nb == 2))
+        if l >= 1:
+            p = sim.block_map(l - 1).reshape(sim.shape(l - 1)[5], sim.shape(l - 1)[4], sim.shape(l - 1)[3])
+            exists = (m == 1) | (m == 2)
+            assert np.array_equal(exists, np.repeat(np.repeat(np.repeat(p == 2, 2, 0), 2, 1), 2, 2))
+    # the finest level holds the whole tree
+    s = sim.shape(2)
+    m2 = sim.block_map(2).reshape(s[5], s[4], s[3])
+    solid = O.voxelize(b, 256, 128, 128).reshape(128, 128, 256)
+    zz, yy, xx = np.nonzero(solid)
+    assert np.all((m2[zz // B, yy // B, xx // B] == 1))
+
+
+def test_refinement_next_to_the_box_faces_is_rejected():
+    b = _tree((40.0, 20.0, 32.0))
+    with pytest.raises(ValueError):
+        O.AmrSim(3, B, 256, 128, 128, U, _nu(b), b, band=[0, 24, 6], wake=[0, 40, 0])
+
+
+def test_uniform_flow_stays_uniform():
+    """Equilibrium at u_in everywhere is a fixed point of every level, of the
+    prolongation and of the restriction (no body)."""
+    b = _tree()
+    sim = O.AmrSim(2, B, NX, NY, NZ, U, _nu(b), b, band=[0, 8], wake=[0, 0])
+    sim.step(6)
+    feq = O.equilibrium(1.0, [U, 0, 0])
+    for l in range(2):
+        f = sim.get_f(l)
+        cls = sim.classes(l)
+        act = (cls == O.CLS_ACTIVE)
+        assert act.sum() > 0
+        assert np.abs(f[:, act] - feq[:, None]).max() < 1e-14
+
+
+def test_unrefined_two_level_grid_is_the_uniform_coarse_run():
+    nu_f = 0.02
+    sim = O.AmrSim(2, B, NX, NY, NZ, U, nu_f, np.zeros((0, 10)), band=[0, 0], wake=[0, 0])
+    assert np.all(sim.block_map(1) == 0)
+    rng = np.random.default_rng(9)
+    N0 = (NX // 2) * (NY // 2) * (NZ // 2)
+    f0 = np.empty((27, N0))
+    for c in range(N0):
+        f0[:, c] = O.equilibrium(1 + 0.01 * rng.standard_normal(), U + 0.01 * rng.standard_normal(3))
+    sim.set_f(0, f0)
+    ref = O.UniformSim(NX // 2, NY // 2, NZ // 2, O.omega_from_nu(nu_f / 2), u_in=U)
+    ref.f[:] = f0
+    sim.step(5)
+    ref.step(5)
+    assert np.array_equal(sim.get_f(0), ref.f)
+
+
+@pytest.mark.slow
+def test_refined_run_agrees_with_uniform_finest():
+    """P9: order-1 tree refined to the finest level within 8 cells of its
+    surface: C_D and the velocity near the tree within discretisation
+    tolerance of the uniform-finest run (80 finest steps of the impulsive start)."""
+    b = _tree()
+    nu = _nu(b)
+    solid = O.voxelize(b, NX, NY, NZ)
+    lk = O.links(b, solid, NX, NY, NZ)
+    amr = O.AmrSim(2, B, NX, NY, NZ, U, nu, b, band=[0, 8], wake=[0, 0], solid=solid, link=lk, n_branch=len(b))
+    uni = O.UniformSim(NX, NY, NZ, O.omega_from_nu(nu), u_in=U, solid=solid, link=lk, n_branch=len(b))
+    steps = 80
+    amr.step(steps // 2)
+    rec = []
+    uni.step(steps, record=rec)
+    ax = O.area_x(solid, NX, NY, NZ)
+    cd = lambda F: F[0] / (0.5 * U * U * ax)
+    fa = amr.force_log()
+    assert len(fa) == steps
+    cd_amr = np.mean([cd(F) for F in fa[-10:]])
+    cd_uni = np.mean([cd(F) for F in rec[-10:]])
+    assert abs(cd_amr - cd_uni) / abs(cd_uni) < 0.02
+    _, ua = amr.fields(1)
+    _, uu = uni.fields()
+    cls = amr.classes(1)
+    near = (cls == O.CLS_ACTIVE) & (solid == 0)
+    assert np.abs(ua[near] - uu[near]).max() / U < 0.02
