@@ -46,18 +46,27 @@ struct lbm_grid {
     int occ_even = 0, occ_odd = 0;  // waves per SIMD cap of the collide kernel (0 = none)
     size_t device_bytes = 0;
     std::vector<void *> allocs;
-    hipGraphExec_t graph_exec = nullptr;
+    unsigned long long *d_ring_pos = nullptr;  // device copy of ring_count (slot of the next sample)
+    // Captured coarse steps.  A coarse step's launches depend on the host
+    // state only through the A-A parity of every level and the phase of the
+    // force sampling, so one graph per such key is replayed, and the host
+    // counters advance by the deltas recorded at capture.
+    struct StepGraph {
+        uint64_t key;
+        hipGraphExec_t exec;
+        int64_t level_steps[8];
+        int64_t coarse, finest, samples, ring;
+    };
+    std::vector<StepGraph> graphs;
     // per-kernel timing (event pairs, kind 0 collide, 1 links)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, int>> ev_pairs;  // (start index, kind)
-    int graph_period = 0;
-    int64_t graph_phase = -1;
 
     ~lbm_grid()
     {
-        if (graph_exec)
-            (void)hipGraphExecDestroy(graph_exec);
+        for (StepGraph &sg : graphs)
+            (void)hipGraphExecDestroy(sg.exec);
         for (hipEvent_t e : ev_pool)
             (void)hipEventDestroy(e);
         for (void *p : allocs)
@@ -75,4 +84,8 @@ lbm_status grid_coarse_step(lbm_grid *g);
 size_t grid_storage_bytes(int storage);
 // records an event on the grid stream when timing is on; returns its index or -1
 int grid_timing_mark(lbm_grid *g);
+// drops every captured coarse step (launch shapes or state changed)
+void grid_graphs_clear(lbm_grid *g);
+// writes the host sample count to the device ring position (synchronous)
+lbm_status grid_sync_ring_pos(lbm_grid *g);
 }  // namespace lbm

@@ -14,6 +14,8 @@ namespace lbm {
 constexpr int NB_INLET = -2;   // x < 0: equilibrium ghost plane
 constexpr int NB_OUTLET = -3;  // x >= nx: zero-gradient ghost plane
 constexpr uint32_t FULL_MASK = 0xFFFFFFFFu;
+// force samples kept on the device (ring of total-force triples)
+constexpr int RING = 65536;
 
 // Arguments of the collide-and-stream kernel of one level.
 constexpr int DENSE_TILE = 256;  // cells per work item of a dense level
@@ -92,8 +94,8 @@ hipError_t launch_init(int unit, int storage, void *pop, size_t dir_elems, const
                        int n, const uint32_t *masks, float u_in, hipStream_t s);
 hipError_t launch_fill_sink_and_all(int storage, void *pop, size_t dir_elems, hipStream_t s);
 hipError_t launch_branch_reduce(const float *lforce, const int *seg, int nseg, double *sample,
-                                double *acc_branch, double *acc_total, double *ring, int ring_slot,
-                                unsigned *counter, hipStream_t s);
+                                double *acc_branch, double *acc_total, double *ring,
+                                unsigned long long *ring_pos, unsigned *counter, hipStream_t s);
 // element addresses (dense: x + nx (y + ny z); blocks: block * B^3 + local)
 hipError_t launch_gather(int B, int storage, int odd, const CollideArgs &a, const uint32_t *cells,
                          int n, double *out_f, size_t out_stride, hipStream_t s);

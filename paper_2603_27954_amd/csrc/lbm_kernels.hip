@@ -373,11 +373,12 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
 
 // One work-group per branch segment (links sorted by branch); the last
 // work-group to finish adds the per-branch sums in branch order into the total,
-// appends it to the sample ring and resets the counter.
+// appends it to the sample ring at the device-held position ring_pos (so a
+// captured graph replays with the right slot) and resets the counter.
 __global__ void __launch_bounds__(256) k_branch_reduce(const float *lforce, const int *seg, int nseg,
                                                        double *sample, double *acc_branch,
-                                                       double *acc_total, double *ring, int ring_slot,
-                                                       unsigned *counter)
+                                                       double *acc_total, double *ring,
+                                                       unsigned long long *ring_pos, unsigned *counter)
 {
     __shared__ double sh[4];
     __shared__ bool last;
@@ -407,22 +408,24 @@ __global__ void __launch_bounds__(256) k_branch_reduce(const float *lforce, cons
         for (int i = 0; i < nseg; ++i)
             for (int a = 0; a < 3; ++a)
                 t[a] += __builtin_nontemporal_load(&sample[3 * i + a]);
+        const unsigned long long slot = *ring_pos % RING;
         for (int a = 0; a < 3; ++a) {
             acc_total[a] += t[a];
-            ring[3 * ring_slot + a] = t[a];
+            ring[3 * slot + a] = t[a];
         }
+        *ring_pos += 1ull;
         *counter = 0u;
     }
 }
 
 hipError_t launch_branch_reduce(const float *lforce, const int *seg, int nseg, double *sample,
-                                double *acc_branch, double *acc_total, double *ring, int ring_slot,
-                                unsigned *counter, hipStream_t s)
+                                double *acc_branch, double *acc_total, double *ring,
+                                unsigned long long *ring_pos, unsigned *counter, hipStream_t s)
 {
     if (nseg == 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_branch_reduce, dim3(nseg), dim3(256), 0, s, lforce, seg, nseg, sample,
-                       acc_branch, acc_total, ring, ring_slot, counter);
+                       acc_branch, acc_total, ring, ring_pos, counter);
     return hipGetLastError();
 }
 

@@ -24,7 +24,6 @@ using namespace lbm;
 
 static thread_local std::string g_thread_error;
 
-static const int RING = 65536;
 
 static lbm_status fail(lbm_grid *g, lbm_status st, const std::string &msg)
 {
@@ -168,8 +167,8 @@ static lbm_status finest_links(lbm_grid *g, int odd_done)
     if (sample) {
         if (g->n_links > 0) {
             HIPX(g, launch_branch_reduce(g->d_lforce, g->d_seg, g->nseg, g->d_sample, g->d_acc_branch,
-                                         g->d_acc_total, g->d_ring, (int)(g->ring_count % RING),
-                                         g->d_counter, g->stream));
+                                         g->d_acc_total, g->d_ring, g->d_ring_pos, g->d_counter,
+                                         g->stream));
         }
         g->samples++;
         g->ring_count++;
@@ -254,12 +253,111 @@ static lbm_status coarse_step(lbm_grid *g)
     return st;
 }
 
+// ---------------------------------------------------------------------------
+// graph-captured coarse steps
+// ---------------------------------------------------------------------------
+
+static const size_t MAX_GRAPHS = 64;
+
+// parity of every level, and which finest sub-steps of the coarse step
+// sample the force (the finest step count after sub-step j is f0 + j + 1)
+static uint64_t step_key(const lbm_grid *g)
+{
+    uint64_t k = 0;
+    for (int l = 0; l < g->L; ++l)
+        k |= (uint64_t)(g->lv[l].steps & 1) << l;
+    const int sub = 1 << (g->L - 1);
+    for (int j = 0; j < sub; ++j)
+        if ((g->finest_steps + j + 1) % g->d.drag_every == 0)
+            k |= 1ull << (8 + j);
+    return k;
+}
+
+static void graphs_clear(lbm_grid *g)
+{
+    for (lbm_grid::StepGraph &sg : g->graphs)
+        (void)hipGraphExecDestroy(sg.exec);
+    g->graphs.clear();
+}
+
+static lbm_status graph_step(lbm_grid *g)
+{
+    const uint64_t key = step_key(g);
+    for (const lbm_grid::StepGraph &sg : g->graphs) {
+        if (sg.key != key)
+            continue;
+        HIPX(g, hipGraphLaunch(sg.exec, g->stream));
+        for (int l = 0; l < g->L; ++l)
+            g->lv[l].steps += sg.level_steps[l];
+        g->coarse_steps += sg.coarse;
+        g->finest_steps += sg.finest;
+        g->samples += sg.samples;
+        g->ring_count += sg.ring;
+        return LBM_OK;
+    }
+    if (g->graphs.size() >= MAX_GRAPHS)
+        graphs_clear(g);
+    // capture one coarse step; its host bookkeeping runs as in an eager step
+    lbm_grid::StepGraph sg{};
+    sg.key = key;
+    int64_t steps0[8] = {0};
+    for (int l = 0; l < g->L; ++l)
+        steps0[l] = g->lv[l].steps;
+    const int64_t c0 = g->coarse_steps, f0 = g->finest_steps, s0 = g->samples, r0 = g->ring_count;
+    auto restore = [&]() {
+        for (int l = 0; l < g->L; ++l)
+            g->lv[l].steps = steps0[l];
+        g->coarse_steps = c0, g->finest_steps = f0, g->samples = s0, g->ring_count = r0;
+    };
+    HIPX(g, hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+    const lbm_status st = coarse_step(g);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(g->stream, &graph);
+    if (st != LBM_OK || ec != hipSuccess) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        restore();
+        return st != LBM_OK ? st : fail(g, LBM_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    }
+    const hipError_t ei = hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        restore();
+        return fail(g, LBM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    for (int l = 0; l < g->L; ++l)
+        sg.level_steps[l] = g->lv[l].steps - steps0[l];
+    sg.coarse = g->coarse_steps - c0;
+    sg.finest = g->finest_steps - f0;
+    sg.samples = g->samples - s0;
+    sg.ring = g->ring_count - r0;
+    g->graphs.push_back(sg);
+    const hipError_t el = hipGraphLaunch(sg.exec, g->stream);
+    if (el != hipSuccess) {
+        restore();
+        return fail(g, LBM_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(el));
+    }
+    return LBM_OK;
+}
+
+static lbm_status sync_ring_pos(lbm_grid *g)
+{
+    if (!g->d_ring_pos)
+        return LBM_OK;
+    const unsigned long long pos = (unsigned long long)g->ring_count;
+    HIPX(g, hipStreamSynchronize(g->stream));
+    HIPX(g, hipMemcpy(g->d_ring_pos, &pos, sizeof pos, hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
 namespace lbm {
 lbm_status grid_fail(lbm_grid *g, lbm_status st, const std::string &msg) { return fail(g, st, msg); }
 CollideArgs grid_collide_args(lbm_grid *g, int l) { return collide_args(g, l); }
 lbm_status grid_coarse_step(lbm_grid *g) { return coarse_step(g); }
 size_t grid_storage_bytes(int storage) { return storage_bytes(storage); }
 int grid_timing_mark(lbm_grid *g) { return timing_mark(g); }
+void grid_graphs_clear(lbm_grid *g) { graphs_clear(g); }
+lbm_status grid_sync_ring_pos(lbm_grid *g) { return sync_ring_pos(g); }
 }  // namespace lbm
 
 // ---------------------------------------------------------------------------
@@ -510,12 +608,14 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
             (st = dalloc(g, &g->d_sample, (size_t)3 * g->nseg)) != LBM_OK ||
             (st = dalloc(g, &g->d_acc_branch, (size_t)3 * g->nseg)) != LBM_OK ||
             (st = dalloc(g, &g->d_acc_total, 3)) != LBM_OK || (st = dalloc(g, &g->d_ring, (size_t)3 * RING)) != LBM_OK ||
-            (st = dalloc(g, &g->d_counter, 1)) != LBM_OK || (st = dalloc(g, &g->d_mass, 4 + 4 * 1024)) != LBM_OK)
+            (st = dalloc(g, &g->d_counter, 1)) != LBM_OK || (st = dalloc(g, &g->d_ring_pos, 1)) != LBM_OK ||
+            (st = dalloc(g, &g->d_mass, 4 + 4 * 1024)) != LBM_OK)
             return st;
         HIPX(g, hipMemsetAsync(g->d_acc_branch, 0, sizeof(double) * 3 * g->nseg, g->stream));
         HIPX(g, hipMemsetAsync(g->d_acc_total, 0, sizeof(double) * 3, g->stream));
         HIPX(g, hipMemsetAsync(g->d_ring, 0, sizeof(double) * 3 * RING, g->stream));
         HIPX(g, hipMemsetAsync(g->d_counter, 0, sizeof(unsigned), g->stream));
+        HIPX(g, hipMemsetAsync(g->d_ring_pos, 0, sizeof(unsigned long long), g->stream));
     }
     HIPX(g, hipStreamSynchronize(g->stream));
     g->state = 1;
@@ -532,8 +632,9 @@ lbm_status lbm_step(lbm_grid *g, int32_t n)
         return fail(g, LBM_E_STATE, "set_geometry first");
     if (n < 0)
         return fail(g, LBM_E_INVALID, "negative step count");
+    const bool graph = (g->d.flags & LBM_F_GRAPH) && !g->timing;
     for (int s = 0; s < n; ++s) {
-        lbm_status st = coarse_step(g);
+        lbm_status st = graph ? graph_step(g) : coarse_step(g);
         if (st != LBM_OK)
             return st;
     }

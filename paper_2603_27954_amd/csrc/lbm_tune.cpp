@@ -59,6 +59,7 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     const std::string key = tune_key(g);
     Choice cached{};
     if (cache_lookup(cache_path, key, &cached)) {
+        grid_graphs_clear(g);
         g->threads = cached.threads;
         g->tile = cached.tile;
         g->occ_even = cached.occ_even;
@@ -157,6 +158,9 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     g->finest_steps = fs;
     g->samples = sm;
     g->ring_count = rc;
+    grid_graphs_clear(g);
+    if (st == LBM_OK)
+        st = grid_sync_ring_pos(g);
     const Choice use = st == LBM_OK ? best : old;
     g->threads = use.threads;
     g->tile = use.tile;
