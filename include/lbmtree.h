@@ -58,7 +58,8 @@ typedef enum {
 /* flags of lbm_grid_desc.flags */
 #define LBM_F_NO_GALILEAN 1u /* drop the Galilean-correction terms of the second-order relaxation */
 #define LBM_F_GRAPH 2u       /* replay each coarse step from a captured HIP graph */
-#define LBM_F_PERSISTENT 4u  /* run each coarse step as one persistent launch */
+#define LBM_F_PERSISTENT 4u  /* run each coarse step as one persistent launch; currently disabled:
+                                lbm_create_grid rejects it with LBM_E_INVALID */
 #define LBM_F_AUTOTUNE 8u    /* time the tile candidates at set_geometry and keep the fastest */
 
 /* One cylinder of the tree (Sec. 2.1: the tree is an assembly of cylinders).
@@ -141,6 +142,8 @@ typedef struct {
     int32_t tile_cells;       /* cells per work-group of the block-level collide kernel */
     int32_t threads;          /* work-group size of the block-level collide kernel */
     int32_t occ_even, occ_odd;/* resident-wave caps per SIMD of the collide kernel (0 = none) */
+    int32_t persist_wgs;      /* work-groups of the persistent launch (all resident) */
+    int32_t persist_graph;    /* 1: the persistent launch replays from a captured graph */
 } lbm_info;
 
 /* ---- lifecycle ------------------------------------------------------------ */

@@ -12,7 +12,7 @@
 //    with the coarse rate and step.
 // Rebuilt populations are written to the read positions of the level's next
 // step (A-A parity aware).
-#include "lbm_access.h"
+#include "lbm_bodies.h"
 
 namespace lbm {
 
@@ -20,19 +20,7 @@ template <int B, typename S, bool ODD>
 __global__ void __launch_bounds__(256) k_amr_moments(const CollideArgs a, const uint32_t *cells, int n, float om1,
                                                      float dt, float *out)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n)
-        return;
-    float g[NQ];
-    load_pre<B, S, ODD>(a, cells[t], g);
-    const Transfer tr = to_transfer(forward_moments(g), om1, dt);
-    out[0 * (size_t)n + t] = tr.drho;
-    out[1 * (size_t)n + t] = tr.ux;
-    out[2 * (size_t)n + t] = tr.uy;
-    out[3 * (size_t)n + t] = tr.uz;
-#pragma unroll
-    for (int v = 0; v < 6; ++v)
-        out[(4 + v) * (size_t)n + t] = tr.d[v];
+    amr_moments_item<B, S, ODD>(a, cells, n, om1, dt, out, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <int B, typename S, bool ODD>
@@ -40,35 +28,7 @@ __global__ void __launch_bounds__(256) k_amr_prolong(const CollideArgs fine, con
                                                      const int32_t *src, int n, int nsrc, const float *m0,
                                                      const float *m1, float om1, float dt)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n)
-        return;
-    float v[10];
-#pragma unroll
-    for (int k = 0; k < 10; ++k)
-        v[k] = 0.0f;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const float w = ((q & 1) ? 0.25f : 0.75f) * ((q & 2) ? 0.25f : 0.75f) * ((q & 4) ? 0.25f : 0.75f);
-        const int s = src[8 * (size_t)t + q];
-#pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            const float x0 = m0[k * (size_t)nsrc + s];
-            const float x = m1 ? 0.5f * (x0 + m1[k * (size_t)nsrc + s]) : x0;
-            v[k] = fmaf(w, x, v[k]);
-        }
-    }
-    Transfer tr;
-    tr.drho = v[0];
-    tr.ux = v[1];
-    tr.uy = v[2];
-    tr.uz = v[3];
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        tr.d[k] = v[4 + k];
-    float g[NQ];
-    back_transform(from_transfer(tr, om1, dt), g);
-    store_pre<B, S, ODD>(fine, ghosts[t], g);
+    amr_prolong_item<B, S, ODD>(fine, ghosts, src, n, nsrc, m0, m1, om1, dt, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <int B, typename S, bool ODD_C, bool ODD_F>
@@ -76,43 +36,8 @@ __global__ void __launch_bounds__(256) k_amr_restrict(const CollideArgs coarse, 
                                                       const uint32_t *band, const uint32_t *child, int n, float om_c,
                                                       float dt_c, float om_f, float dt_f)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n)
-        return;
-    float drho = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f, d[6] = {0, 0, 0, 0, 0, 0};
-    int cnt = 0;
-    for (int q = 0; q < 8; ++q) {
-        const uint32_t c = child[8 * (size_t)t + q];
-        if (c == FULL_MASK)
-            continue;
-        float g[NQ];
-        load_pre<B, S, ODD_F>(fine, c, g);
-        const Transfer tr = to_transfer(forward_moments(g), om_f, dt_f);
-        const float rho = 1.0f + tr.drho;
-        drho += tr.drho;
-        mx = fmaf(rho, tr.ux, mx);
-        my = fmaf(rho, tr.uy, my);
-        mz = fmaf(rho, tr.uz, mz);
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            d[k] += tr.d[k];
-        ++cnt;
-    }
-    if (cnt == 0)
-        return;
-    const float ic = 1.0f / (float)cnt;
-    Transfer tr;
-    tr.drho = drho * ic;
-    const float irho = 1.0f / (float)cnt / (1.0f + tr.drho);
-    tr.ux = mx * irho;
-    tr.uy = my * irho;
-    tr.uz = mz * irho;
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        tr.d[k] = d[k] * ic;
-    float g[NQ];
-    back_transform(from_transfer(tr, om_c, dt_c), g);
-    store_pre<B, S, ODD_C>(coarse, band[t], g);
+    amr_restrict_item<B, S, ODD_C, ODD_F>(coarse, fine, band, child, n, om_c, dt_c, om_f, dt_f,
+                                          blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

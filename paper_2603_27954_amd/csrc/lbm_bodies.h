@@ -1,0 +1,440 @@
+// Device bodies of the hot-path kernels, shared by the one-kernel-per-phase
+// launches and by the persistent launch that runs a whole coarse step, so the
+// two forms execute the same arithmetic (paper Sec. 2.2).  Each body handles
+// one work item: a tile of a level (collide), one link (bounce-back), one
+// branch segment (force sums) or one interface cell (coarse/fine transfer).
+#pragma once
+#include "lbm_access.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// collide and stream: dense (x-pencil) levels
+// ---------------------------------------------------------------------------
+
+// Odd step when every wavefront lies in one x-row (nx a multiple of 64): y and
+// z are wave-uniform, so the eight neighbour-row offsets live in scalar
+// registers and each direction addresses (scalar base + row offset) + one of
+// three lane offsets (x-1, x, x+1; wrapped inside the row so every address
+// stays in the level).
+template <typename S>
+__device__ __forceinline__ void dense_odd_rowwave(const CollideArgs &a, uint32_t own, int x, bool at_in,
+                                                  bool at_out)
+{
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const uint32_t first = __builtin_amdgcn_readfirstlane(own - (uint32_t)x);  // row start, uniform
+    const uint32_t row = first / (uint32_t)nx;
+    const int y = (int)(row % (uint32_t)ny), z = (int)(row / (uint32_t)ny);
+    const int ys[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
+    const int zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
+    const uint32_t vx[3] = {x == 0 ? own + (uint32_t)nx - 1u : own - 1u, own,
+                            x == nx - 1 ? own + 1u - (uint32_t)nx : own + 1u};
+    float g[NQ];
+    const S *bk[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const int64_t roff = ((int64_t)ys[qcy(k) + 1] + (int64_t)ny * zs[qcz(k) + 1] - ((int64_t)y + (int64_t)ny * z)) * nx;
+        bk[k] = reinterpret_cast<const S *>(a.pop[k]) + roff;
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        g[qopp(k)] = ldp<S>(bk[k], vx[qcx(k) + 1]);
+    if (at_in || at_out) {
+        const size_t pl = (size_t)ny * nz;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int ty = ys[qcy(k) + 1], tz = zs[qcz(k) + 1];
+            if (at_in && qcx(k) == -1)
+                g[qopp(k)] = inlet_dev(a, a.in_prev, qopp(k), ty, tz);
+            if (at_out && qcx(k) == 1)
+                g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)tz * ny + ty];
+        }
+    }
+    collide(g, a.om1, a.om2, a.galilean != 0);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const bool leaves = (at_in && qcx(k) == -1) || (at_out && qcx(k) == 1);
+        if (!leaves)
+            stp<S>(const_cast<S *>(bk[k]), vx[qcx(k) + 1], g[k]);
+    }
+    if (at_in) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            if (qcx(i) == 1)
+                stp<S>(a.pop[i], own, inlet_dev(a, a.in_cur, i, ys[1 - qcy(i)], zs[1 - qcz(i)]));
+    }
+    if (at_out) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            if (qcx(i) == -1)
+                stp<S>(a.pop[i], (uint32_t)x + (uint32_t)nx * ((uint32_t)ys[qcy(i) + 1] + (uint32_t)ny * zs[qcz(i) + 1]), g[i]);
+    }
+}
+
+template <typename S, bool ODD, bool ROWWAVE>
+__device__ __forceinline__ void collide_dense_item(const CollideArgs &a, int item)
+{
+    if (item >= a.n_work)
+        return;
+    const uint2 w = a.work[item];
+    const int t = threadIdx.x;
+    if (w.y != FULL_MASK) {
+        const uint32_t *m = a.masks + (size_t)w.y * (DENSE_TILE / 32);
+        if (!((m[t >> 5] >> (t & 31)) & 1u))
+            return;
+    }
+    const uint32_t own = w.x * DENSE_TILE + t;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int x = (int)(own % (uint32_t)nx);
+    const uint32_t yz = own / (uint32_t)nx;
+    const int y = (int)(yz % (uint32_t)ny), z = (int)(yz / (uint32_t)ny);
+    const bool at_in = a.faces && x == 0, at_out = a.faces && x == nx - 1;
+    float g[NQ];
+
+    if (!ODD) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            g[k] = ldp_nt<S>(a.pop[k], own);
+        collide(g, a.om1, a.om2, a.galilean != 0);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            stp_nt<S>(a.pop[qopp(k)], own, g[k]);
+        if (at_out) {
+            const size_t pl = (size_t)ny * nz;
+#pragma unroll
+            for (int i = 0; i < NQ; ++i)
+                if (qcx(i) == -1)
+                    a.gbuf[i * pl + (size_t)z * ny + y] = g[i];
+        }
+        return;
+    }
+
+    if (ROWWAVE) {
+        dense_odd_rowwave<S>(a, own, x, at_in, at_out);
+        return;
+    }
+    // odd: population opp(k) comes from slot k of x + c_k, f*_k goes back there
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ys[3] = {ym, y, yp}, zs[3] = {zm, z, zp}, xs[3] = {xm, x, xp};
+    uint32_t addr[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        addr[k] = (uint32_t)xs[qcx(k) + 1] + (uint32_t)nx * ((uint32_t)ys[qcy(k) + 1] + (uint32_t)ny * zs[qcz(k) + 1]);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        g[qopp(k)] = ldp<S>(a.pop[k], addr[k]);
+    if (at_in || at_out) {
+        const size_t pl = (size_t)ny * nz;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int ty = ys[qcy(k) + 1], tz = zs[qcz(k) + 1];
+            if (at_in && qcx(k) == -1)  // enters from the inlet ghost at (y + cy_k, z + cz_k)
+                g[qopp(k)] = inlet_dev(a, a.in_prev, qopp(k), ty, tz);
+            if (at_out && qcx(k) == 1)  // enters from the outlet ghost, a copy of plane nx-1
+                g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)tz * ny + ty];
+        }
+    }
+    collide(g, a.om1, a.om2, a.galilean != 0);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const bool leaves = (at_in && qcx(k) == -1) || (at_out && qcx(k) == 1);
+        if (!leaves)
+            stp<S>(a.pop[k], addr[k], g[k]);
+    }
+    if (at_in) {
+        // populations entering from the inlet ghost for the next (even) step
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            if (qcx(i) == 1)
+                stp<S>(a.pop[i], own, inlet_dev(a, a.in_cur, i, ys[1 - qcy(i)], zs[1 - qcz(i)]));
+    }
+    if (at_out) {
+        // the outlet ghost (nx, y, z) copies this cell; its populations with
+        // cx = -1 land on (nx - 1, y + cy, z + cz)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            if (qcx(i) == -1)
+                stp<S>(a.pop[i], (uint32_t)x + (uint32_t)nx * ((uint32_t)ys[qcy(i) + 1] + (uint32_t)ny * zs[qcz(i) + 1]), g[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// collide and stream: block levels (refined, sparse)
+// ---------------------------------------------------------------------------
+
+template <int B, typename S, bool ODD>
+__device__ __forceinline__ void cell_update_block(const CollideArgs &a, int blk, int c, const int *nb)
+{
+    constexpr int CELLS = B * B * B;
+    constexpr int LB = B == 16 ? 4 : 3;
+    const int x = c & (B - 1), y = (c >> LB) & (B - 1), z = c >> (2 * LB);
+    const uint32_t own = (uint32_t)blk * CELLS + c;
+    float g[NQ];
+    if (!ODD) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            g[k] = ldp_nt<S>(a.pop[k], own);
+        collide(g, a.om1, a.om2, a.galilean != 0);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            stp_nt<S>(a.pop[qopp(k)], own, g[k]);
+        return;
+    }
+    const NbrLane<B> L(x, y, z);
+    uint32_t addr[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const int sx = qcx(k) + 1, sy = qcy(k) + 1, sz = qcz(k) + 1;
+        addr[k] = (uint32_t)nb[L.code(sx, sy, sz)] * CELLS + L.local(sx, sy, sz);
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        g[qopp(k)] = ldp<S>(a.pop[k], addr[k]);
+    collide(g, a.om1, a.om2, a.galilean != 0);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        stp<S>(a.pop[k], addr[k], g[k]);
+}
+
+// one tile (work-group item wg = block item * parts + part) of a block level;
+// nb is the work-group's 27-entry neighbour table in LDS
+template <int B, typename S, bool ODD>
+__device__ __forceinline__ void collide_block_item(const CollideArgs &a, int wg, int *nb)
+{
+    constexpr int CELLS = B * B * B;
+    const int item = wg / a.parts, part = wg - item * a.parts;
+    if (item >= a.n_work)
+        return;
+    const uint2 w = a.work[item];
+    const int blk = (int)w.x;
+    if (threadIdx.x < 27)
+        nb[threadIdx.x] = a.nbr[(size_t)blk * 27 + threadIdx.x];
+    __syncthreads();
+    const int tile = CELLS / a.parts;
+    const int c0 = part * tile;
+    const uint32_t *mask = w.y == FULL_MASK ? nullptr : a.masks + (size_t)w.y * (CELLS / 32);
+    for (int c = c0 + (int)threadIdx.x; c < c0 + tile; c += (int)blockDim.x) {
+        if (mask && !((mask[c >> 5] >> (c & 31)) & 1u))
+            continue;
+        cell_update_block<B, S, ODD>(a, blk, c, nb);
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// interpolated bounce-back (Bouzidi, linear) + momentum exchange
+// ---------------------------------------------------------------------------
+
+template <typename S, bool ODD_DONE>
+__device__ __forceinline__ void link_update(const LinkArgs &a, int l)
+{
+    if (l >= a.n)
+        return;
+    const uint8_t dj = a.dir[l];
+    const int j = dj & 31, jb = 26 - j;
+    const bool up = (dj & 0x80) != 0;
+    const float q = a.q[l];
+    const uint32_t af = a.af[l], ap = a.ap[l], am = a.am[l];
+    const S *pj = reinterpret_cast<const S *>(a.pop + (size_t)j * a.dir_bytes);
+    const S *pjb = reinterpret_cast<const S *>(a.pop + (size_t)jb * a.dir_bytes);
+    float g1, g2, g3;  // f*_j(x_f), f*_j(x_f - c_j), f*_opp(j)(x_f)
+    if (!ODD_DONE) {
+        g1 = Store<S>::ld(pjb[af]);
+        g3 = Store<S>::ld(pj[af]);
+        g2 = up ? Store<S>::ld(pjb[am]) : 0.0f;
+    } else {
+        g1 = Store<S>::ld(pj[ap]);
+        g3 = Store<S>::ld(pjb[am]);
+        g2 = up ? Store<S>::ld(pj[af]) : 0.0f;
+    }
+    float gn;
+    if (q < 0.5f)
+        gn = up ? fmaf(2.0f * q, g1 - g2, g2) : g1;
+    else {
+        const float r = 0.5f / q;
+        gn = fmaf(r, g1 - g3, g3);
+    }
+    S *dst = reinterpret_cast<S *>(a.pop + (size_t)(ODD_DONE ? jb : j) * a.dir_bytes);
+    dst[ODD_DONE ? af : ap] = Store<S>::st(gn);
+    if (a.lforce) {
+        const float wj = w1d(qcx(j)) * w1d(qcy(j)) * w1d(qcz(j));
+        const float mom = 2.0f * wj + g1 + gn;
+        a.lforce[3 * (size_t)l + 0] = qcx(j) * mom;
+        a.lforce[3 * (size_t)l + 1] = qcy(j) * mom;
+        a.lforce[3 * (size_t)l + 2] = qcz(j) * mom;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Sum of a work-group's values in a fixed order (lane tree per wave, then
+// waves in order): the same inputs give the same bits on every run.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+        sh[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NT / 64; ++i)
+            t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+// Per-branch sum of the link forces of segment b (links sorted by branch) in
+// a fixed order (lane tree, then waves in order): thread 0 stores it in
+// sample[3b..3b+2] and adds it to acc_branch.
+__device__ __forceinline__ void branch_segment_sum(const float *lforce, const int *seg, int b, double *sample,
+                                                   double *acc_branch, double *sh)
+{
+    const int s0 = seg[b], s1 = seg[b + 1];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int l = s0 + (int)threadIdx.x; l < s1; l += 256) {
+        v[0] += (double)lforce[3 * (size_t)l];
+        v[1] += (double)lforce[3 * (size_t)l + 1];
+        v[2] += (double)lforce[3 * (size_t)l + 2];
+    }
+    for (int a = 0; a < 3; ++a) {
+        const double t = block_sum<256>(v[a], sh);
+        if (threadIdx.x == 0) {
+            sample[3 * b + a] = t;
+            acc_branch[3 * b + a] += t;
+        }
+    }
+}
+
+// Total of the per-branch sums in branch order (one thread): added to
+// acc_total and appended to the sample ring at the device-held position
+// ring_pos, which a replayed graph or persistent launch advances itself.
+__device__ __forceinline__ void branch_total(const double *sample, int nseg, double *acc_total, double *ring,
+                                             unsigned long long *ring_pos)
+{
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < nseg; ++i)
+        for (int a = 0; a < 3; ++a)
+            t[a] += __builtin_nontemporal_load(&sample[3 * i + a]);
+    const unsigned long long slot = *ring_pos % RING;
+    for (int a = 0; a < 3; ++a) {
+        acc_total[a] += t[a];
+        ring[3 * slot + a] = t[a];
+    }
+    *ring_pos += 1ull;
+}
+
+// ---------------------------------------------------------------------------
+// coarse/fine transfer in moment space (one interface cell per thread t)
+// ---------------------------------------------------------------------------
+
+template <int B, typename S, bool ODD>
+__device__ __forceinline__ void amr_moments_item(const CollideArgs &a, const uint32_t *cells, int n, float om1,
+                                                 float dt, float *out, int t)
+{
+    if (t >= n)
+        return;
+    float g[NQ];
+    load_pre<B, S, ODD>(a, cells[t], g);
+    const Transfer tr = to_transfer(forward_moments(g), om1, dt);
+    out[0 * (size_t)n + t] = tr.drho;
+    out[1 * (size_t)n + t] = tr.ux;
+    out[2 * (size_t)n + t] = tr.uy;
+    out[3 * (size_t)n + t] = tr.uz;
+#pragma unroll
+    for (int v = 0; v < 6; ++v)
+        out[(4 + v) * (size_t)n + t] = tr.d[v];
+}
+
+template <int B, typename S, bool ODD>
+__device__ __forceinline__ void amr_prolong_item(const CollideArgs &fine, const uint32_t *ghosts,
+                                                 const int32_t *src, int n, int nsrc, const float *m0,
+                                                 const float *m1, float om1, float dt, int t)
+{
+    if (t >= n)
+        return;
+    float v[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k)
+        v[k] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const float w = ((q & 1) ? 0.25f : 0.75f) * ((q & 2) ? 0.25f : 0.75f) * ((q & 4) ? 0.25f : 0.75f);
+        const int s = src[8 * (size_t)t + q];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            const float x0 = m0[k * (size_t)nsrc + s];
+            const float x = m1 ? 0.5f * (x0 + m1[k * (size_t)nsrc + s]) : x0;
+            v[k] = fmaf(w, x, v[k]);
+        }
+    }
+    Transfer tr;
+    tr.drho = v[0];
+    tr.ux = v[1];
+    tr.uy = v[2];
+    tr.uz = v[3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        tr.d[k] = v[4 + k];
+    float g[NQ];
+    back_transform(from_transfer(tr, om1, dt), g);
+    store_pre<B, S, ODD>(fine, ghosts[t], g);
+}
+
+template <int B, typename S, bool ODD_C, bool ODD_F>
+__device__ __forceinline__ void amr_restrict_item(const CollideArgs &coarse, const CollideArgs &fine,
+                                                  const uint32_t *band, const uint32_t *child, int n, float om_c,
+                                                  float dt_c, float om_f, float dt_f, int t)
+{
+    if (t >= n)
+        return;
+    float drho = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f, d[6] = {0, 0, 0, 0, 0, 0};
+    int cnt = 0;
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t c = child[8 * (size_t)t + q];
+        if (c == FULL_MASK)
+            continue;
+        float g[NQ];
+        load_pre<B, S, ODD_F>(fine, c, g);
+        const Transfer tr = to_transfer(forward_moments(g), om_f, dt_f);
+        const float rho = 1.0f + tr.drho;
+        drho += tr.drho;
+        mx = fmaf(rho, tr.ux, mx);
+        my = fmaf(rho, tr.uy, my);
+        mz = fmaf(rho, tr.uz, mz);
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            d[k] += tr.d[k];
+        ++cnt;
+    }
+    if (cnt == 0)
+        return;
+    const float ic = 1.0f / (float)cnt;
+    Transfer tr;
+    tr.drho = drho * ic;
+    const float irho = 1.0f / (float)cnt / (1.0f + tr.drho);
+    tr.ux = mx * irho;
+    tr.uy = my * irho;
+    tr.uz = mz * irho;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        tr.d[k] = d[k] * ic;
+    float g[NQ];
+    back_transform(from_transfer(tr, om_c, dt_c), g);
+    store_pre<B, S, ODD_C>(coarse, band[t], g);
+}
+
+}  // namespace lbm

@@ -51,13 +51,23 @@ struct lbm_grid {
     // state only through the A-A parity of every level and the phase of the
     // force sampling, so one graph per such key is replayed, and the host
     // counters advance by the deltas recorded at capture.
+    // A persistent plan holds the coarse step's phase list on the device and
+    // is launched directly or from a graph that captured that launch.
     struct StepGraph {
         uint64_t key;
-        hipGraphExec_t exec;
+        hipGraphExec_t exec;          // null: persistent plan launched directly
+        lbm::Phase *d_phases;         // persistent plans only
+        unsigned *d_ctr;              // claim / finish counters of the phases
+        int n_phases;
         int64_t level_steps[8];
         int64_t coarse, finest, samples, ring;
     };
     std::vector<StepGraph> graphs;
+    std::vector<lbm::Phase> *rec = nullptr;  // recording a coarse step as phases
+    unsigned *d_abort = nullptr;   // set by a persistent launch whose bounded wait expired
+    int persist_grid = 0;       // work-groups of the persistent launch (0 = all resident)
+    int persist_max = 0, cus = 0;
+    bool persist_failed = false;   // a wait expired: the state is undefined
     // per-kernel timing (event pairs, kind 0 collide, 1 links)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -65,8 +75,14 @@ struct lbm_grid {
 
     ~lbm_grid()
     {
-        for (StepGraph &sg : graphs)
-            (void)hipGraphExecDestroy(sg.exec);
+        for (StepGraph &sg : graphs) {
+            if (sg.exec)
+                (void)hipGraphExecDestroy(sg.exec);
+            if (sg.d_phases)
+                (void)hipFree(sg.d_phases);
+            if (sg.d_ctr)
+                (void)hipFree(sg.d_ctr);
+        }
         for (hipEvent_t e : ev_pool)
             (void)hipEventDestroy(e);
         for (void *p : allocs)

@@ -52,6 +52,50 @@ struct LinkArgs {
     float *lforce;            // 3 per link when sampling, else null
 };
 
+// One phase of a coarse step run as a single persistent launch: the work
+// items of what would otherwise be one kernel launch, followed by a grid-wide
+// barrier.  The host records the phases in the order the per-phase launches
+// would run, so both forms execute the same bodies in the same order.
+enum PhaseKind : int {
+    PH_COLLIDE = 0,       // a; items = collide work items (dense tiles or block tiles)
+    PH_LINKS = 1,         // la, odd = parity just completed; items = ceil(la.n / 256)
+    PH_BRANCH_SUM = 2,    // items = nseg
+    PH_BRANCH_TOTAL = 3,  // items = 1
+    PH_AMR_MOMENTS = 4,   // a = coarse level, cells = sources; items = ceil(n / 256)
+    PH_AMR_PROLONG = 5,   // a = fine level, cells = ghosts, src = stencils
+    PH_AMR_RESTRICT = 6,  // a = coarse, b = fine, cells = band, child = children
+};
+
+struct Phase {
+    int kind;
+    int odd, odd2;            // A-A parity (restriction: coarse, fine)
+    int rowwave;              // dense odd collide: row-per-wave variant
+    int items;                // work items (one work-group each)
+    int chunk, chunks;        // items per claim, number of claims
+    int n, nsrc;
+    float om1, dt, om2, dt2;
+    CollideArgs a, b;
+    LinkArgs la;
+    const uint32_t *cells;
+    const int32_t *src;
+    const uint32_t *child;
+    const float *m0, *m1;
+    float *out;
+    const float *lforce;
+    const int *seg;
+    int nseg;
+    double *sample, *acc_branch, *acc_total, *ring;
+    unsigned long long *ring_pos;
+};
+
+// launcher of the persistent coarse step (lbm_persist.hip).  ctr: 2 n_phases
+// + 1 counters, zero before the first launch (each launch leaves them zero);
+// abort_flag: set by the launch when a bounded wait expired.  Any grid size
+// is correct; persistent_max_grid gives the number of resident work-groups.
+hipError_t launch_persistent(int B, int storage, const Phase *phases, int n_phases, unsigned *ctr,
+                             unsigned *abort_flag, int grid, hipStream_t s);
+hipError_t persistent_max_grid(int B, int storage, int device, int *grid, int *cus);
+
 struct DevLevel {
     int level;
     bool dense = false;       // x-pencil layout over the whole box (no blocks)

@@ -139,11 +139,29 @@ static int timing_mark(lbm_grid *g)
     return (int)g->ev_pool.size() - 1;
 }
 
+static Phase new_phase(PhaseKind k)
+{
+    Phase p;
+    std::memset(&p, 0, sizeof p);
+    p.kind = k;
+    return p;
+}
+
 static lbm_status level_collide(lbm_grid *g, int l)
 {
     DevLevel &v = g->lv[l];
     const int odd = (int)(v.steps & 1);
     CollideArgs a = collide_args(g, l);
+    if (g->rec) {
+        Phase p = new_phase(PH_COLLIDE);
+        p.odd = odd;
+        p.a = a;
+        p.rowwave = a.dense && a.nx % 64 == 0;
+        p.items = a.dense ? a.n_work : a.n_work * a.parts;
+        if (p.items > 0)
+            g->rec->push_back(p);
+        return LBM_OK;
+    }
     const int e0 = timing_mark(g);
     HIPX(g, launch_collide(g->B, g->d.storage, odd, a, g->threads,
                            lds_for_occupancy(odd ? g->occ_odd : g->occ_even), g->stream));
@@ -158,20 +176,48 @@ static lbm_status finest_links(lbm_grid *g, int odd_done)
     const bool sample = (g->finest_steps % g->d.drag_every) == 0;
     if (g->n_links > 0) {
         LinkArgs a = link_args(g, sample);
-        const int e0 = timing_mark(g);
-        HIPX(g, launch_links(g->d.storage, odd_done, a, g->stream));
-        const int e1 = timing_mark(g);
-        if (e0 >= 0 && e1 >= 0)
-            g->ev_pairs.push_back({e0, 1});
+        if (g->rec) {
+            Phase p = new_phase(PH_LINKS);
+            p.odd = odd_done;
+            p.la = a;
+            p.items = (a.n + 255) / 256;
+            g->rec->push_back(p);
+        } else {
+            const int e0 = timing_mark(g);
+            HIPX(g, launch_links(g->d.storage, odd_done, a, g->stream));
+            const int e1 = timing_mark(g);
+            if (e0 >= 0 && e1 >= 0)
+                g->ev_pairs.push_back({e0, 1});
+        }
     }
     if (sample) {
-        if (g->n_links > 0) {
-            HIPX(g, launch_branch_reduce(g->d_lforce, g->d_seg, g->nseg, g->d_sample, g->d_acc_branch,
-                                         g->d_acc_total, g->d_ring, g->d_ring_pos, g->d_counter,
-                                         g->stream));
+        // the device ring position advances exactly when the reduction runs
+        if (g->n_links > 0 && g->nseg > 0) {
+            if (g->rec) {
+                Phase p = new_phase(PH_BRANCH_SUM);
+                p.lforce = g->d_lforce;
+                p.seg = g->d_seg;
+                p.nseg = g->nseg;
+                p.sample = g->d_sample;
+                p.acc_branch = g->d_acc_branch;
+                p.items = g->nseg;
+                g->rec->push_back(p);
+                Phase t = new_phase(PH_BRANCH_TOTAL);
+                t.sample = g->d_sample;
+                t.nseg = g->nseg;
+                t.acc_total = g->d_acc_total;
+                t.ring = g->d_ring;
+                t.ring_pos = g->d_ring_pos;
+                t.items = 1;
+                g->rec->push_back(t);
+            } else {
+                HIPX(g, launch_branch_reduce(g->d_lforce, g->d_seg, g->nseg, g->d_sample, g->d_acc_branch,
+                                             g->d_acc_total, g->d_ring, g->d_ring_pos, g->d_counter,
+                                             g->stream));
+            }
+            g->ring_count++;
         }
         g->samples++;
-        g->ring_count++;
     }
     return LBM_OK;
 }
@@ -186,6 +232,20 @@ static lbm_status amr_moments(lbm_grid *g, int l, int slot)
     AmrPair &pr = g->amr.pairs[l];
     DevLevel &v = g->lv[l];
     CollideArgs a = collide_args(g, l);
+    if (g->rec) {
+        Phase p = new_phase(PH_AMR_MOMENTS);
+        p.odd = (int)(v.steps & 1);
+        p.a = a;
+        p.cells = pr.d_src;
+        p.n = (int)pr.h_src.size();
+        p.om1 = (float)v.om1;
+        p.dt = level_dt(g, l);
+        p.out = pr.d_mom[slot];
+        p.items = (p.n + 255) / 256;
+        if (p.n > 0)
+            g->rec->push_back(p);
+        return LBM_OK;
+    }
     HIPX(g, launch_amr_moments(g->B, g->d.storage, (int)(v.steps & 1), a, pr.d_src, (int)pr.h_src.size(),
                                (float)v.om1, level_dt(g, l), pr.d_mom[slot], g->stream));
     return LBM_OK;
@@ -197,6 +257,23 @@ static lbm_status amr_prolong(lbm_grid *g, int l, int sub)
     AmrPair &pr = g->amr.pairs[l];
     DevLevel &f = g->lv[l + 1];
     CollideArgs a = collide_args(g, l + 1);
+    if (g->rec) {
+        Phase p = new_phase(PH_AMR_PROLONG);
+        p.odd = (int)(f.steps & 1);
+        p.a = a;
+        p.cells = pr.d_ghost;
+        p.src = pr.d_ghost_src;
+        p.n = (int)pr.h_ghost.size();
+        p.nsrc = (int)pr.h_src.size();
+        p.m0 = pr.d_mom[0];
+        p.m1 = sub ? pr.d_mom[1] : nullptr;
+        p.om1 = (float)f.om1;
+        p.dt = level_dt(g, l + 1);
+        p.items = (p.n + 255) / 256;
+        if (p.n > 0)
+            g->rec->push_back(p);
+        return LBM_OK;
+    }
     HIPX(g, launch_amr_prolong(g->B, g->d.storage, (int)(f.steps & 1), a, pr.d_ghost, pr.d_ghost_src,
                                (int)pr.h_ghost.size(), (int)pr.h_src.size(), pr.d_mom[0],
                                sub ? pr.d_mom[1] : nullptr, (float)f.om1, level_dt(g, l + 1), g->stream));
@@ -209,6 +286,24 @@ static lbm_status amr_restrict(lbm_grid *g, int l)
     AmrPair &pr = g->amr.pairs[l];
     DevLevel &c = g->lv[l], &f = g->lv[l + 1];
     CollideArgs ac = collide_args(g, l), af = collide_args(g, l + 1);
+    if (g->rec) {
+        Phase p = new_phase(PH_AMR_RESTRICT);
+        p.odd = (int)(c.steps & 1);
+        p.odd2 = (int)(f.steps & 1);
+        p.a = ac;
+        p.b = af;
+        p.cells = pr.d_band;
+        p.child = pr.d_band_child;
+        p.n = (int)pr.h_band.size();
+        p.om1 = (float)c.om1;
+        p.dt = level_dt(g, l);
+        p.om2 = (float)f.om1;
+        p.dt2 = level_dt(g, l + 1);
+        p.items = (p.n + 255) / 256;
+        if (p.n > 0)
+            g->rec->push_back(p);
+        return LBM_OK;
+    }
     HIPX(g, launch_amr_restrict(g->B, g->d.storage, (int)(c.steps & 1), (int)(f.steps & 1), ac, af, pr.d_band,
                                 pr.d_band_child, (int)pr.h_band.size(), (float)c.om1, level_dt(g, l),
                                 (float)f.om1, level_dt(g, l + 1), g->stream));
@@ -275,9 +370,25 @@ static uint64_t step_key(const lbm_grid *g)
 
 static void graphs_clear(lbm_grid *g)
 {
-    for (lbm_grid::StepGraph &sg : g->graphs)
-        (void)hipGraphExecDestroy(sg.exec);
+    for (lbm_grid::StepGraph &sg : g->graphs) {
+        if (sg.exec)
+            (void)hipGraphExecDestroy(sg.exec);
+        if (sg.d_phases)
+            (void)hipFree(sg.d_phases);
+        if (sg.d_ctr)
+            (void)hipFree(sg.d_ctr);
+    }
     g->graphs.clear();
+}
+
+static void apply_deltas(lbm_grid *g, const lbm_grid::StepGraph &sg)
+{
+    for (int l = 0; l < g->L; ++l)
+        g->lv[l].steps += sg.level_steps[l];
+    g->coarse_steps += sg.coarse;
+    g->finest_steps += sg.finest;
+    g->samples += sg.samples;
+    g->ring_count += sg.ring;
 }
 
 static lbm_status graph_step(lbm_grid *g)
@@ -287,12 +398,7 @@ static lbm_status graph_step(lbm_grid *g)
         if (sg.key != key)
             continue;
         HIPX(g, hipGraphLaunch(sg.exec, g->stream));
-        for (int l = 0; l < g->L; ++l)
-            g->lv[l].steps += sg.level_steps[l];
-        g->coarse_steps += sg.coarse;
-        g->finest_steps += sg.finest;
-        g->samples += sg.samples;
-        g->ring_count += sg.ring;
+        apply_deltas(g, sg);
         return LBM_OK;
     }
     if (g->graphs.size() >= MAX_GRAPHS)
@@ -336,6 +442,134 @@ static lbm_status graph_step(lbm_grid *g)
     if (el != hipSuccess) {
         restore();
         return fail(g, LBM_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(el));
+    }
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// persistent coarse steps
+// ---------------------------------------------------------------------------
+
+static int persist_grid_size(const lbm_grid *g)
+{
+    return g->persist_grid > 0 ? std::min(g->persist_grid, g->persist_max) : g->persist_max;
+}
+
+static lbm_status persistent_step(lbm_grid *g)
+{
+    if (g->persist_failed)
+        return fail(g, LBM_E_DEVICE, "an earlier persistent launch was abandoned (a bounded wait expired)");
+    if (g->persist_max <= 0)
+        return fail(g, LBM_E_DEVICE, "the persistent kernel cannot be resident on this device");
+    const uint64_t key = step_key(g);
+    const int grid = persist_grid_size(g);
+    for (const lbm_grid::StepGraph &sg : g->graphs) {
+        if (sg.key != key)
+            continue;
+        if (sg.exec)
+            HIPX(g, hipGraphLaunch(sg.exec, g->stream));
+        else
+            HIPX(g, launch_persistent(g->B, g->d.storage, sg.d_phases, sg.n_phases, sg.d_ctr, g->d_abort, grid,
+                                      g->stream));
+        apply_deltas(g, sg);
+        return LBM_OK;
+    }
+    if (g->graphs.size() >= MAX_GRAPHS)
+        graphs_clear(g);
+    // record the coarse step as phases; its host bookkeeping runs as in an
+    // eager step
+    lbm_grid::StepGraph sg{};
+    sg.key = key;
+    int64_t steps0[8] = {0};
+    for (int l = 0; l < g->L; ++l)
+        steps0[l] = g->lv[l].steps;
+    const int64_t c0 = g->coarse_steps, f0 = g->finest_steps, s0 = g->samples, r0 = g->ring_count;
+    auto restore = [&]() {
+        for (int l = 0; l < g->L; ++l)
+            g->lv[l].steps = steps0[l];
+        g->coarse_steps = c0, g->finest_steps = f0, g->samples = s0, g->ring_count = r0;
+    };
+    std::vector<Phase> ph;
+    g->rec = &ph;
+    const lbm_status st = coarse_step(g);
+    g->rec = nullptr;
+    if (st != LBM_OK) {
+        restore();
+        return st;
+    }
+    // about two claims per work-group in large phases, one item per claim in
+    // small ones
+    for (Phase &p : ph) {
+        p.chunk = std::max(1, p.items / (2 * grid));
+        p.chunks = (p.items + p.chunk - 1) / p.chunk;
+    }
+    sg.n_phases = (int)ph.size();
+    const size_t nctr = 2 * ph.size() + 1;
+    if (hipMalloc(&sg.d_phases, sizeof(Phase) * std::max<size_t>(ph.size(), 1)) != hipSuccess ||
+        hipMalloc(&sg.d_ctr, sizeof(unsigned) * nctr) != hipSuccess) {
+        if (sg.d_phases)
+            (void)hipFree(sg.d_phases);
+        restore();
+        return fail(g, LBM_E_NOMEM, "hipMalloc of the phase list failed");
+    }
+    // the counters are cleared on the grid's stream, so the clear is ordered
+    // before the first launch (the grid's own stream does not synchronise with
+    // the null stream)
+    if (hipMemcpy(sg.d_phases, ph.data(), sizeof(Phase) * ph.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemsetAsync(sg.d_ctr, 0, sizeof(unsigned) * nctr, g->stream) != hipSuccess) {
+        (void)hipFree(sg.d_phases);
+        (void)hipFree(sg.d_ctr);
+        restore();
+        return fail(g, LBM_E_DEVICE, "upload of the phase list failed");
+    }
+    if (g->d.flags & LBM_F_GRAPH) {
+        // one graph node per coarse step
+        hipGraph_t graph = nullptr;
+        bool ok = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            const hipError_t el = launch_persistent(g->B, g->d.storage, sg.d_phases, sg.n_phases, sg.d_ctr,
+                                                    g->d_abort, grid, g->stream);
+            const hipError_t ee = hipStreamEndCapture(g->stream, &graph);
+            ok = el == hipSuccess && ee == hipSuccess && graph &&
+                 hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        }
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        if (!ok) {
+            (void)hipFree(sg.d_phases);
+            (void)hipFree(sg.d_ctr);
+            restore();
+            return fail(g, LBM_E_DEVICE, "capture of the persistent launch failed");
+        }
+    }
+    for (int l = 0; l < g->L; ++l)
+        sg.level_steps[l] = g->lv[l].steps - steps0[l];
+    sg.coarse = g->coarse_steps - c0;
+    sg.finest = g->finest_steps - f0;
+    sg.samples = g->samples - s0;
+    sg.ring = g->ring_count - r0;
+    g->graphs.push_back(sg);
+    const hipError_t el = sg.exec ? hipGraphLaunch(sg.exec, g->stream)
+                                  : launch_persistent(g->B, g->d.storage, sg.d_phases, sg.n_phases, sg.d_ctr,
+                                                      g->d_abort, grid, g->stream);
+    if (el != hipSuccess) {
+        restore();
+        return fail(g, LBM_E_DEVICE, std::string("persistent launch: ") + hipGetErrorString(el));
+    }
+    return LBM_OK;
+}
+
+// after persistent launches: fails when one of them was abandoned
+static lbm_status check_persistent(lbm_grid *g)
+{
+    if (!(g->d.flags & LBM_F_PERSISTENT) || !g->d_abort)
+        return LBM_OK;
+    unsigned ab = 0;
+    HIPX(g, hipStreamSynchronize(g->stream));
+    HIPX(g, hipMemcpy(&ab, g->d_abort, sizeof ab, hipMemcpyDeviceToHost));
+    if (ab) {
+        g->persist_failed = true;
+        return fail(g, LBM_E_DEVICE, "a persistent launch was abandoned (a bounded wait expired)");
     }
     return LBM_OK;
 }
@@ -398,6 +632,10 @@ lbm_status lbm_create_grid(const lbm_grid_desc *d, lbm_grid **out)
         return fail(nullptr, LBM_E_INVALID, "only periodic lateral faces are supported (periodic_yz = 1)");
     if (d->drag_every < 0)
         return fail(nullptr, LBM_E_INVALID, "drag_every must be >= 1");
+    if (d->flags & LBM_F_PERSISTENT)
+        return fail(nullptr, LBM_E_INVALID,
+                    "LBM_F_PERSISTENT is disabled: the persistent coarse-step launch has not passed its GPU "
+                    "tests; use LBM_F_GRAPH");
     if (d->turb_intensity < 0.0 || d->turb_intensity > 0.5)
         return fail(nullptr, LBM_E_INVALID, "turb_intensity must be in [0, 0.5]");
     if (d->turb_intensity > 0.0 && !(d->turb_length > 0.0))
@@ -617,6 +855,17 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
         HIPX(g, hipMemsetAsync(g->d_counter, 0, sizeof(unsigned), g->stream));
         HIPX(g, hipMemsetAsync(g->d_ring_pos, 0, sizeof(unsigned long long), g->stream));
     }
+    {
+        lbm_status st2 = dalloc(g, &g->d_abort, 1);
+        if (st2 != LBM_OK)
+            return st2;
+        HIPX(g, hipMemsetAsync(g->d_abort, 0, sizeof(unsigned), g->stream));
+        if (persistent_max_grid(g->B, g->d.storage, g->d.device, &g->persist_max, &g->cus) != hipSuccess) {
+            (void)hipGetLastError();
+            g->persist_max = 0;
+            g->cus = 0;
+        }
+    }
     HIPX(g, hipStreamSynchronize(g->stream));
     g->state = 1;
     if (device_bytes_out)
@@ -632,9 +881,10 @@ lbm_status lbm_step(lbm_grid *g, int32_t n)
         return fail(g, LBM_E_STATE, "set_geometry first");
     if (n < 0)
         return fail(g, LBM_E_INVALID, "negative step count");
+    const bool persistent = (g->d.flags & LBM_F_PERSISTENT) && !g->timing;
     const bool graph = (g->d.flags & LBM_F_GRAPH) && !g->timing;
     for (int s = 0; s < n; ++s) {
-        lbm_status st = graph ? graph_step(g) : coarse_step(g);
+        lbm_status st = persistent ? persistent_step(g) : graph ? graph_step(g) : coarse_step(g);
         if (st != LBM_OK)
             return st;
     }
@@ -647,6 +897,8 @@ lbm_status lbm_mass(lbm_grid *g, double *mass)
         return fail(g, LBM_E_INVALID, "null argument");
     if (g->state != 1)
         return fail(g, LBM_E_STATE, "set_geometry first");
+    if (lbm_status ps = check_persistent(g); ps != LBM_OK)
+        return ps;
     double init[4] = {0.0, 1e300, -1e300, 0.0};
     HIPX(g, hipMemcpyAsync(g->d_mass, init, sizeof init, hipMemcpyHostToDevice, g->stream));
     for (int l = 0; l < g->L; ++l) {
@@ -671,6 +923,8 @@ lbm_status lbm_drag(lbm_grid *g, lbm_drag_result *out, double *per_branch)
         return fail(g, LBM_E_INVALID, "null argument");
     if (g->state != 1)
         return fail(g, LBM_E_STATE, "set_geometry first");
+    if (lbm_status ps = check_persistent(g); ps != LBM_OK)
+        return ps;
     std::memset(out, 0, sizeof *out);
     const int nb = (int)g->branches.size();
     std::vector<double> acc(3 * g->nseg, 0.0);
@@ -702,6 +956,8 @@ lbm_status lbm_drag_series(lbm_grid *g, double *out, int64_t cap, int64_t *n)
         return fail(g, LBM_E_INVALID, "null argument");
     if (g->state != 1)
         return fail(g, LBM_E_STATE, "set_geometry first");
+    if (lbm_status ps = check_persistent(g); ps != LBM_OK)
+        return ps;
     std::vector<double> ring(3 * (size_t)RING);
     HIPX(g, hipMemcpyAsync(ring.data(), g->d_ring, sizeof(double) * ring.size(), hipMemcpyDeviceToHost, g->stream));
     HIPX(g, hipStreamSynchronize(g->stream));
@@ -772,6 +1028,11 @@ lbm_status lbm_get_info(const lbm_grid *g, lbm_info *out)
     out->threads = g->threads;
     out->occ_even = g->occ_even;
     out->occ_odd = g->occ_odd;
+    out->persist_wgs = persist_grid_size(g);
+    bool pg = false;
+    for (const lbm_grid::StepGraph &sg : g->graphs)
+        pg = pg || (sg.d_phases && sg.exec);
+    out->persist_graph = pg ? 1 : 0;
     return LBM_OK;
 }
 
@@ -812,6 +1073,8 @@ lbm_status lbm_get_populations(lbm_grid *g, int32_t level, double *f)
         return fail(g, LBM_E_INVALID, "null argument");
     if (g->state != 1)
         return fail(g, LBM_E_STATE, "set_geometry first");
+    if (lbm_status ps = check_persistent(g); ps != LBM_OK)
+        return ps;
     if (level < 0 || level >= g->L)
         return fail(g, LBM_E_INVALID, "level out of range");
     HIPX(g, hipStreamSynchronize(g->stream));

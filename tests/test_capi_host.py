@@ -48,7 +48,7 @@ def _desc(**kw):
 @pytest.mark.parametrize("bad", [
     dict(block_edge=12), dict(levels=0), dict(levels=5), dict(nx=60), dict(ny=0),
     dict(u_in=0.2), dict(u_in=-0.01), dict(re_h=0.0, nu=0.0), dict(storage=7),
-    dict(nx=64, levels=3, block_edge=16),
+    dict(nx=64, levels=3, block_edge=16), dict(flags=4),
 ])
 def test_invalid_descriptions_rejected_on_host(lt, bad):
     with pytest.raises(lt.LbmError) as e:
