@@ -34,6 +34,10 @@ NX, NY, NZ, H = 512, 256, 256, 128.0
 RE_H, U_IN = 2500.0, 0.05
 
 
+KERNEL_SOURCES = ("paper_2603_27954_amd/csrc/lbm_kernels.hip", "paper_2603_27954_amd/csrc/lbm_bodies.h",
+                  "paper_2603_27954_amd/csrc/lbm_access.h", "paper_2603_27954_amd/csrc/lbm_device.h")
+
+
 def measured_traffic():
     """HBM bytes per FP32 collide launch from the committed rocprofv3 counter
     summary, or None when the kernel sources changed since it was taken."""
@@ -47,7 +51,7 @@ def measured_traffic():
             k, _, v = line.strip().partition(" ")
             vals[k] = v.strip()
     m = hashlib.sha256()
-    for f in ("paper_2603_27954_amd/csrc/lbm_kernels.hip", "paper_2603_27954_amd/csrc/lbm_device.h"):
+    for f in KERNEL_SOURCES:
         m.update(open(os.path.join(ROOT, f), "rb").read())
     if vals.get("kernel_sources_sha256_16") != m.hexdigest()[:16]:
         return None
@@ -100,6 +104,76 @@ def cd_after(lt, torch, arr, storage, nsteps):
     return s[0] / (0.5 * U_IN ** 2 * ax)
 
 
+# Three-level workload: 16^3-cell blocks, finest box 1024 x 512 x 512 (4H x 2H
+# x 2H, H = 256 finest cells), coarse level 256 x 128 x 128 (1024 coarse
+# blocks); order-4 seeded three-child tree (seed 3, 121 branches); finest
+# blocks within 16 finest cells of a branch surface, middle blocks within 32
+# cells plus a wake box one H downstream; Re_H = 2e4.  The centre of mass sits
+# at (272, 245, 282), which centres the tree's extent in y and z and leaves the
+# refined region one coarse block clear of the box faces (wider bands do not
+# fit a 2H cross-section).
+AMR = dict(nx=1024, ny=512, nz=512, H=256.0, re_h=2.0e4, com=(272.0, 245.0, 282.0),
+           band=[0, 32, 16], wake=[0, 256, 0])
+
+
+def amr_tree(lt):
+    p = lt.tree_params(3, 4, 1.0, 0.3, [0.7] * 3, [0.7] * 3, [0.0, 120.0, 240.0], [35.0] * 3, [90.0] * 3,
+                       jitter=5.0, seed=3)
+    arr = lt.tree_generate(p)
+    lt.tree_place(arr, AMR["H"], list(AMR["com"]))
+    return arr
+
+
+def amr_leg(lt, torch, steps, warmup):
+    """Coarse steps of the three-level grid, eager launches and graph replay
+    (FP32 storage, autotuned block tiles).  MLUPS counts leaf fluid cells of
+    every level times its sub-steps per coarse step (2^l)."""
+    import tempfile
+    stream = STREAM
+    arr = amr_tree(lt)
+    res = {}
+    cache = os.path.join(tempfile.mkdtemp(), "tune.txt")  # both modes use the tiles tuned once
+    for mode, flags in (("eager", 0), ("graph", lt.LBM_F_GRAPH)):
+        g = lt.Grid(AMR["nx"], AMR["ny"], AMR["nz"], u_in=U_IN, re_h=AMR["re_h"], block_edge=16, levels=3,
+                    storage="fp32", drag_every=1, flags=flags, stream=stream.cuda_stream)
+        t0 = time.time()
+        g.set_geometry(arr, refine={"band": AMR["band"], "wake": AMR["wake"]})
+        setup = time.time() - t0
+        if TUNE:
+            g.autotune(cache)
+        info = g.info()
+        leaf = info["updated_cells"][:3]  # leaf fluid cells per level
+        upd = sum(leaf[l] << l for l in range(3))
+        work = sum(info["collided_cells"][l] << l for l in range(3))
+        g.step(warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        d = g.drag()
+        r = {"mlups": upd * steps / (ms * 1e-3) / 1e6, "ms_per_coarse_step": ms / steps,
+             "step_hbm_frac": 216.0 * work * steps / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), "cd": d["cd"]}
+        if mode == "eager":
+            g.timing(True)
+            g.step(steps)
+            torch.cuda.synchronize()
+            kt = g.timing_read()
+            g.timing(False)
+            r["collide_gbs"] = 216.0 * work * steps / (kt["collide_ms"] * 1e-3) / 1e9
+            res["grid"] = {"blocks": info["blocks"][:3], "leaf_fluid_cells": leaf,
+                           "collided_cells": info["collided_cells"][:3],
+                           "updates_per_coarse_step": upd, "links": info["links"], "branches": info["branches"],
+                           "device_gb": round(info["device_bytes"] / 1e9, 2), "setup_s": round(setup, 1),
+                           "tile_cells": info["tile_cells"], "threads": info["threads"],
+                           "effective_finest_cells": AMR["nx"] * AMR["ny"] * AMR["nz"]}
+        res[mode] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+        g.close()
+    return res
+
+
 def cpu_leg(lt, arr, nsteps):
     import oracle as O
     b = lt.branches_to_numpy(arr)
@@ -129,6 +203,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--storage", choices=["both", "fp32", "fp16"], default="both")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-amr", action="store_true", help="skip the three-level AMR leg")
+    ap.add_argument("--amr-steps", type=int, default=40)
+    ap.add_argument("--amr-only", action="store_true", help="run only the three-level AMR leg (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 512 MiB device copy (torch) as the reference dispatch "
                          "for the HBM byte counters")
@@ -156,6 +233,9 @@ def main():
         del src, dst
     global TUNE
     TUNE = not args.no_tune
+    if args.amr_only:
+        print(json.dumps({"amr_3level": amr_leg(lt, torch, args.amr_steps, 4)}), flush=True)
+        return
     arr = build_tree(lt)
     r32 = r16 = None
     if args.storage in ("both", "fp32"):
@@ -213,6 +293,12 @@ def main():
         out["cd_error"] = {"steps": args.cpu_steps, "cd_oracle": c["cd"],
                            "fp32_rel": abs(cd32 - c["cd"]) / abs(c["cd"]),
                            "fp16_rel": abs(cd16 - c["cd"]) / abs(c["cd"])}
+    if not args.no_amr:
+        a = amr_leg(lt, torch, args.amr_steps, 4)
+        a["workload"] = ("3-level octree, 16^3 blocks, finest 1024x512x512 (coarse 256x128x128), order-4 "
+                         "seeded tree H=256, Re_H=2e4, FP32, bands 16/32 + 1H wake")
+        a["coarse_steps"] = args.amr_steps
+        out["amr_3level"] = a
     print(json.dumps(out), flush=True)
 
 

@@ -133,7 +133,7 @@ typedef struct {
     int32_t levels, block_edge, storage;
     int64_t blocks[4];        /* allocated blocks per level (active + covered + ghost) */
     int64_t active_cells[4];  /* leaf fluid + solid cells per level */
-    int64_t updated_cells[4]; /* cells collided per level sub-step */
+    int64_t updated_cells[4]; /* leaf fluid cells per level: the cell updates one level sub-step counts */
     int64_t links;
     int32_t branches;
     double omega1[4];
@@ -144,6 +144,7 @@ typedef struct {
     int32_t occ_even, occ_odd;/* resident-wave caps per SIMD of the collide kernel (0 = none) */
     int32_t persist_wgs;      /* work-groups of the persistent launch (all resident) */
     int32_t persist_graph;    /* 1: the persistent launch replays from a captured graph */
+    int64_t collided_cells[4];/* cells collided per level sub-step (leaf + band + ghost, solid excluded) */
 } lbm_info;
 
 /* ---- lifecycle ------------------------------------------------------------ */
@@ -212,6 +213,28 @@ lbm_status lbm_get_links(lbm_grid *g, int64_t cap, int64_t *cell, int8_t *dir, d
 /* Block map of level l over its block lattice (nbx_l * nby_l * nbz_l int8):
  * 0 none, 1 leaf, 2 refined (covered by level l+1), 3 ghost storage. */
 lbm_status lbm_get_block_map(lbm_grid *g, int32_t level, int8_t *map);
+
+/* Host-only plan of a grid: the validation of lbm_create_grid and
+ * lbm_set_geometry, the voxelisation and the block grid of every level, as
+ * lbm_set_geometry would build them, without touching a device.  For sizing a
+ * run against device memory before allocating it. */
+typedef struct {
+    int32_t levels, block_edge;
+    int32_t lattice[4][3];        /* blocks along x, y, z of each level's box */
+    int64_t blocks[4];            /* blocks held per level (leaf + refined + ghost storage) */
+    int64_t leaf_cells[4];        /* leaf cells per level (solid included) */
+    int64_t collided_cells[4];    /* cells collided per level sub-step (leaf + band + ghost) */
+    int64_t updated_cells[4];     /* leaf fluid cells per level (what MLUPS counts) */
+    int64_t links, solid_cells;
+    int64_t pop_bytes;            /* population storage of every level in d->storage */
+} lbm_plan;
+
+/* maps may be NULL; otherwise maps[l] (may be NULL) receives level l's block
+ * map (lattice[l] product int8, values as lbm_get_block_map).  Errors as
+ * lbm_create_grid and lbm_set_geometry (LBM_E_INVALID), the message in
+ * lbm_last_error(NULL). */
+lbm_status lbm_plan_levels(const lbm_grid_desc *d, const lbm_branch *b, int32_t n_b,
+                           const lbm_refine_desc *refine, lbm_plan *out, int8_t *const *maps);
 
 /* FP64 mass sum over active cells (synchronous). */
 lbm_status lbm_mass(lbm_grid *g, double *mass);

@@ -54,6 +54,13 @@ class RefineDesc(C.Structure):
     _fields_ = [("band", C.c_int32 * 4), ("wake", C.c_int32 * 4)]
 
 
+class Plan(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("block_edge", C.c_int32), ("lattice", (C.c_int32 * 3) * 4),
+                ("blocks", C.c_int64 * 4), ("leaf_cells", C.c_int64 * 4), ("collided_cells", C.c_int64 * 4),
+                ("updated_cells", C.c_int64 * 4), ("links", C.c_int64), ("solid_cells", C.c_int64),
+                ("pop_bytes", C.c_int64)]
+
+
 class DragResult(C.Structure):
     _fields_ = [("force", C.c_double * 3), ("cd", C.c_double), ("area_x", C.c_double),
                 ("height", C.c_double), ("mass", C.c_double), ("samples", C.c_int64), ("step", C.c_int64)]
@@ -66,7 +73,7 @@ class Info(C.Structure):
                 ("omega1", C.c_double * 4), ("height", C.c_double), ("area_x", C.c_double),
                 ("nu_finest", C.c_double), ("device_bytes", C.c_size_t), ("tile_cells", C.c_int32),
                 ("threads", C.c_int32), ("occ_even", C.c_int32), ("occ_odd", C.c_int32),
-                ("persist_wgs", C.c_int32), ("persist_graph", C.c_int32)]
+                ("persist_wgs", C.c_int32), ("persist_graph", C.c_int32), ("collided_cells", C.c_int64 * 4)]
 
 
 _lib = None
@@ -98,6 +105,8 @@ def lib():
         "lbm_get_links": [_P, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int8), _dp,
                           C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
         "lbm_get_block_map": [_P, C.c_int32, C.POINTER(C.c_int8)],
+        "lbm_plan_levels": [C.POINTER(GridDesc), C.POINTER(Branch), C.c_int32, C.POINTER(RefineDesc),
+                            C.POINTER(Plan), C.POINTER(C.POINTER(C.c_int8))],
         "lbm_mass": [_P, _dp],
         "lbm_autotune": [_P, C.c_char_p],
         "lbm_save": [_P, C.c_char_p],
@@ -212,21 +221,69 @@ def collide_cell_host(f, omega1, omega2=1.0, galilean=True):
 
 # ---- grid --------------------------------------------------------------------
 
+def _make_desc(nx, ny, nz, u_in=0.05, re_h=0.0, nu=0.0, block_edge=16, levels=1, storage="fp32", drag_every=1,
+               flags=0, device=0, stream=None, turb_intensity=0.0, turb_length=0.0, turb_seed=0, turb_modes=0):
+    d = GridDesc()
+    d.nx, d.ny, d.nz = nx, ny, nz
+    d.block_edge, d.levels = block_edge, levels
+    d.u_in, d.re_h, d.nu = u_in, re_h, nu
+    d.storage = STORAGE[storage] if isinstance(storage, str) else storage
+    d.periodic_yz = 1
+    d.turb_intensity, d.turb_length, d.turb_seed, d.turb_modes = turb_intensity, turb_length, turb_seed, turb_modes
+    d.drag_every, d.flags, d.device = drag_every, flags, device
+    d.stream = stream
+    return d
+
+
+def _refine_desc(refine):
+    if refine is None:
+        return None
+    r = RefineDesc()
+    for k, v in enumerate(refine.get("band", [])):
+        r.band[k] = v
+    for k, v in enumerate(refine.get("wake", [])):
+        r.wake[k] = v
+    return r
+
+
+def plan_levels(branches, refine=None, maps=False, **desc):
+    """Host-only plan of a grid (lbm_plan_levels): per-level lattice, block
+    and cell counts, link and solid counts, population bytes, and optionally
+    the block map of every level.  desc takes the Grid arguments."""
+    if isinstance(branches, np.ndarray):
+        branches = branches_from_numpy(branches)
+    d = _make_desc(**desc)
+    r = _refine_desc(refine)
+    out = Plan()
+    L = d.levels
+    arrs = []
+    ptrs = None
+    if maps:
+        s = d.block_edge << (L - 1)
+        for l in range(L):
+            f = 1 << l
+            arrs.append(np.zeros((d.nx // s) * f * (d.ny // s) * f * (d.nz // s) * f, np.int8))
+        ptrs = (C.POINTER(C.c_int8) * 4)(*[a.ctypes.data_as(C.POINTER(C.c_int8)) for a in arrs])
+    _check(lib().lbm_plan_levels(C.byref(d), branches, len(branches), C.byref(r) if r else None, C.byref(out),
+                                 ptrs))
+    res = {"levels": out.levels, "block_edge": out.block_edge,
+           "lattice": [tuple(out.lattice[l]) for l in range(L)], "blocks": list(out.blocks[:L]),
+           "leaf_cells": list(out.leaf_cells[:L]), "collided_cells": list(out.collided_cells[:L]),
+           "updated_cells": list(out.updated_cells[:L]),
+           "links": out.links, "solid_cells": out.solid_cells, "pop_bytes": out.pop_bytes}
+    if maps:
+        res["maps"] = arrs
+    return res
+
+
 class Grid:
     """Owns one lbm_grid handle."""
 
     def __init__(self, nx, ny, nz, u_in=0.05, re_h=0.0, nu=0.0, block_edge=16, levels=1,
                  storage="fp32", drag_every=1, flags=0, device=0, stream=None,
                  turb_intensity=0.0, turb_length=0.0, turb_seed=0, turb_modes=0):
-        d = GridDesc()
-        d.nx, d.ny, d.nz = nx, ny, nz
-        d.block_edge, d.levels = block_edge, levels
-        d.u_in, d.re_h, d.nu = u_in, re_h, nu
-        d.storage = STORAGE[storage] if isinstance(storage, str) else storage
-        d.periodic_yz = 1
-        d.turb_intensity, d.turb_length, d.turb_seed, d.turb_modes = turb_intensity, turb_length, turb_seed, turb_modes
-        d.drag_every, d.flags, d.device = drag_every, flags, device
-        d.stream = stream
+        d = _make_desc(nx, ny, nz, u_in, re_h, nu, block_edge, levels, storage, drag_every, flags, device, stream,
+                       turb_intensity, turb_length, turb_seed, turb_modes)
         self.desc = d
         self.h = _P()
         _check(lib().lbm_create_grid(C.byref(d), C.byref(self.h)))
@@ -250,13 +307,7 @@ class Grid:
     def set_geometry(self, branches, refine: Optional[dict] = None):
         if isinstance(branches, np.ndarray):
             branches = branches_from_numpy(branches)
-        r = None
-        if refine is not None:
-            r = RefineDesc()
-            for k, v in enumerate(refine.get("band", [])):
-                r.band[k] = v
-            for k, v in enumerate(refine.get("wake", [])):
-                r.wake[k] = v
+        r = _refine_desc(refine)
         nbytes = C.c_size_t(0)
         _check(lib().lbm_set_geometry(self.h, branches, len(branches), C.byref(r) if r else None,
                                       C.byref(nbytes)), self.h)
@@ -291,7 +342,8 @@ class Grid:
                 "omega1": list(i.omega1), "height": i.height, "area_x": i.area_x,
                 "nu_finest": i.nu_finest, "device_bytes": i.device_bytes, "tile_cells": i.tile_cells,
                 "threads": i.threads, "occ_even": i.occ_even, "occ_odd": i.occ_odd,
-                "persist_wgs": i.persist_wgs, "persist_graph": i.persist_graph}
+                "persist_wgs": i.persist_wgs, "persist_graph": i.persist_graph,
+                "collided_cells": list(i.collided_cells)}
 
     def get_populations(self, level=0):
         nx, ny, nz = self.level_shape(level)

@@ -114,7 +114,8 @@ struct DevLevel {
     float *gbuf = nullptr;
     double om1 = 1.0;
     int64_t steps = 0;
-    int64_t updated_cells = 0;
+    int64_t updated_cells = 0;   // leaf fluid cells (the updates a level sub-step counts)
+    int64_t collided_cells = 0;  // cells collided per sub-step (leaf + band + ghost, solid excluded)
     int64_t leaf_cells = 0;
     // host mirrors
     std::vector<int> h_bxyz;          // 3 per block

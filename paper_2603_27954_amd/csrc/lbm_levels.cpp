@@ -244,6 +244,7 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
         v.h_map.assign((size_t)v.nbx * v.nby * v.nbz, 1);
         v.leaf_cells = (int64_t)d.nx * d.ny * d.nz;
         dense_tiles(v, [&](int64_t c) { return solid[(size_t)c] == 0; }, v.h_work, &v.updated_cells);
+        v.collided_cells = v.updated_cells;
         v.h_leaf = v.h_work;
         return LBM_OK;
     }
@@ -370,6 +371,7 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
         const bool finest = l == L - 1;
         v.leaf_cells = 0;
         v.updated_cells = 0;
+        v.collided_cells = 0;
         if (v.dense) {
             // level 0: collide active and band cells; leaf = active
             std::vector<uint8_t> cls((size_t)v.nx * v.ny * v.nz);
@@ -377,8 +379,7 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
                 for (int y = 0; y < v.ny; ++y)
                     for (int x = 0; x < v.nx; ++x)
                         cls[(size_t)x + (size_t)v.nx * ((size_t)y + (size_t)v.ny * z)] = (uint8_t)cell_class(l, x, y, z);
-            int64_t dummy = 0;
-            dense_tiles(v, [&](int64_t c) { return cls[c] == 1 || cls[c] == 2; }, v.h_work, &dummy);
+            dense_tiles(v, [&](int64_t c) { return cls[c] == 1 || cls[c] == 2; }, v.h_work, &v.collided_cells);
             dense_tiles(v, [&](int64_t c) { return cls[c] == 1; }, v.h_leaf, &v.updated_cells);
             v.leaf_cells = v.updated_cells;
             continue;
@@ -403,6 +404,7 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
                 }
             }
             v.updated_cells += nl;
+            v.collided_cells += nw;
             auto push = [&](std::vector<uint2> &list, const std::vector<uint32_t> &m, int cnt) {
                 if (cnt == 0)
                     return;

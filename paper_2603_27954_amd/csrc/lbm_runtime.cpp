@@ -607,39 +607,73 @@ const char *lbm_last_error(const lbm_grid *g)
     return g_thread_error.c_str();
 }
 
+// host validation of a grid description (shared by lbm_create_grid and
+// lbm_plan_levels)
+static lbm_status check_desc(const lbm_grid_desc *d, std::string *msg)
+{
+    const int B = d->block_edge;
+    if (B != 8 && B != 16)
+        return (*msg = "block_edge must be 8 or 16", LBM_E_INVALID);
+    if (d->levels < 1 || d->levels > 4)
+        return (*msg = "levels must be 1..4", LBM_E_INVALID);
+    const int unit = B << (d->levels - 1);
+    if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0 || d->nx % unit || d->ny % unit || d->nz % unit)
+        return (*msg = "nx, ny, nz must be positive multiples of block_edge << (levels-1)", LBM_E_INVALID);
+    if ((int64_t)(d->nx / unit) * (d->ny / unit) * (d->nz / unit) > (1 << 24))
+        return (*msg = "too many coarse blocks", LBM_E_INVALID);
+    if (!(d->u_in >= 0.0) || std::sqrt(3.0) * d->u_in >= 0.3)
+        return (*msg = "u_in must satisfy 0 <= sqrt(3) u_in < 0.3", LBM_E_INVALID);
+    if (!(d->nu > 0.0) && !(d->re_h > 0.0))
+        return (*msg = "need nu > 0 or re_h > 0", LBM_E_INVALID);
+    if (d->storage < 0 || d->storage > 2)
+        return (*msg = "storage must be LBM_FP32, LBM_FP16_DEV or LBM_BF16_DEV", LBM_E_INVALID);
+    if (d->periodic_yz != 1)
+        return (*msg = "only periodic lateral faces are supported (periodic_yz = 1)", LBM_E_INVALID);
+    if (d->drag_every < 0)
+        return (*msg = "drag_every must be >= 1", LBM_E_INVALID);
+    if (d->flags & LBM_F_PERSISTENT)
+        return (*msg = "LBM_F_PERSISTENT is disabled: the persistent coarse-step launch has not passed its GPU "
+                       "tests; use LBM_F_GRAPH",
+                LBM_E_INVALID);
+    if (d->turb_intensity < 0.0 || d->turb_intensity > 0.5)
+        return (*msg = "turb_intensity must be in [0, 0.5]", LBM_E_INVALID);
+    if (d->turb_intensity > 0.0 && !(d->turb_length > 0.0))
+        return (*msg = "turb_length must be > 0 with inflow turbulence", LBM_E_INVALID);
+    return LBM_OK;
+}
+
+// host validation of a branch list (shared by lbm_set_geometry and
+// lbm_plan_levels)
+static lbm_status check_branches(const lbm_grid_desc &d, const lbm_branch *b, int32_t n_b, std::string *msg)
+{
+    if (!b || n_b <= 0)
+        return (*msg = "need at least one branch", LBM_E_INVALID);
+    for (int i = 0; i < n_b; ++i) {
+        if (b[i].id != i)
+            return (*msg = "branch ids must be 0 .. n_b-1 in order", LBM_E_INVALID);
+        if (!(b[i].diameter > 0.0))
+            return (*msg = "branch diameter must be > 0", LBM_E_INVALID);
+        const double dx = b[i].p1[0] - b[i].p0[0], dy = b[i].p1[1] - b[i].p0[1], dz = b[i].p1[2] - b[i].p0[2];
+        if (!(dx * dx + dy * dy + dz * dz > 0.0))
+            return (*msg = "branch of zero length", LBM_E_INVALID);
+    }
+    const int margin = d.levels == 1 ? 2 : d.block_edge << (d.levels - 1);
+    if (!tree_fits_box(b, n_b, d.nx, d.ny, d.nz, margin))
+        return (*msg = "tree comes too close to the box faces", LBM_E_INVALID);
+    return LBM_OK;
+}
+
 lbm_status lbm_create_grid(const lbm_grid_desc *d, lbm_grid **out)
 {
     if (!d || !out)
         return fail(nullptr, LBM_E_INVALID, "null argument");
     *out = nullptr;
+    {
+        std::string msg;
+        if (check_desc(d, &msg) != LBM_OK)
+            return fail(nullptr, LBM_E_INVALID, msg);
+    }
     const int B = d->block_edge;
-    if (B != 8 && B != 16)
-        return fail(nullptr, LBM_E_INVALID, "block_edge must be 8 or 16");
-    if (d->levels < 1 || d->levels > 4)
-        return fail(nullptr, LBM_E_INVALID, "levels must be 1..4");
-    const int unit = B << (d->levels - 1);
-    if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0 || d->nx % unit || d->ny % unit || d->nz % unit)
-        return fail(nullptr, LBM_E_INVALID, "nx, ny, nz must be positive multiples of block_edge << (levels-1)");
-    if ((int64_t)(d->nx / unit) * (d->ny / unit) * (d->nz / unit) > (1 << 24))
-        return fail(nullptr, LBM_E_INVALID, "too many coarse blocks");
-    if (!(d->u_in >= 0.0) || std::sqrt(3.0) * d->u_in >= 0.3)
-        return fail(nullptr, LBM_E_INVALID, "u_in must satisfy 0 <= sqrt(3) u_in < 0.3");
-    if (!(d->nu > 0.0) && !(d->re_h > 0.0))
-        return fail(nullptr, LBM_E_INVALID, "need nu > 0 or re_h > 0");
-    if (d->storage < 0 || d->storage > 2)
-        return fail(nullptr, LBM_E_INVALID, "storage must be LBM_FP32, LBM_FP16_DEV or LBM_BF16_DEV");
-    if (d->periodic_yz != 1)
-        return fail(nullptr, LBM_E_INVALID, "only periodic lateral faces are supported (periodic_yz = 1)");
-    if (d->drag_every < 0)
-        return fail(nullptr, LBM_E_INVALID, "drag_every must be >= 1");
-    if (d->flags & LBM_F_PERSISTENT)
-        return fail(nullptr, LBM_E_INVALID,
-                    "LBM_F_PERSISTENT is disabled: the persistent coarse-step launch has not passed its GPU "
-                    "tests; use LBM_F_GRAPH");
-    if (d->turb_intensity < 0.0 || d->turb_intensity > 0.5)
-        return fail(nullptr, LBM_E_INVALID, "turb_intensity must be in [0, 0.5]");
-    if (d->turb_intensity > 0.0 && !(d->turb_length > 0.0))
-        return fail(nullptr, LBM_E_INVALID, "turb_length must be > 0 with inflow turbulence");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
         return fail(nullptr, LBM_E_DEVICE, "no HIP device available");
@@ -724,21 +758,12 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
         return fail(nullptr, LBM_E_INVALID, "null grid");
     if (g->state != 0)
         return fail(g, LBM_E_STATE, "geometry already set");
-    if (!b || n_b <= 0)
-        return fail(g, LBM_E_INVALID, "need at least one branch");
-    for (int i = 0; i < n_b; ++i) {
-        if (b[i].id != i)
-            return fail(g, LBM_E_INVALID, "branch ids must be 0 .. n_b-1 in order");
-        if (!(b[i].diameter > 0.0))
-            return fail(g, LBM_E_INVALID, "branch diameter must be > 0");
-        const double dx = b[i].p1[0] - b[i].p0[0], dy = b[i].p1[1] - b[i].p0[1], dz = b[i].p1[2] - b[i].p0[2];
-        if (!(dx * dx + dy * dy + dz * dz > 0.0))
-            return fail(g, LBM_E_INVALID, "branch of zero length");
-    }
     const lbm_grid_desc &d = g->d;
-    const int margin = g->L == 1 ? 2 : g->B << (g->L - 1);
-    if (!tree_fits_box(b, n_b, d.nx, d.ny, d.nz, margin))
-        return fail(g, LBM_E_INVALID, "tree comes too close to the box faces");
+    {
+        std::string msg;
+        if (check_branches(d, b, n_b, &msg) != LBM_OK)
+            return fail(g, LBM_E_INVALID, msg);
+    }
     if (g->L > 1 && !refine)
         return fail(g, LBM_E_INVALID, "refinement bands required when levels > 1");
     (void)hipSetDevice(d.device);
@@ -1016,6 +1041,7 @@ lbm_status lbm_get_info(const lbm_grid *g, lbm_info *out)
         out->blocks[l] = g->lv[l].nb;
         out->active_cells[l] = g->lv[l].leaf_cells;
         out->updated_cells[l] = g->lv[l].updated_cells;
+        out->collided_cells[l] = g->lv[l].collided_cells;
         out->omega1[l] = g->lv[l].om1;
     }
     out->links = g->n_links;
@@ -1190,6 +1216,50 @@ lbm_status lbm_get_links(lbm_grid *g, int64_t cap, int64_t *cell, int8_t *dir, d
         if (dir) dir[t] = g->links[t].dir;
         if (q) q[t] = g->links[t].q;
         if (branch) branch[t] = g->links[t].branch;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_plan_levels(const lbm_grid_desc *d, const lbm_branch *b, int32_t n_b, const lbm_refine_desc *refine,
+                           lbm_plan *out, int8_t *const *maps)
+{
+    if (!d || !out)
+        return fail(nullptr, LBM_E_INVALID, "null argument");
+    std::string msg;
+    if (check_desc(d, &msg) != LBM_OK || check_branches(*d, b, n_b, &msg) != LBM_OK)
+        return fail(nullptr, LBM_E_INVALID, msg);
+    if (d->levels > 1 && !refine)
+        return fail(nullptr, LBM_E_INVALID, "refinement bands required when levels > 1");
+    std::vector<uint8_t> solid;
+    std::vector<HostLink> links;
+    voxelize(b, n_b, d->nx, d->ny, d->nz, solid);
+    build_links(b, n_b, d->nx, d->ny, d->nz, solid, links);
+    std::vector<DevLevel> lv;
+    AmrPlan plan;
+    const int B = d->block_edge;
+    const lbm_status st = build_levels(*d, B, d->levels, b, n_b, refine, solid, lv, plan, &msg);
+    if (st != LBM_OK)
+        return fail(nullptr, st, msg);
+    std::memset(out, 0, sizeof *out);
+    out->levels = d->levels;
+    out->block_edge = B;
+    out->links = (int64_t)links.size();
+    for (uint8_t v : solid)
+        out->solid_cells += v != 0;
+    const size_t eb = storage_bytes(d->storage);
+    for (int l = 0; l < d->levels; ++l) {
+        const DevLevel &v = lv[l];
+        out->blocks[l] = v.nb;
+        out->leaf_cells[l] = v.leaf_cells;
+        out->collided_cells[l] = v.collided_cells;
+        out->updated_cells[l] = v.updated_cells;
+        const size_t elems = v.dense ? (size_t)v.nx * v.ny * v.nz : (size_t)(v.nb + 1) * B * B * B;
+        out->pop_bytes += (int64_t)(elems * 27 * eb);
+        out->lattice[l][0] = v.nbx;
+        out->lattice[l][1] = v.nby;
+        out->lattice[l][2] = v.nbz;
+        if (maps && maps[l])
+            std::memcpy(maps[l], v.h_map.data(), v.h_map.size());
     }
     return LBM_OK;
 }

@@ -123,3 +123,33 @@ def test_fp32_collision_matches_oracle(lt):
         assert abs(got.sum() - ref.sum()) < 2e-7
         assert np.allclose(got @ O.CVEC, ref @ O.CVEC, atol=2e-7)
     assert worst < 5e-7
+
+
+@pytest.mark.parametrize("case", [
+    dict(L=2, B=8, box=(96, 96, 96), com=(40.0, 48.0, 48.0), band=[0, 8], wake=[0, 0]),
+    dict(L=3, B=8, box=(256, 128, 128), com=(96.0, 64.0, 64.0), band=[0, 2, 0], wake=[0, 0, 0]),
+    dict(L=2, B=16, box=(128, 128, 128), com=(48.0, 64.0, 64.0), band=[0, 4], wake=[0, 0]),
+])
+def test_planned_block_maps_match_oracle(lt, case):
+    """The library's host-built block grid (lbm_plan_levels, the same builder
+    lbm_set_geometry uses) equals the oracle's, level by level."""
+    nx, ny, nz = case["box"]
+    b = O.build_tree(O.cfg1_tree_params(), 0.0, list(case["com"]))
+    refine = {"band": case["band"], "wake": case["wake"]}
+    plan = lt.plan_levels(b, refine=refine, maps=True, nx=nx, ny=ny, nz=nz, u_in=0.05, re_h=100.0,
+                          block_edge=case["B"], levels=case["L"])
+    nu = 0.05 * O.tree_height(b) / 100.0
+    sim = O.AmrSim(case["L"], case["B"], nx, ny, nz, 0.05, nu, b, case["band"], case["wake"])
+    for l in range(case["L"]):
+        assert np.array_equal(plan["maps"][l].astype(np.uint8), sim.block_map(l)), f"level {l}"
+    solid = O.voxelize(b, nx, ny, nz)
+    assert plan["solid_cells"] == int(solid.sum())
+    assert plan["links"] == len(O.links(b, solid, nx, ny, nz)["cell"])
+
+
+def test_plan_rejects_refinement_at_the_faces(lt):
+    b = O.build_tree(O.cfg1_tree_params(), 0.0, [40.0, 20.0, 32.0])
+    with pytest.raises(lt.LbmError) as e:
+        lt.plan_levels(b, refine={"band": [0, 24, 6], "wake": [0, 40, 0]}, nx=256, ny=128, nz=128, u_in=0.05,
+                       re_h=100.0, block_edge=8, levels=3)
+    assert e.value.status == lt.LBM_E_INVALID
