@@ -97,8 +97,8 @@ typedef struct {
     double nu;            /* finest-level lattice viscosity; > 0 overrides re_h */
     int32_t storage;      /* lbm_storage */
     int32_t periodic_yz;  /* must be 1: periodic lateral faces */
-    double turb_intensity; /* inlet I_u (0 = uniform inflow) */
-    double turb_length;    /* integral length of the inflow turbulence, finest cells */
+    double turb_intensity; /* inlet I_u (0 = uniform inflow); synthesis as lbm_inflow_modes */
+    double turb_length;    /* longitudinal integral length of the inflow turbulence, finest cells */
     uint64_t turb_seed;
     int32_t turb_modes;    /* number of random Fourier modes (0 -> 200) */
     int32_t drag_every;    /* finest sub-steps between force samples (>= 1) */
@@ -213,6 +213,17 @@ lbm_status lbm_get_links(lbm_grid *g, int64_t cap, int64_t *cell, int8_t *dir, d
 /* Block map of level l over its block lattice (nbx_l * nby_l * nbz_l int8):
  * 0 none, 1 leaf, 2 refined (covered by level l+1), 3 ghost storage. */
 lbm_status lbm_get_block_map(lbm_grid *g, int32_t level, int8_t *map);
+
+/* Host-only mode set of the synthetic turbulent inflow that lbm_set_geometry
+ * builds from turb_seed / turb_modes / turb_intensity / turb_length (inlet grid
+ * spacing dx = 2^(levels-1) finest cells).  Random Fourier modes with a von
+ * Karman spectrum (the paper, Sec. 4.2, fixes only the intensity I_u =
+ * u'_rms / U_inf): u'(x, t) = 2 sum_n amp_n sigma_n cos(k_n . (x - u_in t e_x)
+ * + psi_n).  out: 8 * n_modes doubles, blocks kx, ky, kz, sigma_x, sigma_y,
+ * sigma_z, psi, amp; *k_e (may be NULL) the calibrated spectrum peak
+ * parameter. */
+lbm_status lbm_inflow_modes(uint64_t seed, int32_t n_modes, double intensity, double length, double u_in,
+                            double dx, double *out, double *k_e);
 
 /* Host-only plan of a grid: the validation of lbm_create_grid and
  * lbm_set_geometry, the voxelisation and the block grid of every level, as

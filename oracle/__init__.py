@@ -4,8 +4,8 @@ TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` import this package.  The product library and
 its Python binding never import it; it shares no code with them.  Every
 function here is a thin ctypes wrapper around the plain C in this directory
-(``lbm_oracle.c``, ``geom_oracle.c``, ``amr_oracle.c``, ``turb_oracle.c``) or
-plain numpy (``mlp_oracle.py``, ``analytic_oracle.py``).
+(``lbm_oracle.c``, ``geom_oracle.c``, ``amr_oracle.c``) or plain numpy
+(``turb_oracle.py`` for the inflow turbulence).
 
 Population layout: ``f[i, cell]`` with ``i = (cx+1) + 3(cy+1) + 9(cz+1)`` and
 ``cell = x + nx*(y + ny*z)``.
@@ -376,6 +376,12 @@ class AmrSim:
     def set_f(self, l, f):
         f = np.ascontiguousarray(f, dtype=np.float64)
         lib().or_amr_set_f(self.h, l, _ptr(f))
+
+    def set_inlet_series(self, planes):
+        """planes: (n, nz0, ny0, 3) inlet ghost-plane fluctuations of level-0
+        steps 0 .. n-1 (counted from the start of the run)."""
+        self._inlet = np.ascontiguousarray(planes, dtype=np.float64)
+        lib().or_amr_set_inlet(self.h, _ptr(self._inlet), len(self._inlet))
 
     def step(self, n=1):
         lib().or_amr_step(self.h, n)

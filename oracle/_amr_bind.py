@@ -1,5 +1,5 @@
-"""ctypes signatures of the multi-level reference (amr_oracle.c) and of the
-inflow reference (turb_oracle.c).  Test infrastructure only."""
+"""ctypes signatures of the multi-level reference (amr_oracle.c).  Test
+infrastructure only."""
 import ctypes as C
 
 _dp = C.POINTER(C.c_double)
@@ -25,8 +25,6 @@ def bind(L):
         L.or_amr_force_log.restype = C.c_int64
         L.or_amr_force_log.argtypes = [C.c_void_p, _dp, C.c_int64]
         L.or_amr_branch_force.argtypes = [C.c_void_p, _dp]
+        L.or_amr_set_inlet.argtypes = [C.c_void_p, _dp, C.c_int64]
         L.or_cell_transfer.argtypes = [_dp, C.c_double, C.c_double, _dp]
         L.or_cell_rebuild.argtypes = [_dp, C.c_double, C.c_double, _dp]
-    if hasattr(L, "or_rfm_build"):
-        from . import _turb_bind
-        _turb_bind.bind(L)

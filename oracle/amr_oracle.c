@@ -92,6 +92,9 @@ typedef struct {
     double *branch_force; /* 3 * n_branch, last finest step */
     int64_t log_cap, log_n;
     int error;
+    const double *inlet; /* optional inlet fluctuation planes: plane k (3 per level-0 inlet cell, y fastest)
+                            holds u' of the ghost plane at the time of level-0 step k */
+    int64_t inlet_n;
 } or_amr;
 
 static int cxo(int i) { return i % 3 - 1; }
@@ -509,6 +512,12 @@ static void level_step(or_amr *a, int l)
                     }
                     if (l == 0 && sx < 0) {
                         double feq[Q], ug[3] = {a->u_in, 0, 0};
+                        if (a->inlet && a->steps[0] < a->inlet_n) {
+                            const double *du = a->inlet + 3 * ((size_t)a->steps[0] * ny * nz + (size_t)sy + (size_t)ny * sz);
+                            ug[0] += du[0];
+                            ug[1] += du[1];
+                            ug[2] += du[2];
+                        }
                         or_equilibrium(1.0, ug, feq);
                         val = feq[i];
                     } else if (l == 0 && sx >= nx) {
@@ -724,6 +733,15 @@ void or_amr_get_f(const or_amr *a, int l, double *out)
 void or_amr_set_f(or_amr *a, int l, const double *in)
 {
     memcpy(a->f[l], in, sizeof(double) * Q * (size_t)a->lnx[l] * a->lny[l] * a->lnz[l]);
+}
+
+/* Inlet ghost-plane fluctuations of level-0 steps 0 .. n-1 (Sec. 4.2 inflow
+ * turbulence); steps beyond n use the uniform inflow.  The array must outlive
+ * the stepping. */
+void or_amr_set_inlet(or_amr *a, const double *planes, int64_t n)
+{
+    a->inlet = planes;
+    a->inlet_n = planes ? n : 0;
 }
 
 void or_amr_step(or_amr *a, int n_coarse)

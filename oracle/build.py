@@ -9,7 +9,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["lbm_oracle.c", "geom_oracle.c", "amr_oracle.c", "turb_oracle.c"]
+SOURCES = ["lbm_oracle.c", "geom_oracle.c", "amr_oracle.c"]
 LIB = os.path.join(HERE, "liblbm_oracle.so")
 
 

@@ -105,6 +105,7 @@ def lib():
         "lbm_get_links": [_P, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int8), _dp,
                           C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
         "lbm_get_block_map": [_P, C.c_int32, C.POINTER(C.c_int8)],
+        "lbm_inflow_modes": [C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp],
         "lbm_plan_levels": [C.POINTER(GridDesc), C.POINTER(Branch), C.c_int32, C.POINTER(RefineDesc),
                             C.POINTER(Plan), C.POINTER(C.POINTER(C.c_int8))],
         "lbm_mass": [_P, _dp],
@@ -244,6 +245,17 @@ def _refine_desc(refine):
     for k, v in enumerate(refine.get("wake", [])):
         r.wake[k] = v
     return r
+
+
+def inflow_modes(seed, n_modes, intensity, length, u_in, dx):
+    """Host-built mode set of the synthetic turbulent inflow (lbm_inflow_modes):
+    dict of arrays kvec (n, 3), sigma (n, 3), psi, amp and the float k_e."""
+    out = np.empty(8 * n_modes)
+    ke = C.c_double(0.0)
+    _check(lib().lbm_inflow_modes(seed, n_modes, intensity, length, u_in, dx, _dptr(out), C.byref(ke)))
+    o = out.reshape(8, n_modes)
+    return {"kvec": o[0:3].T.copy(), "sigma": o[3:6].T.copy(), "psi": o[6].copy(), "amp": o[7].copy(),
+            "k_e": ke.value}
 
 
 def plan_levels(branches, refine=None, maps=False, **desc):

@@ -110,7 +110,7 @@ lbm_status lbm_load(lbm_grid *g, const char *path)
     g->finest_steps = h.finest_steps;
     g->samples = h.samples;
     g->ring_count = h.ring_count;
-    return grid_sync_ring_pos(g);
+    return grid_sync_device_counters(g);
 }
 
 // Host probe of the FP32 collision used by the kernels (one cell, FP64 in/out

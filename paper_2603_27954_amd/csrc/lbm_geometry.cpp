@@ -11,6 +11,7 @@
 // SplitMix64 (Steele, Lea & Flood 2014), one per child, in depth-first
 // pre-order of the children.
 #include "lbm_geometry.h"
+#include "lbm_random.h"
 
 #include <algorithm>
 #include <cmath>
@@ -31,19 +32,6 @@ inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
 struct Frame {
     V3 pos, head, left, up;
-};
-
-struct SplitMix64 {
-    uint64_t s;
-    uint64_t next()
-    {
-        s += 0x9E3779B97F4A7C15ULL;
-        uint64_t z = s;
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-        return z ^ (z >> 31);
-    }
-    double uniform() { return double(next() >> 11) * 0x1.0p-53; }
 };
 
 Frame pitch(Frame f, double deg)

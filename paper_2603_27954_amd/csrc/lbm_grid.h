@@ -47,6 +47,13 @@ struct lbm_grid {
     size_t device_bytes = 0;
     std::vector<void *> allocs;
     unsigned long long *d_ring_pos = nullptr;  // device copy of ring_count (slot of the next sample)
+    // synthetic turbulent inflow (coarsest level's inlet)
+    bool turb = false;
+    int n_modes = 0;
+    double turb_ke = 0.0;
+    double *d_modes = nullptr;             // 8 n_modes doubles
+    float *d_in_prev = nullptr, *d_in_cur = nullptr;  // 3 floats per inlet cell
+    unsigned long long *d_tick = nullptr;  // odd level-0 steps done (= level-0 steps / 2)
     // Captured coarse steps.  A coarse step's launches depend on the host
     // state only through the A-A parity of every level and the phase of the
     // force sampling, so one graph per such key is replayed, and the host
@@ -102,6 +109,7 @@ size_t grid_storage_bytes(int storage);
 int grid_timing_mark(lbm_grid *g);
 // drops every captured coarse step (launch shapes or state changed)
 void grid_graphs_clear(lbm_grid *g);
-// writes the host sample count to the device ring position (synchronous)
-lbm_status grid_sync_ring_pos(lbm_grid *g);
+// writes the host-held counters the kernels read from device memory (ring
+// position, inflow time) after the host state was restored (synchronous)
+lbm_status grid_sync_device_counters(lbm_grid *g);
 }  // namespace lbm

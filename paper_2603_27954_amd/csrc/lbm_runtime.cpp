@@ -19,6 +19,7 @@
 #include "lbm_internal.h"
 #include "lbm_levels.h"
 #include "lbm_grid.h"
+#include "lbm_inflow.h"
 
 using namespace lbm;
 
@@ -101,8 +102,8 @@ static CollideArgs collide_args(lbm_grid *g, int l)
     a.ny = v.ny;
     a.nz = v.nz;
     a.u_in = (float)g->d.u_in;
-    a.in_prev = nullptr;
-    a.in_cur = nullptr;
+    a.in_prev = (l == 0 && g->turb) ? g->d_in_prev : nullptr;
+    a.in_cur = (l == 0 && g->turb) ? g->d_in_cur : nullptr;
     a.gbuf = v.gbuf;
     return a;
 }
@@ -147,11 +148,24 @@ static Phase new_phase(PhaseKind k)
     return p;
 }
 
+// inlet planes of the coming odd level-0 step (times 2m and 2m + 1, m = tick)
+static lbm_status inflow_planes(lbm_grid *g)
+{
+    const double d0 = (double)(1 << (g->L - 1));
+    const DevLevel &v = g->lv[0];
+    HIPX(g, launch_inflow(g->d_modes, g->n_modes, g->d_tick, g->d.u_in, d0, d0, v.ny, v.nz, g->d_in_prev,
+                          g->d_in_cur, g->stream));
+    return LBM_OK;
+}
+
 static lbm_status level_collide(lbm_grid *g, int l)
 {
     DevLevel &v = g->lv[l];
     const int odd = (int)(v.steps & 1);
     CollideArgs a = collide_args(g, l);
+    const bool inflow = l == 0 && g->turb && odd;
+    if (g->rec && inflow)
+        return fail(g, LBM_E_INVALID, "turbulent inflow is not available in the persistent form");
     if (g->rec) {
         Phase p = new_phase(PH_COLLIDE);
         p.odd = odd;
@@ -162,12 +176,19 @@ static lbm_status level_collide(lbm_grid *g, int l)
             g->rec->push_back(p);
         return LBM_OK;
     }
+    if (inflow) {
+        lbm_status st = inflow_planes(g);
+        if (st != LBM_OK)
+            return st;
+    }
     const int e0 = timing_mark(g);
     HIPX(g, launch_collide(g->B, g->d.storage, odd, a, g->threads,
                            lds_for_occupancy(odd ? g->occ_odd : g->occ_even), g->stream));
     const int e1 = timing_mark(g);
     if (e0 >= 0 && e1 >= 0)
         g->ev_pairs.push_back({e0, 0});
+    if (inflow)
+        HIPX(g, launch_tick(g->d_tick, g->stream));
     return LBM_OK;
 }
 
@@ -574,13 +595,26 @@ static lbm_status check_persistent(lbm_grid *g)
     return LBM_OK;
 }
 
-static lbm_status sync_ring_pos(lbm_grid *g)
+static lbm_status sync_device_counters(lbm_grid *g)
 {
-    if (!g->d_ring_pos)
-        return LBM_OK;
-    const unsigned long long pos = (unsigned long long)g->ring_count;
     HIPX(g, hipStreamSynchronize(g->stream));
-    HIPX(g, hipMemcpy(g->d_ring_pos, &pos, sizeof pos, hipMemcpyHostToDevice));
+    if (g->d_ring_pos) {
+        const unsigned long long pos = (unsigned long long)g->ring_count;
+        HIPX(g, hipMemcpy(g->d_ring_pos, &pos, sizeof pos, hipMemcpyHostToDevice));
+    }
+    if (g->d_tick) {
+        const unsigned long long tick = (unsigned long long)(g->lv[0].steps / 2);
+        HIPX(g, hipMemcpy(g->d_tick, &tick, sizeof tick, hipMemcpyHostToDevice));
+    }
+    return LBM_OK;
+}
+
+// before reading level-0 pre-collision states at odd parity: the inlet plane
+// of the time the coming step reads
+static lbm_status prepare_inlet(lbm_grid *g)
+{
+    if (g->turb && (g->lv[0].steps & 1))
+        return inflow_planes(g);
     return LBM_OK;
 }
 
@@ -591,7 +625,7 @@ lbm_status grid_coarse_step(lbm_grid *g) { return coarse_step(g); }
 size_t grid_storage_bytes(int storage) { return storage_bytes(storage); }
 int grid_timing_mark(lbm_grid *g) { return timing_mark(g); }
 void grid_graphs_clear(lbm_grid *g) { graphs_clear(g); }
-lbm_status grid_sync_ring_pos(lbm_grid *g) { return sync_ring_pos(g); }
+lbm_status grid_sync_device_counters(lbm_grid *g) { return sync_device_counters(g); }
 }  // namespace lbm
 
 // ---------------------------------------------------------------------------
@@ -880,6 +914,22 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
         HIPX(g, hipMemsetAsync(g->d_counter, 0, sizeof(unsigned), g->stream));
         HIPX(g, hipMemsetAsync(g->d_ring_pos, 0, sizeof(unsigned long long), g->stream));
     }
+    if (g->d.turb_intensity > 0.0) {
+        InflowModes m;
+        const double d0 = (double)(1 << (g->L - 1));
+        build_inflow_modes(g->d.turb_seed, g->d.turb_modes, g->d.turb_intensity, g->d.turb_length, d.u_in, d0, m);
+        std::vector<double> packed;
+        for (const std::vector<double> *v : {&m.kx, &m.ky, &m.kz, &m.sx, &m.sy, &m.sz, &m.psi, &m.amp})
+            packed.insert(packed.end(), v->begin(), v->end());
+        const size_t plane = (size_t)3 * g->lv[0].ny * g->lv[0].nz;
+        if ((st = upload(g, &g->d_modes, packed)) != LBM_OK || (st = dalloc(g, &g->d_in_prev, plane)) != LBM_OK ||
+            (st = dalloc(g, &g->d_in_cur, plane)) != LBM_OK || (st = dalloc(g, &g->d_tick, 1)) != LBM_OK)
+            return st;
+        HIPX(g, hipMemsetAsync(g->d_tick, 0, sizeof(unsigned long long), g->stream));
+        g->n_modes = g->d.turb_modes;
+        g->turb_ke = m.k_e;
+        g->turb = true;
+    }
     {
         lbm_status st2 = dalloc(g, &g->d_abort, 1);
         if (st2 != LBM_OK)
@@ -924,6 +974,8 @@ lbm_status lbm_mass(lbm_grid *g, double *mass)
         return fail(g, LBM_E_STATE, "set_geometry first");
     if (lbm_status ps = check_persistent(g); ps != LBM_OK)
         return ps;
+    if (lbm_status pi = prepare_inlet(g); pi != LBM_OK)
+        return pi;
     double init[4] = {0.0, 1e300, -1e300, 0.0};
     HIPX(g, hipMemcpyAsync(g->d_mass, init, sizeof init, hipMemcpyHostToDevice, g->stream));
     for (int l = 0; l < g->L; ++l) {
@@ -1101,6 +1153,8 @@ lbm_status lbm_get_populations(lbm_grid *g, int32_t level, double *f)
         return fail(g, LBM_E_STATE, "set_geometry first");
     if (lbm_status ps = check_persistent(g); ps != LBM_OK)
         return ps;
+    if (lbm_status pi = prepare_inlet(g); pi != LBM_OK)
+        return pi;
     if (level < 0 || level >= g->L)
         return fail(g, LBM_E_INVALID, "level out of range");
     HIPX(g, hipStreamSynchronize(g->stream));
@@ -1217,6 +1271,22 @@ lbm_status lbm_get_links(lbm_grid *g, int64_t cap, int64_t *cell, int8_t *dir, d
         if (q) q[t] = g->links[t].q;
         if (branch) branch[t] = g->links[t].branch;
     }
+    return LBM_OK;
+}
+
+lbm_status lbm_inflow_modes(uint64_t seed, int32_t n_modes, double intensity, double length, double u_in,
+                           double dx, double *out, double *k_e)
+{
+    if (!out || n_modes <= 0 || !(intensity > 0.0) || !(length > 0.0) || !(u_in > 0.0) || !(dx > 0.0))
+        return fail(nullptr, LBM_E_INVALID, "bad inflow-mode arguments");
+    InflowModes m;
+    build_inflow_modes(seed, n_modes, intensity, length, u_in, dx, m);
+    size_t o = 0;
+    for (const std::vector<double> *v : {&m.kx, &m.ky, &m.kz, &m.sx, &m.sy, &m.sz, &m.psi, &m.amp})
+        for (double x : *v)
+            out[o++] = x;
+    if (k_e)
+        *k_e = m.k_e;
     return LBM_OK;
 }
 

@@ -160,7 +160,7 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     g->ring_count = rc;
     grid_graphs_clear(g);
     if (st == LBM_OK)
-        st = grid_sync_ring_pos(g);
+        st = grid_sync_device_counters(g);
     const Choice use = st == LBM_OK ? best : old;
     g->threads = use.threads;
     g->tile = use.tile;

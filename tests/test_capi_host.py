@@ -153,3 +153,17 @@ def test_plan_rejects_refinement_at_the_faces(lt):
         lt.plan_levels(b, refine={"band": [0, 24, 6], "wake": [0, 40, 0]}, nx=256, ny=128, nz=128, u_in=0.05,
                        re_h=100.0, block_edge=8, levels=3)
     assert e.value.status == lt.LBM_E_INVALID
+
+
+@pytest.mark.parametrize("seed,n,dx,length", [(40, 200, 4.0, 128.0), (7, 64, 1.0, 8.0)])
+def test_inflow_modes_match_oracle(lt, seed, n, dx, length):
+    """The library's host-built inflow mode set (its own generator, shells and
+    calibration) equals the oracle's built from the same seed."""
+    from oracle import turb_oracle as T
+    m = lt.inflow_modes(seed, n, 0.08, length, 0.05, dx)
+    o = T.build_modes(seed, n, 0.08, length, 0.05, dx)
+    assert abs(m["k_e"] - o.k_e) < 1e-12 * o.k_e
+    assert np.allclose(m["kvec"], o.kvec, rtol=1e-13, atol=1e-16)
+    assert np.allclose(m["sigma"], o.sigma, rtol=1e-13, atol=1e-15)
+    assert np.allclose(m["psi"], o.psi, rtol=1e-15, atol=0)
+    assert np.allclose(m["amp"], o.amp, rtol=1e-11, atol=0)
