@@ -1,0 +1,59 @@
+"""FP64 reference of the branch-wise analytic drag model.
+
+TEST INFRASTRUCTURE ONLY (imported by the tests, the smoke check and the
+benchmark's CPU leg; the product library never loads it).
+
+Paper Sec. 2.4.  Each branch is a cylinder of length L and diameter D whose
+axis makes the angle alpha with the flow direction.  Its drag is
+F_d = C_d(Re_D) (rho U^2 / 2) L D sin^3(alpha) (Eq. (2)), and the tree's
+estimate is C_D-est = sum F_d / ((rho U^2 / 2) A_x) (Eq. (4)).  The branch
+Reynolds number is Re_D = Re_H D / H.
+
+The paper fits C_d(Re) to published cylinder measurements that it does not
+print.  The curve used here is SYNTHETIC, a documented stand-in and not the
+paper's fit:
+
+    C_sub(Re)  = 1 + 10 Re^(-2/3)      (subcritical correlation of White 1991)
+    C_post(Re) = 0.25 + 0.35 / (1 + exp(-(ln Re - ln(20 Re_cr)) / 0.8))
+    w(Re)      = 1 / (1 + exp((ln Re - ln Re_cr) / 0.12))
+    C_d(Re)    = w C_sub + (1 - w) C_post
+
+The critical Reynolds number is Re_cr = 2.7e5 for uniform inflow.  With the
+trunk's D0 / H near 0.09, this places the tree's crisis near Re_H = 3e6.  For
+an inflow turbulence intensity of 8 % it is Re_cr = 1.4e4, which places the
+crisis near Re_H = 1.5e5.  The paper reports both onsets (Sec. 4.1, 4.2).
+"""
+import math
+
+import numpy as np
+
+RE_CR = {0.0: 2.7e5, 0.08: 1.4e4}
+
+
+def cylinder_cd(re, intensity=0.0):
+    re = np.asarray(re, dtype=np.float64)
+    rc = RE_CR[intensity]
+    lr = np.log(re)
+    sub = 1.0 + 10.0 * re ** (-2.0 / 3.0)
+    post = 0.25 + 0.35 / (1.0 + np.exp(-(lr - math.log(20.0 * rc)) / 0.8))
+    w = 1.0 / (1.0 + np.exp((lr - math.log(rc)) / 0.12))
+    return w * sub + (1.0 - w) * post
+
+
+def branch_geometry(b):
+    """Per branch: length L, diameter D, angle alpha to +x (radians), height of
+    the midpoint.  b: (n, 10) branch records."""
+    d = b[:, 3:6] - b[:, 0:3]
+    L = np.linalg.norm(d, axis=1)
+    cos_a = np.abs(d[:, 0]) / L
+    alpha = np.arccos(np.clip(cos_a, 0.0, 1.0))
+    zmid = 0.5 * (b[:, 2] + b[:, 5])
+    return L, b[:, 6], alpha, zmid
+
+
+def tree_cd_est(b, re_h, height, area_x, intensity=0.0):
+    """C_D-est of Eq. (4) for one tree at each Re_H in re_h (array)."""
+    L, D, alpha, _ = branch_geometry(b)
+    w = L * D * np.sin(alpha) ** 3
+    re_h = np.atleast_1d(np.asarray(re_h, dtype=np.float64))
+    return np.array([np.sum(cylinder_cd(r * D / height, intensity) * w) for r in re_h]) / area_x

@@ -1,0 +1,124 @@
+"""Pins of the surrogate oracles: the network's FP64 backpropagation against
+finite differences, the BF16 rounding against torch's conversion, Adam's first
+step in closed form, the linear regime of the network, and the analytic
+branch-wise model (paper Sec. 2.4, Eqs. (2) and (4)) in its special cases and
+in the qualitative crisis behaviour the paper reports (Sec. 4.1)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import analytic_oracle as A
+from oracle import mlp_oracle as M
+
+
+def _params(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(M.N_PARAM) * scale
+
+
+def test_parameter_count():
+    assert M.N_PARAM == 4609
+
+
+def test_bf16_rounding_matches_torch():
+    import torch
+    rng = np.random.default_rng(1)
+    x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-6, 6, 10000),
+                        [1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -9, -0.0, 65504.0]]).astype(np.float32)
+    want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(M.bf16_round(x), want)
+    # ties go to even: 1 + 2^-8 is half-way between 1 and 1 + 2^-7
+    assert M.bf16_round(np.float32(1.0 + 2.0 ** -8)) == 1.0
+    assert M.bf16_round(np.float32(1.0 + 3 * 2.0 ** -8)) == 1.0 + 2.0 ** -6
+
+
+def test_backprop_matches_finite_differences():
+    rng = np.random.default_rng(2)
+    p = _params(3)
+    X = rng.standard_normal((16, 5))
+    T = rng.standard_normal(16)
+    _, g = M.loss_grad(p, X, T, weights_bf16=False)
+    h = 1e-6
+    idx = rng.choice(M.N_PARAM, 200, replace=False)
+    fd = np.empty(len(idx))
+    for k, i in enumerate(idx):
+        e = np.zeros(M.N_PARAM)
+        e[i] = h
+        lp, _ = M.loss_grad(p + e, X, T, weights_bf16=False)
+        lm, _ = M.loss_grad(p - e, X, T, weights_bf16=False)
+        fd[k] = (lp - lm) / (2 * h)
+    # ReLU kinks: skip the (rare) parameters whose finite difference straddles one
+    ok = np.abs(fd - g[idx]) <= 1e-6 * (np.abs(g[idx]) + 1e-3)
+    assert ok.mean() > 0.97
+    assert np.median(np.abs(fd - g[idx]) / (np.abs(g[idx]) + 1e-12)) < 1e-7
+
+
+def test_rounded_weights_gradient_is_straight_through():
+    rng = np.random.default_rng(4)
+    p = _params(5)
+    X = rng.standard_normal((8, 5))
+    T = rng.standard_normal(8)
+    pr = M.unpack(p)
+    for k in ("W1", "W2", "w3"):
+        pr[k] = M.bf16_round(pr[k])
+    a = M.loss_grad(p, X, T, weights_bf16=True)
+    b = M.loss_grad(M.pack(pr), X, T, weights_bf16=False)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+def test_linear_regime_is_a_matrix_product():
+    """With every pre-activation positive the network is affine."""
+    rng = np.random.default_rng(6)
+    w = {"W1": rng.uniform(0.1, 0.5, (64, 5)), "b1": np.full(64, 1.0), "W2": rng.uniform(0.0, 0.1, (64, 64)),
+         "b2": np.full(64, 0.5), "w3": rng.standard_normal(64), "b3": np.array([0.25])}
+    X = rng.uniform(0.0, 1.0, (10, 5))
+    y, _ = M.forward(M.pack(w), X, weights_bf16=False)
+    direct = ((X @ w["W1"].T + w["b1"]) @ w["W2"].T + w["b2"]) @ w["w3"] + w["b3"][0]
+    assert np.allclose(y, direct, rtol=1e-14, atol=1e-14)
+
+
+def test_adam_first_step_moves_by_lr_times_sign():
+    g = np.array([1e-3, -2.0, 5.0, -1e-6])
+    p1, m, v = M.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=0.01, eps=1e-12)
+    assert np.allclose(p1, -0.01 * np.sign(g), rtol=1e-5)
+
+
+def test_cylinder_curve_values():
+    # subcritical: White's correlation 1 + 10 Re^(-2/3)
+    assert A.cylinder_cd(1000.0) == pytest.approx(1.1, rel=1e-6)
+    assert A.cylinder_cd(8.0) == pytest.approx(3.5, rel=1e-6)
+    # crisis: post-critical values well below the subcritical plateau
+    assert A.cylinder_cd(2e6) < 0.5 < A.cylinder_cd(1e5)
+    assert A.cylinder_cd(3e4, 0.08) < 0.5 < A.cylinder_cd(3e4, 0.0)
+
+
+def test_single_normal_cylinder_reduces_to_its_drag_coefficient():
+    """Eq. (4) with one branch normal to the flow and A_x = L D: C_D-est =
+    C_d(Re_D); inclined by alpha it scales with sin^3(alpha); along the flow
+    it vanishes."""
+    L, D, H = 10.0, 1.0, 10.0
+    for a_deg, fac in ((90.0, 1.0), (60.0, math.sin(math.radians(60.0)) ** 3), (0.0, 0.0)):
+        a = math.radians(a_deg)
+        b = np.array([[0.0, 0.0, 0.0, L * math.cos(a), 0.0, L * math.sin(a), D, 0, -1, 0]])
+        c = A.tree_cd_est(b, [1e4, 1e6], H, L * D)
+        want = A.cylinder_cd(np.array([1e4, 1e6]) * D / H) * fac
+        assert np.allclose(c, want, rtol=1e-12, atol=1e-15)
+
+
+def test_crisis_of_the_paper_trees_starts_near_3e6_and_softens_with_n():
+    """The paper finds the crisis near Re_H ~ 3e6 for every n and a less steep
+    drop as the number of generations n grows (Sec. 4.1).  Onset here: the
+    first Re_H where C_D-est falls 10 % below its value at Re_H = 1e5."""
+    re = 10.0 ** np.linspace(4, 9, 201)
+    slopes = []
+    for n in (4, 6, 8):
+        b = O.tree_generate(O.paper_tree_params(n))
+        c = A.tree_cd_est(b, re, O.tree_height(b), 1.0)
+        ref = c[np.searchsorted(re, 1e5)]
+        onset = re[np.argmax((re > 1e5) & (c < 0.9 * ref))]
+        assert 1e6 < onset < 1e7
+        s = np.diff(np.log(c)) / np.diff(np.log(re))
+        slopes.append(-s.min())
+    assert slopes[0] > slopes[1] > slopes[2]
