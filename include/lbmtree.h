@@ -214,6 +214,48 @@ lbm_status lbm_get_links(lbm_grid *g, int64_t cap, int64_t *cell, int8_t *dir, d
  * 0 none, 1 leaf, 2 refined (covered by level l+1), 3 ghost storage. */
 lbm_status lbm_get_block_map(lbm_grid *g, int32_t level, int8_t *map);
 
+/* ---- learned per-branch drag surrogate ---------------------------------------
+ * A network stands in for the branch-wise drag-coefficient lookup of the
+ * analytic model (paper Sec. 2.4, Eq. (2)): 5 inputs (log10 Re_D, inclination
+ * alpha in degrees, generation, inflow intensity I_u, midpoint height / H) ->
+ * 64 ReLU -> 64 ReLU -> 1 output, the branch force coefficient
+ * F_x / ((rho U^2 / 2) L D).  Parameters, 4609 floats, packed as W1 (64 x 5,
+ * row-major, out x in), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3 (1).
+ * Weights are used in BF16 (rounded to nearest even from an FP32 master copy),
+ * biases in FP32, accumulation in FP32; inference runs on the matrix cores
+ * with BF16 operands.  Features are standardised with x_mean / x_std inside
+ * the network and the output is y_mean + y_std * (network output).  The loss
+ * is the mean square error on standardised targets; the optimiser is Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).  All array arguments
+ * named x, t, y are device pointers (rows of 5 floats for x); host arrays are
+ * said so.  One handle per host thread; calls are ordered on the handle's
+ * stream and return after their work completed. */
+typedef struct lbm_mlp lbm_mlp;
+
+/* He-uniform hidden weights, Glorot-uniform output weights and zero biases
+ * drawn from SplitMix64(seed); stream NULL -> the handle owns one. */
+lbm_status lbm_mlp_create(uint64_t seed, int32_t device, void *stream, lbm_mlp **out);
+void lbm_mlp_destroy(lbm_mlp *m);
+/* FP32 master parameters to / from host arrays of 4609 floats; setting them
+ * also resets the optimiser state. */
+lbm_status lbm_mlp_get_params(lbm_mlp *m, float *params);
+lbm_status lbm_mlp_set_params(lbm_mlp *m, const float *params);
+/* feature and target standardisation (host arrays of 5; scales > 0) */
+lbm_status lbm_mlp_set_scaling(lbm_mlp *m, const float *x_mean, const float *x_std, float y_mean, float y_std);
+/* gradient (host, 4609) and loss (host, may be NULL) of the mean-square loss
+ * over n samples x (n x 5) with raw targets t (n); deterministic */
+lbm_status lbm_mlp_grad(lbm_mlp *m, const float *x, const float *t, int64_t n, float *grad, float *loss);
+/* one Adam step with a host gradient (4609) */
+lbm_status lbm_mlp_adam_step(lbm_mlp *m, const float *grad, float lr);
+/* epochs over n samples in shuffled mini-batches (Fisher-Yates from
+ * SplitMix64(seed + epoch)); learning rate lr for the first 70 % of the
+ * epochs, lr / 10 after; loss_per_epoch (host, epochs floats, may be NULL)
+ * receives the full-data loss after each epoch */
+lbm_status lbm_mlp_train(lbm_mlp *m, const float *x, const float *t, int64_t n, int32_t epochs, int32_t batch,
+                         float lr, uint64_t seed, float *loss_per_epoch);
+/* y (n floats, output units) of n rows of raw features x */
+lbm_status lbm_mlp_predict(lbm_mlp *m, const float *x, int64_t n, float *y);
+
 /* Host-only mode set of the synthetic turbulent inflow that lbm_set_geometry
  * builds from turb_seed / turb_modes / turb_intensity / turb_length (inlet grid
  * spacing dx = 2^(levels-1) finest cells).  Random Fourier modes with a von

@@ -105,6 +105,15 @@ def lib():
         "lbm_get_links": [_P, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int8), _dp,
                           C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
         "lbm_get_block_map": [_P, C.c_int32, C.POINTER(C.c_int8)],
+        "lbm_mlp_create": [C.c_uint64, C.c_int32, _P, C.POINTER(_P)],
+        "lbm_mlp_get_params": [_P, C.POINTER(C.c_float)],
+        "lbm_mlp_set_params": [_P, C.POINTER(C.c_float)],
+        "lbm_mlp_set_scaling": [_P, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_float, C.c_float],
+        "lbm_mlp_grad": [_P, _P, _P, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)],
+        "lbm_mlp_adam_step": [_P, C.POINTER(C.c_float), C.c_float],
+        "lbm_mlp_train": [_P, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64,
+                          C.POINTER(C.c_float)],
+        "lbm_mlp_predict": [_P, _P, C.c_int64, _P],
         "lbm_inflow_modes": [C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp],
         "lbm_plan_levels": [C.POINTER(GridDesc), C.POINTER(Branch), C.c_int32, C.POINTER(RefineDesc),
                             C.POINTER(Plan), C.POINTER(C.POINTER(C.c_int8))],
@@ -125,6 +134,8 @@ def lib():
         fn.restype = C.c_int
     L.lbm_destroy_grid.argtypes = [_P]
     L.lbm_destroy_grid.restype = None
+    L.lbm_mlp_destroy.argtypes = [_P]
+    L.lbm_mlp_destroy.restype = None
     L.lbm_last_error.argtypes = [_P]
     L.lbm_last_error.restype = C.c_char_p
     _lib = L
@@ -245,6 +256,72 @@ def _refine_desc(refine):
     for k, v in enumerate(refine.get("wake", [])):
         r.wake[k] = v
     return r
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Mlp:
+    """Owns one lbm_mlp handle (the per-branch drag surrogate network).  Device
+    arrays are torch CUDA tensors (float32, contiguous); the library computes on
+    them in place of copies."""
+
+    N_PARAM = 4609
+
+    def __init__(self, seed=0, device=0, stream=None):
+        self.h = _P()
+        _check(lib().lbm_mlp_create(seed, device, stream, C.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            lib().lbm_mlp_destroy(self.h)
+            self.h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        p = np.empty(self.N_PARAM, np.float32)
+        _check(lib().lbm_mlp_get_params(self.h, _fptr(p)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(lib().lbm_mlp_set_params(self.h, _fptr(p)))
+
+    def set_scaling(self, x_mean, x_std, y_mean, y_std):
+        xm = np.ascontiguousarray(x_mean, dtype=np.float32)
+        xs = np.ascontiguousarray(x_std, dtype=np.float32)
+        _check(lib().lbm_mlp_set_scaling(self.h, _fptr(xm), _fptr(xs), float(y_mean), float(y_std)))
+
+    @staticmethod
+    def _dev(a):
+        assert a.is_cuda and a.dtype.is_floating_point and a.is_contiguous()
+        return C.c_void_p(a.data_ptr())
+
+    def grad(self, x, t):
+        g = np.empty(self.N_PARAM, np.float32)
+        loss = C.c_float(0.0)
+        _check(lib().lbm_mlp_grad(self.h, self._dev(x), self._dev(t), x.shape[0], _fptr(g), C.byref(loss)))
+        return g, loss.value
+
+    def adam_step(self, grad, lr):
+        g = np.ascontiguousarray(grad, dtype=np.float32)
+        _check(lib().lbm_mlp_adam_step(self.h, _fptr(g), float(lr)))
+
+    def train(self, x, t, epochs, batch=256, lr=1e-3, seed=0):
+        losses = np.empty(epochs, np.float32)
+        _check(lib().lbm_mlp_train(self.h, self._dev(x), self._dev(t), x.shape[0], epochs, batch, float(lr), seed,
+                                   _fptr(losses)))
+        return losses
+
+    def predict(self, x, out):
+        _check(lib().lbm_mlp_predict(self.h, self._dev(x), x.shape[0], self._dev(out)))
+        return out
 
 
 def inflow_modes(seed, n_modes, intensity, length, u_in, dx):

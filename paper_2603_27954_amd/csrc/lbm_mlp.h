@@ -1,0 +1,56 @@
+// Per-branch drag surrogate network (5-64-64-1, ReLU) on the device.  Internal.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int MLP_IN = 5, MLP_H = 64;
+// packed parameter offsets: W1 (64 x 5), b1, W2 (64 x 64), b2, w3, b3
+constexpr int MLP_W1 = 0, MLP_B1 = 320, MLP_W2 = 384, MLP_B2 = 4480, MLP_W3 = 4544, MLP_B3 = 4608;
+constexpr int MLP_NPARAM = 4609;
+constexpr int MLP_CHUNK = 32;           // samples per work-group of the gradient kernel
+constexpr int MLP_PSTRIDE = MLP_NPARAM + 1;  // partial sums: parameters, then the loss
+
+struct MlpDev {
+    float *master;      // FP32 master parameters
+    float *wr;          // parameters as the kernels use them (weights rounded to BF16)
+    uint16_t *w1b;      // BF16 bits of W1, padded to 64 x 8
+    uint16_t *w2b;      // BF16 bits of W2, 64 x 64
+    float *m, *v;       // Adam moments
+    float *grad;        // reduced gradient (+ loss at MLP_NPARAM)
+    float *partial;     // per-chunk partial sums, MLP_PSTRIDE each
+    float *sc;          // x_mean[5], x_std[5], y_mean, y_std
+};
+
+// Gradient of the mean-square loss over the batch samples idx[base ..
+// base + count) (idx may be null: samples base ..), on targets standardised
+// with y_mean / y_std, normalised by n_norm; per-chunk partial sums.
+hipError_t launch_mlp_grad(const MlpDev &d, const float *x, const float *t, const int32_t *idx, int64_t base,
+                           int count, int n_norm, hipStream_t s);
+// grad = sum of the partial sums of nchunks chunks, in chunk order
+hipError_t launch_mlp_reduce(const MlpDev &d, int nchunks, hipStream_t s);
+// one Adam step on grad; bc1 = 1 - beta1^t, bc2 = 1 - beta2^t; refreshes wr, w1b, w2b
+hipError_t launch_mlp_adam(const MlpDev &d, float lr, float beta1, float beta2, float eps, float bc1, float bc2,
+                           hipStream_t s);
+// refreshes wr, w1b, w2b from master (after parameters are set)
+hipError_t launch_mlp_round(const MlpDev &d, hipStream_t s);
+// y = network(x) for n rows of raw features, in output units (matrix cores, BF16 operands)
+hipError_t launch_mlp_predict(const MlpDev &d, const float *x, int64_t n, float *y, hipStream_t s);
+
+// Branch-wise drag sums of many trees at many Re_H (see lbm_surrogate_sweep).
+struct SweepArgs {
+    const float *feat;     // per branch: lgd (log10 D/H), alpha (deg), generation, zmid / H, L D / H^2
+    const int64_t *tree_start;  // n_trees + 1 branch offsets
+    int n_trees;
+    const float *lg_re;    // log10 Re_H values
+    int n_re;
+    float intensity;
+    float lg_lo, lg_hi;    // training envelope of log10 Re_D
+    float re_cr;           // critical Re_D of the cylinder curve for this intensity
+    const float *area;     // per tree A_x / H^2
+    float *cd;             // n_trees x n_re
+};
+hipError_t launch_tree_sweep(const MlpDev &d, const SweepArgs &a, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,348 @@
+// Kernels of the per-branch drag surrogate (5-64-64-1 ReLU network).
+//
+// Precision: FP32 master parameters; the kernels use the weights rounded to
+// BF16 (ties to even) and FP32 biases, and accumulate in FP32.  Training keeps
+// activations in FP32.  Inference runs on the matrix cores with BF16 operands
+// (scaled features and first-layer activations rounded to BF16) and FP32
+// accumulators.
+//
+// Training is deterministic: each work-group sums the gradient of a fixed
+// chunk of samples in a fixed order, and the chunks are added in chunk order.
+//
+// Inference maps 32 samples onto the N dimension of the 32x32x8 BF16 MFMA, with
+// neurons on M.  The 16 accumulator registers of lane l hold rows
+// 8 (i / 4) + 4 (l / 32) + (i % 4) of column l % 32.  That is exactly the B
+// operand (k = 4 (l / 32) + j, column l % 32) of the next layer's k-steps, so
+// the hidden activations pass from layer to layer without leaving the lane.
+#include "lbm_mlp.h"
+
+#include <algorithm>
+
+namespace lbm {
+
+namespace {
+
+__device__ __forceinline__ uint32_t bf16_bits(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ float bf16_round(float x) { return __uint_as_float(bf16_bits(x) << 16); }
+
+__device__ __forceinline__ bool is_weight(int p)
+{
+    return (p >= MLP_W1 && p < MLP_B1) || (p >= MLP_W2 && p < MLP_B2) || (p >= MLP_W3 && p < MLP_B3);
+}
+
+// ---------------------------------------------------------------------------
+// training: per-chunk gradient (32 samples, 8 threads per sample)
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_mlp_grad(const float *wr, const float *sc, const float *x, const float *t,
+                                                  const int32_t *idx, int64_t base, int count, int n_norm,
+                                                  float *partial)
+{
+    constexpr int S = MLP_CHUNK, H = MLP_H;
+    __shared__ float sW2[H * H];
+    __shared__ float sH1[S * H], sH2[S * H], sD2[S * H], sD1[S * H];
+    __shared__ float sX[S * MLP_IN], sY[S], sT[S], sDY[S], sYp[S * 8];
+    const int tid = threadIdx.x;
+    const int c0 = blockIdx.x * S;
+    const int ns = min(S, count - c0);
+    for (int i = tid; i < H * H; i += 256)
+        sW2[i] = wr[MLP_W2 + i];
+    for (int i = tid; i < S * MLP_IN; i += 256) {
+        const int s = i / MLP_IN, k = i - s * MLP_IN;
+        float v = 0.0f;
+        if (s < ns) {
+            const int64_t row = idx ? (int64_t)idx[base + c0 + s] : base + c0 + s;
+            v = (x[row * MLP_IN + k] - sc[k]) / sc[MLP_IN + k];
+        }
+        sX[i] = v;
+    }
+    if (tid < S) {
+        float v = 0.0f;
+        if (tid < ns) {
+            const int64_t row = idx ? (int64_t)idx[base + c0 + tid] : base + c0 + tid;
+            v = (t[row] - sc[10]) / sc[11];
+        }
+        sT[tid] = v;
+    }
+    __syncthreads();
+    const int s = tid >> 3, part = tid & 7;  // sample, group of 8 hidden units
+    const bool live = s < ns;
+    // layer 1
+    for (int u = part * 8; u < part * 8 + 8; ++u) {
+        float z = wr[MLP_B1 + u];
+        for (int k = 0; k < MLP_IN; ++k)
+            z = fmaf(wr[MLP_W1 + u * MLP_IN + k], sX[s * MLP_IN + k], z);
+        sH1[s * H + u] = z > 0.0f ? z : 0.0f;
+    }
+    __syncthreads();
+    // layer 2 and the output
+    float yp = 0.0f;
+    for (int u = part * 8; u < part * 8 + 8; ++u) {
+        float z = wr[MLP_B2 + u];
+        for (int i = 0; i < H; ++i)
+            z = fmaf(sW2[u * H + i], sH1[s * H + i], z);
+        const float h = z > 0.0f ? z : 0.0f;
+        sH2[s * H + u] = h;
+        yp = fmaf(wr[MLP_W3 + u], h, yp);
+    }
+    sYp[s * 8 + part] = yp;
+    __syncthreads();
+    if (tid < S) {
+        float y = wr[MLP_B3];
+        for (int q = 0; q < 8; ++q)
+            y += sYp[tid * 8 + q];
+        sY[tid] = y;
+        sDY[tid] = tid < ns ? 2.0f * (y - sT[tid]) / (float)n_norm : 0.0f;
+    }
+    __syncthreads();
+    // backward through layer 2
+    for (int u = part * 8; u < part * 8 + 8; ++u)
+        sD2[s * H + u] = (live && sH2[s * H + u] > 0.0f) ? sDY[s] * wr[MLP_W3 + u] : 0.0f;
+    __syncthreads();
+    for (int i = part * 8; i < part * 8 + 8; ++i) {
+        float d = 0.0f;
+        for (int u = 0; u < H; ++u)
+            d = fmaf(sW2[u * H + i], sD2[s * H + u], d);
+        sD1[s * H + i] = sH1[s * H + i] > 0.0f ? d : 0.0f;
+    }
+    __syncthreads();
+    // parameter gradients of this chunk (sums over samples in order)
+    float *out = partial + (size_t)blockIdx.x * MLP_PSTRIDE;
+    {
+        const int u = tid >> 2, i0 = (tid & 3) * 16;
+        for (int i = i0; i < i0 + 16; ++i) {
+            float g = 0.0f;
+            for (int q = 0; q < S; ++q)
+                g = fmaf(sD2[q * H + u], sH1[q * H + i], g);
+            out[MLP_W2 + u * H + i] = g;
+        }
+    }
+    for (int p = tid; p < 320 + 64 + 64 + 64 + 1 + 1; p += 256) {
+        float g = 0.0f;
+        if (p < 320) {  // W1
+            const int u = p / MLP_IN, k = p - u * MLP_IN;
+            for (int q = 0; q < S; ++q)
+                g = fmaf(sD1[q * H + u], sX[q * MLP_IN + k], g);
+            out[MLP_W1 + p] = g;
+        } else if (p < 384) {  // b1
+            const int u = p - 320;
+            for (int q = 0; q < S; ++q)
+                g += sD1[q * H + u];
+            out[MLP_B1 + u] = g;
+        } else if (p < 448) {  // b2
+            const int u = p - 384;
+            for (int q = 0; q < S; ++q)
+                g += sD2[q * H + u];
+            out[MLP_B2 + u] = g;
+        } else if (p < 512) {  // w3
+            const int u = p - 448;
+            for (int q = 0; q < S; ++q)
+                g = fmaf(sDY[q], sH2[q * H + u], g);
+            out[MLP_W3 + u] = g;
+        } else if (p == 512) {  // b3
+            for (int q = 0; q < S; ++q)
+                g += sDY[q];
+            out[MLP_B3] = g;
+        } else {  // loss
+            for (int q = 0; q < ns; ++q) {
+                const float r = sY[q] - sT[q];
+                g = fmaf(r, r, g);
+            }
+            out[MLP_NPARAM] = g / (float)n_norm;
+        }
+    }
+}
+
+__global__ void k_mlp_reduce(const float *partial, int nchunks, float *grad)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MLP_PSTRIDE)
+        return;
+    float g = 0.0f;
+    for (int c = 0; c < nchunks; ++c)
+        g += partial[(size_t)c * MLP_PSTRIDE + p];
+    grad[p] = g;
+}
+
+__device__ __forceinline__ void store_param(const MlpDev &d, int p, float v)
+{
+    d.master[p] = v;
+    const float r = is_weight(p) ? bf16_round(v) : v;
+    d.wr[p] = r;
+    if (p >= MLP_W1 && p < MLP_B1) {
+        const int u = (p - MLP_W1) / MLP_IN, k = (p - MLP_W1) - u * MLP_IN;
+        d.w1b[u * 8 + k] = (uint16_t)bf16_bits(v);
+    } else if (p >= MLP_W2 && p < MLP_B2) {
+        d.w2b[p - MLP_W2] = (uint16_t)bf16_bits(v);
+    }
+}
+
+__global__ void k_mlp_adam(MlpDev d, float lr, float beta1, float beta2, float eps, float bc1, float bc2)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MLP_NPARAM)
+        return;
+    const float g = d.grad[p];
+    const float m = beta1 * d.m[p] + (1.0f - beta1) * g;
+    const float v = beta2 * d.v[p] + (1.0f - beta2) * g * g;
+    d.m[p] = m;
+    d.v[p] = v;
+    const float mh = m / bc1, vh = v / bc2;
+    store_param(d, p, d.master[p] - lr * mh / (sqrtf(vh) + eps));
+}
+
+__global__ void k_mlp_round(MlpDev d)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < MLP_NPARAM)
+        store_param(d, p, d.master[p]);
+    if (p < 64 * 3)  // padding columns 5..7 of W1
+        d.w1b[(p / 3) * 8 + 5 + p % 3] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// inference on the matrix cores
+// ---------------------------------------------------------------------------
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int acc_row(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
+
+// Network weights held in registers by one wave (A operands) and the biases
+// and output weights in LDS.
+struct MlpRegs {
+    bf16x4 a1[2], a2[2][8];
+};
+
+__device__ __forceinline__ void load_regs(const MlpDev &d, MlpRegs &r, int lane)
+{
+    const int m = lane & 31, kh = 4 * (lane >> 5);
+    for (int t = 0; t < 2; ++t) {
+        r.a1[t] = *reinterpret_cast<const bf16x4 *>(d.w1b + (32 * t + m) * 8 + kh);
+        for (int s = 0; s < 8; ++s)
+            r.a2[t][s] = *reinterpret_cast<const bf16x4 *>(d.w2b + (32 * t + m) * 64 + 8 * s + kh);
+    }
+}
+
+// y (scaled output units, before b3) of the sample of column lane % 32, given
+// its scaled features in b1 (B operand of the first layer); sb = b1[64],
+// b2[64], w3[64] in LDS.  Both lanes of a column return the same value.
+__device__ __forceinline__ float mlp_tile(const MlpRegs &r, bf16x4 b1, const float *sb, int lane)
+{
+    f32x16 c1[2];
+    for (int t = 0; t < 2; ++t) {
+        for (int i = 0; i < 16; ++i)
+            c1[t][i] = sb[32 * t + acc_row(i, lane)];
+        c1[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(r.a1[t], b1, c1[t], 0, 0, 0);
+    }
+    bf16x4 b2[8];
+    for (int t = 0; t < 2; ++t)
+        for (int q = 0; q < 4; ++q)
+            for (int j = 0; j < 4; ++j) {
+                const float h = fmaxf(c1[t][4 * q + j], 0.0f);
+                b2[4 * t + q][j] = (short)bf16_bits(h);
+            }
+    float y = 0.0f;
+    for (int t = 0; t < 2; ++t) {
+        f32x16 c2;
+        for (int i = 0; i < 16; ++i)
+            c2[i] = sb[64 + 32 * t + acc_row(i, lane)];
+        for (int s = 0; s < 8; ++s)
+            c2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(r.a2[t][s], b2[s], c2, 0, 0, 0);
+        for (int i = 0; i < 16; ++i)
+            y = fmaf(sb[128 + 32 * t + acc_row(i, lane)], fmaxf(c2[i], 0.0f), y);
+    }
+    return y + __shfl_xor(y, 32, 64);
+}
+
+__device__ __forceinline__ void load_bias(const MlpDev &d, float *sb)
+{
+    for (int i = threadIdx.x; i < 192; i += blockDim.x)
+        sb[i] = i < 64 ? d.wr[MLP_B1 + i] : (i < 128 ? d.wr[MLP_B2 + i - 64] : d.wr[MLP_W3 + i - 128]);
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_mlp_predict(MlpDev d, const float *x, int64_t n, float *y)
+{
+    __shared__ float sb[192];
+    load_bias(d, sb);
+    const int lane = threadIdx.x & 63;
+    MlpRegs r;
+    load_regs(d, r, lane);
+    float mean[MLP_IN], inv[MLP_IN];
+    for (int k = 0; k < MLP_IN; ++k) {
+        mean[k] = d.sc[k];
+        inv[k] = 1.0f / d.sc[MLP_IN + k];
+    }
+    const float b3 = d.wr[MLP_B3], ym = d.sc[10], ys = d.sc[11];
+    const int64_t tiles = (n + 31) / 32;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t tile = wave; tile < tiles; tile += waves) {
+        const int64_t row = tile * 32 + (lane & 31);
+        bf16x4 b1;
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * (lane >> 5) + j;
+            float v = 0.0f;
+            if (k < MLP_IN && row < n)
+                v = (x[row * MLP_IN + k] - mean[k]) * inv[k];
+            b1[j] = (short)bf16_bits(v);
+        }
+        const float out = mlp_tile(r, b1, sb, lane);
+        if (lane < 32 && row < n)
+            y[row] = (out + b3) * ys + ym;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_mlp_grad(const MlpDev &d, const float *x, const float *t, const int32_t *idx, int64_t base,
+                           int count, int n_norm, hipStream_t s)
+{
+    if (count <= 0)
+        return hipSuccess;
+    const int chunks = (count + MLP_CHUNK - 1) / MLP_CHUNK;
+    hipLaunchKernelGGL(k_mlp_grad, dim3(chunks), dim3(256), 0, s, d.wr, d.sc, x, t, idx, base, count, n_norm,
+                       d.partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_reduce(const MlpDev &d, int nchunks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_PSTRIDE + 255) / 256), dim3(256), 0, s, d.partial, nchunks, d.grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(const MlpDev &d, float lr, float beta1, float beta2, float eps, float bc1, float bc2,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, d, lr, beta1, beta2, eps, bc1,
+                       bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_round(const MlpDev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mlp_round, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_predict(const MlpDev &d, const float *x, int64_t n, float *y, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const int64_t tiles = (n + 31) / 32;
+    const int64_t blocks = std::min<int64_t>((tiles + 3) / 4, 8192);
+    hipLaunchKernelGGL(k_mlp_predict, dim3((unsigned)blocks), dim3(256), 0, s, d, x, n, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_sweep(const MlpDev &, const SweepArgs &, hipStream_t) { return hipErrorNotSupported; }
+
+}  // namespace lbm

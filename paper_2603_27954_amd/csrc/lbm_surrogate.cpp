@@ -1,0 +1,297 @@
+// Host side of the per-branch drag surrogate (C ABI in include/lbmtree.h):
+// parameter initialisation, training loop, inference and the branch-wise drag
+// sweep over many trees.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbmtree.h"
+#include "lbm_grid.h"
+#include "lbm_mlp.h"
+#include "lbm_random.h"
+
+using namespace lbm;
+
+struct lbm_mlp {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    MlpDev d{};
+    int chunk_cap = 0;        // partial-sum capacity in chunks
+    int32_t *idx = nullptr;   // training permutation
+    int64_t idx_cap = 0;
+    int64_t adam_t = 0;
+    std::vector<void *> allocs;
+
+    ~lbm_mlp()
+    {
+        for (void *p : allocs)
+            (void)hipFree(p);
+        if (idx)
+            (void)hipFree(idx);
+        if (own_stream && stream)
+            (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+
+lbm_status mfail(lbm_status st, const std::string &msg) { return grid_fail(nullptr, st, msg); }
+
+#define MHIP(call)                                                                             \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return mfail(LBM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+template <typename T>
+lbm_status malloc_dev(lbm_mlp *m, T **p, size_t count)
+{
+    void *q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess)
+        return mfail(LBM_E_NOMEM, "hipMalloc failed");
+    m->allocs.push_back(q);
+    *p = (T *)q;
+    return LBM_OK;
+}
+
+lbm_status ensure_chunks(lbm_mlp *m, int chunks)
+{
+    if (chunks <= m->chunk_cap)
+        return LBM_OK;
+    float *p = nullptr;
+    if (hipMalloc(&p, sizeof(float) * (size_t)chunks * MLP_PSTRIDE) != hipSuccess)
+        return mfail(LBM_E_NOMEM, "hipMalloc of the gradient partials failed");
+    auto it = std::find(m->allocs.begin(), m->allocs.end(), (void *)m->d.partial);
+    if (it != m->allocs.end()) {
+        (void)hipFree(*it);
+        m->allocs.erase(it);
+    }
+    m->allocs.push_back(p);
+    m->d.partial = p;
+    m->chunk_cap = chunks;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_mlp_create(uint64_t seed, int32_t device, void *stream, lbm_mlp **out)
+{
+    if (!out)
+        return mfail(LBM_E_INVALID, "null argument");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return mfail(LBM_E_DEVICE, "no HIP device available");
+    if (device < 0 || device >= ndev)
+        return mfail(LBM_E_INVALID, "device ordinal out of range");
+    MHIP(hipSetDevice(device));
+    lbm_mlp *m = new lbm_mlp();
+    m->device = device;
+    if (stream) {
+        m->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete m;
+            return mfail(LBM_E_DEVICE, "hipStreamCreate failed");
+        }
+        m->own_stream = true;
+    }
+    lbm_status st;
+    if ((st = malloc_dev(m, &m->d.master, MLP_NPARAM)) != LBM_OK || (st = malloc_dev(m, &m->d.wr, MLP_NPARAM)) != LBM_OK ||
+        (st = malloc_dev(m, &m->d.w1b, 64 * 8)) != LBM_OK || (st = malloc_dev(m, &m->d.w2b, 64 * 64)) != LBM_OK ||
+        (st = malloc_dev(m, &m->d.m, MLP_NPARAM)) != LBM_OK || (st = malloc_dev(m, &m->d.v, MLP_NPARAM)) != LBM_OK ||
+        (st = malloc_dev(m, &m->d.grad, MLP_PSTRIDE)) != LBM_OK || (st = malloc_dev(m, &m->d.sc, 12)) != LBM_OK ||
+        (st = ensure_chunks(m, 64)) != LBM_OK) {
+        delete m;
+        return st;
+    }
+    // He-uniform weights for the ReLU layers, Glorot-uniform output weights,
+    // zero biases; draws from SplitMix64(seed) in parameter order
+    std::vector<float> p(MLP_NPARAM, 0.0f);
+    SplitMix64 rng{seed};
+    auto fill = [&](int off, int count, double bound) {
+        for (int i = 0; i < count; ++i)
+            p[off + i] = (float)((2.0 * rng.uniform() - 1.0) * bound);
+    };
+    fill(MLP_W1, 320, std::sqrt(6.0 / MLP_IN));
+    fill(MLP_W2, 4096, std::sqrt(6.0 / MLP_H));
+    fill(MLP_W3, 64, std::sqrt(6.0 / (MLP_H + 1)));
+    const float sc[12] = {0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 0, 1};
+    hipError_t e = hipMemcpy(m->d.master, p.data(), sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(m->d.sc, sc, sizeof sc, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(m->d.w1b, 0, sizeof(uint16_t) * 64 * 8, m->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(m->d.m, 0, sizeof(float) * MLP_NPARAM, m->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(m->d.v, 0, sizeof(float) * MLP_NPARAM, m->stream);
+    if (e == hipSuccess)
+        e = launch_mlp_round(m->d, m->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) {
+        delete m;
+        return mfail(LBM_E_DEVICE, std::string("surrogate set-up: ") + hipGetErrorString(e));
+    }
+    *out = m;
+    return LBM_OK;
+}
+
+void lbm_mlp_destroy(lbm_mlp *m) { delete m; }
+
+lbm_status lbm_mlp_get_params(lbm_mlp *m, float *params)
+{
+    if (!m || !params)
+        return mfail(LBM_E_INVALID, "null argument");
+    MHIP(hipStreamSynchronize(m->stream));
+    MHIP(hipMemcpy(params, m->d.master, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost));
+    return LBM_OK;
+}
+
+lbm_status lbm_mlp_set_params(lbm_mlp *m, const float *params)
+{
+    if (!m || !params)
+        return mfail(LBM_E_INVALID, "null argument");
+    MHIP(hipStreamSynchronize(m->stream));
+    MHIP(hipMemcpy(m->d.master, params, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice));
+    MHIP(hipMemsetAsync(m->d.m, 0, sizeof(float) * MLP_NPARAM, m->stream));
+    MHIP(hipMemsetAsync(m->d.v, 0, sizeof(float) * MLP_NPARAM, m->stream));
+    MHIP(launch_mlp_round(m->d, m->stream));
+    MHIP(hipStreamSynchronize(m->stream));
+    m->adam_t = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_mlp_set_scaling(lbm_mlp *m, const float *x_mean, const float *x_std, float y_mean, float y_std)
+{
+    if (!m || !x_mean || !x_std)
+        return mfail(LBM_E_INVALID, "null argument");
+    float sc[12];
+    for (int k = 0; k < MLP_IN; ++k) {
+        if (!(x_std[k] > 0.0f))
+            return mfail(LBM_E_INVALID, "feature scales must be > 0");
+        sc[k] = x_mean[k];
+        sc[MLP_IN + k] = x_std[k];
+    }
+    if (!(y_std > 0.0f))
+        return mfail(LBM_E_INVALID, "target scale must be > 0");
+    sc[10] = y_mean;
+    sc[11] = y_std;
+    MHIP(hipStreamSynchronize(m->stream));
+    MHIP(hipMemcpy(m->d.sc, sc, sizeof sc, hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+lbm_status lbm_mlp_grad(lbm_mlp *m, const float *x, const float *t, int64_t n, float *grad, float *loss)
+{
+    if (!m || !x || !t || !grad || n <= 0 || n > (1 << 30))
+        return mfail(LBM_E_INVALID, "bad arguments");
+    const int chunks = (int)((n + MLP_CHUNK - 1) / MLP_CHUNK);
+    lbm_status st = ensure_chunks(m, chunks);
+    if (st != LBM_OK)
+        return st;
+    MHIP(launch_mlp_grad(m->d, x, t, nullptr, 0, (int)n, (int)n, m->stream));
+    MHIP(launch_mlp_reduce(m->d, chunks, m->stream));
+    std::vector<float> g(MLP_PSTRIDE);
+    MHIP(hipMemcpyAsync(g.data(), m->d.grad, sizeof(float) * MLP_PSTRIDE, hipMemcpyDeviceToHost, m->stream));
+    MHIP(hipStreamSynchronize(m->stream));
+    std::memcpy(grad, g.data(), sizeof(float) * MLP_NPARAM);
+    if (loss)
+        *loss = g[MLP_NPARAM];
+    return LBM_OK;
+}
+
+lbm_status lbm_mlp_adam_step(lbm_mlp *m, const float *grad, float lr)
+{
+    if (!m || !grad)
+        return mfail(LBM_E_INVALID, "null argument");
+    MHIP(hipStreamSynchronize(m->stream));
+    MHIP(hipMemcpy(m->d.grad, grad, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice));
+    m->adam_t++;
+    const float bc1 = (float)(1.0 - std::pow(0.9, (double)m->adam_t));
+    const float bc2 = (float)(1.0 - std::pow(0.999, (double)m->adam_t));
+    MHIP(launch_mlp_adam(m->d, lr, 0.9f, 0.999f, 1e-8f, bc1, bc2, m->stream));
+    MHIP(hipStreamSynchronize(m->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_mlp_train(lbm_mlp *m, const float *x, const float *t, int64_t n, int32_t epochs, int32_t batch,
+                         float lr, uint64_t seed, float *loss_per_epoch)
+{
+    if (!m || !x || !t || n <= 0 || n > (1 << 30) || epochs <= 0 || batch <= 0 || !(lr > 0.0f))
+        return mfail(LBM_E_INVALID, "bad arguments");
+    const int chunks = (batch + MLP_CHUNK - 1) / MLP_CHUNK;
+    lbm_status st = ensure_chunks(m, chunks);
+    if (st != LBM_OK)
+        return st;
+    if (m->idx_cap < n) {
+        if (m->idx)
+            (void)hipFree(m->idx);
+        m->idx = nullptr;
+        if (hipMalloc(&m->idx, sizeof(int32_t) * (size_t)n) != hipSuccess)
+            return mfail(LBM_E_NOMEM, "hipMalloc of the permutation failed");
+        m->idx_cap = n;
+    }
+    std::vector<int32_t> perm((size_t)n);
+    std::vector<float> losses((size_t)epochs, 0.0f);
+    for (int e = 0; e < epochs; ++e) {
+        // Fisher-Yates shuffle from SplitMix64(seed + epoch); the previous
+        // epoch's upload of the permutation must have drained first
+        MHIP(hipStreamSynchronize(m->stream));
+        for (int64_t i = 0; i < n; ++i)
+            perm[(size_t)i] = (int32_t)i;
+        SplitMix64 rng{seed + (uint64_t)e};
+        for (int64_t i = n - 1; i > 0; --i) {
+            const int64_t j = (int64_t)(rng.uniform() * (double)(i + 1));
+            std::swap(perm[(size_t)i], perm[(size_t)j]);
+        }
+        MHIP(hipMemcpyAsync(m->idx, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, m->stream));
+        // constant rate, then a tenth of it for the last 30 % of the epochs
+        const float lr_e = e < (7 * epochs) / 10 ? lr : 0.1f * lr;
+        for (int64_t b0 = 0; b0 < n; b0 += batch) {
+            const int count = (int)std::min<int64_t>(batch, n - b0);
+            MHIP(launch_mlp_grad(m->d, x, t, m->idx, b0, count, count, m->stream));
+            MHIP(launch_mlp_reduce(m->d, (count + MLP_CHUNK - 1) / MLP_CHUNK, m->stream));
+            m->adam_t++;
+            const float bc1 = (float)(1.0 - std::pow(0.9, (double)m->adam_t));
+            const float bc2 = (float)(1.0 - std::pow(0.999, (double)m->adam_t));
+            MHIP(launch_mlp_adam(m->d, lr_e, 0.9f, 0.999f, 1e-8f, bc1, bc2, m->stream));
+        }
+        // the epoch's loss is the full-data loss after the epoch
+        if (loss_per_epoch) {
+            const int all = (int)((n + MLP_CHUNK - 1) / MLP_CHUNK);
+            if ((st = ensure_chunks(m, all)) != LBM_OK)
+                return st;
+            MHIP(launch_mlp_grad(m->d, x, t, nullptr, 0, (int)n, (int)n, m->stream));
+            MHIP(launch_mlp_reduce(m->d, all, m->stream));
+            float l = 0.0f;
+            MHIP(hipMemcpyAsync(&l, m->d.grad + MLP_NPARAM, sizeof(float), hipMemcpyDeviceToHost, m->stream));
+            MHIP(hipStreamSynchronize(m->stream));
+            losses[(size_t)e] = l;
+        }
+    }
+    MHIP(hipStreamSynchronize(m->stream));
+    if (loss_per_epoch)
+        std::memcpy(loss_per_epoch, losses.data(), sizeof(float) * (size_t)epochs);
+    return LBM_OK;
+}
+
+lbm_status lbm_mlp_predict(lbm_mlp *m, const float *x, int64_t n, float *y)
+{
+    if (!m || !x || !y || n < 0)
+        return mfail(LBM_E_INVALID, "bad arguments");
+    MHIP(launch_mlp_predict(m->d, x, n, y, m->stream));
+    MHIP(hipStreamSynchronize(m->stream));
+    return LBM_OK;
+}
+
+}  // extern "C"
