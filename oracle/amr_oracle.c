@@ -541,7 +541,7 @@ static void level_step(or_amr *a, int l)
                             } else {
                                 val = fs[j * N + c] / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * fs[i * N + c];
                             }
-                            double mom = fs[j * N + c] + val;
+                            double mom = fs[j * N + c] + val - 2.0 * or_weight(j); /* gauge pressure */
                             fz[3 * z + 0] += cxo(j) * mom;
                             fz[3 * z + 1] += cyo(j) * mom;
                             fz[3 * z + 2] += czo(j) * mom;

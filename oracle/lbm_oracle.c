@@ -16,7 +16,11 @@
  *   - second-order interpolated bounce-back (Bouzidi et al. 2001, linear form)
  *     on the tree surface;
  *   - momentum-exchange force (Wen et al. 2014) summed over the surface and per
- *     branch, feeding C_D of Eq. (7).
+ *     branch, feeding C_D of Eq. (7).  Each link contributes
+ *     c_j (f*_j + f_opp(j)(t+1) - 2 w_j): the resting state's share sums to zero
+ *     over the closed tree (links in directions j and -j pair up on every
+ *     lattice line) and is left out so that a branch, whose surface is open
+ *     where it joins its parent, carries gauge rather than absolute pressure.
  *
  * Readings where the paper is silent (listed with the rest in the design notes):
  *   relaxation: omega1 from the viscosity, omega2 (bulk) a parameter (1 by
@@ -416,7 +420,10 @@ int or_step(const or_params *p, const double *f_in, double *f_out, const uint8_t
                             } else {
                                 val = fs[j * N + c] / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * fs[i * N + c];
                             }
-                            double mom = fs[j * N + c] + val;
+                            /* gauge pressure: the resting state's share 2 w_j drops out
+                             * of the total over a closed surface and is removed so that
+                             * per-branch sums over open surfaces are meaningful */
+                            double mom = fs[j * N + c] + val - 2.0 * or_weight(j);
                             fz[3 * z + 0] += cxof(j) * mom;
                             fz[3 * z + 1] += cyof(j) * mom;
                             fz[3 * z + 2] += czof(j) * mom;

@@ -259,8 +259,11 @@ __device__ __forceinline__ void link_update(const LinkArgs &a, int l)
     S *dst = reinterpret_cast<S *>(a.pop + (size_t)(ODD_DONE ? jb : j) * a.dir_bytes);
     dst[ODD_DONE ? af : ap] = Store<S>::st(gn);
     if (a.lforce) {
-        const float wj = w1d(qcx(j)) * w1d(qcy(j)) * w1d(qcz(j));
-        const float mom = 2.0f * wj + g1 + gn;
+        // momentum exchange c_j (f*_j + f_opp(j)(t+1)) in gauge form: with
+        // deviations g = f - w the resting state's 2 w_j, which sums to zero
+        // over the closed tree, is already absent, so a branch (an open part of
+        // the surface) carries gauge pressure
+        const float mom = g1 + gn;
         a.lforce[3 * (size_t)l + 0] = qcx(j) * mom;
         a.lforce[3 * (size_t)l + 1] = qcy(j) * mom;
         a.lforce[3 * (size_t)l + 2] = qcz(j) * mom;

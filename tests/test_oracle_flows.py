@@ -150,8 +150,10 @@ def test_quiescent_fluid_around_tree_stays_at_rest():
     sim.step(5)
     assert np.abs(sim.f - f0).max() < 1e-15
     assert np.abs(sim.last_force).max() < 1e-14
-    # each branch's share of the surface is open, so the uniform pressure puts a
-    # force on it; only the closed union carries none
+    # link forces use gauge pressure (the resting state's share, which sums to
+    # zero over the closed tree, is left out), so every branch -- an open part
+    # of the surface -- carries no force at rest either
+    assert np.abs(sim.last_branch_force).max() < 1e-14
     assert np.allclose(sim.last_branch_force.sum(0), 0.0, atol=1e-14)
 
 
