@@ -256,6 +256,14 @@ lbm_status lbm_mlp_train(lbm_mlp *m, const float *x, const float *t, int64_t n, 
 /* y (n floats, output units) of n rows of raw features x */
 lbm_status lbm_mlp_predict(lbm_mlp *m, const float *x, int64_t n, float *y);
 
+/* Host-only surrogate features of a tree's branches at Re_H (rows of 5 floats
+ * in feat): log10(Re_H D / H), the angle alpha between the branch axis and the
+ * flow (+x) in degrees, the generation, the inflow intensity, and the height
+ * of the branch midpoint above the trunk base over H (H as lbm_tree_place
+ * measures it).  ld (may be NULL) receives L D per branch. */
+lbm_status lbm_branch_features(const lbm_branch *b, int32_t n, double re_h, double intensity, float *feat,
+                               double *ld);
+
 /* Host-only mode set of the synthetic turbulent inflow that lbm_set_geometry
  * builds from turb_seed / turb_modes / turb_intensity / turb_length (inlet grid
  * spacing dx = 2^(levels-1) finest cells).  Random Fourier modes with a von

@@ -114,6 +114,7 @@ def lib():
         "lbm_mlp_train": [_P, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64,
                           C.POINTER(C.c_float)],
         "lbm_mlp_predict": [_P, _P, C.c_int64, _P],
+        "lbm_branch_features": [C.POINTER(Branch), C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_float), _dp],
         "lbm_inflow_modes": [C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp],
         "lbm_plan_levels": [C.POINTER(GridDesc), C.POINTER(Branch), C.c_int32, C.POINTER(RefineDesc),
                             C.POINTER(Plan), C.POINTER(C.POINTER(C.c_int8))],
@@ -322,6 +323,18 @@ class Mlp:
     def predict(self, x, out):
         _check(lib().lbm_mlp_predict(self.h, self._dev(x), x.shape[0], self._dev(out)))
         return out
+
+
+def branch_features(branches, re_h, intensity=0.0):
+    """(features (n, 5) float32, L D (n,) float64) of a tree's branches
+    (lbm_branch_features)."""
+    if isinstance(branches, np.ndarray):
+        branches = branches_from_numpy(branches)
+    n = len(branches)
+    feat = np.empty((n, 5), np.float32)
+    ld = np.empty(n)
+    _check(lib().lbm_branch_features(branches, n, float(re_h), float(intensity), _fptr(feat), _dptr(ld)))
+    return feat, ld
 
 
 def inflow_modes(seed, n_modes, intensity, length, u_in, dx):

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/lbmtree.h"
+#include "lbm_geometry.h"
 #include "lbm_grid.h"
 #include "lbm_mlp.h"
 #include "lbm_random.h"
@@ -282,6 +283,29 @@ lbm_status lbm_mlp_train(lbm_mlp *m, const float *x, const float *t, int64_t n, 
     MHIP(hipStreamSynchronize(m->stream));
     if (loss_per_epoch)
         std::memcpy(loss_per_epoch, losses.data(), sizeof(float) * (size_t)epochs);
+    return LBM_OK;
+}
+
+lbm_status lbm_branch_features(const lbm_branch *b, int32_t n, double re_h, double intensity, float *feat,
+                               double *ld)
+{
+    if (!b || n <= 0 || !feat || !(re_h > 0.0))
+        return mfail(LBM_E_INVALID, "bad arguments");
+    const double H = tree_height(b, n), zb = b[0].p0[2];
+    if (!(H > 0.0))
+        return mfail(LBM_E_INVALID, "tree of zero height");
+    for (int i = 0; i < n; ++i) {
+        const double dx = b[i].p1[0] - b[i].p0[0], dy = b[i].p1[1] - b[i].p0[1], dz = b[i].p1[2] - b[i].p0[2];
+        const double L = std::sqrt(dx * dx + dy * dy + dz * dz), D = b[i].diameter;
+        const double alpha = std::acos(std::min(1.0, std::fabs(dx) / L)) * (180.0 / M_PI);
+        feat[5 * (size_t)i + 0] = (float)std::log10(re_h * D / H);
+        feat[5 * (size_t)i + 1] = (float)alpha;
+        feat[5 * (size_t)i + 2] = (float)b[i].generation;
+        feat[5 * (size_t)i + 3] = (float)intensity;
+        feat[5 * (size_t)i + 4] = (float)((0.5 * (b[i].p0[2] + b[i].p1[2]) - zb) / H);
+        if (ld)
+            ld[i] = L * D;
+    }
     return LBM_OK;
 }
 
