@@ -256,6 +256,53 @@ lbm_status lbm_mlp_train(lbm_mlp *m, const float *x, const float *t, int64_t n, 
 /* y (n floats, output units) of n rows of raw features x */
 lbm_status lbm_mlp_predict(lbm_mlp *m, const float *x, int64_t n, float *y);
 
+/* ---- branch-wise drag sums over many trees -------------------------------
+ * Host-only batch of seeded trees from base: tree i has seed seed0 + i and
+ * order orders[i] (orders may be NULL: base->order), is scaled to unit height
+ * (lbm_tree_place) and yields one record of 10 floats per branch: log10(D/H),
+ * alpha (angle to +x, degrees), generation, midpoint height above the trunk
+ * base / H, L D / H^2, then the axis projected on the (y, z) plane and the
+ * radius (y0, z0, y1, z1, D/2, units of H).  tree_start (n_trees + 1) gets the
+ * branch offsets; with rec == NULL only tree_start is filled (sizing).
+ * Trees are generated in parallel (OpenMP). */
+lbm_status lbm_tree_batch(const lbm_tree_params *base, uint64_t seed0, int32_t n_trees, const int32_t *orders,
+                          int64_t cap, float *rec, int64_t *tree_start);
+
+/* Frontal area A_x / H^2 of each tree of a batch (device arrays): the union of
+ * the branches' projected capsules (segment plus radius), rasterised on pixels
+ * of edge h (units of H; 1/256 in the sweeps) anchored at the tree's lower
+ * (y, z) bound; a pixel counts when its centre lies within a capsule (-1 when a
+ * tree spans more than 640 pixels).  Ordered on stream; returns when done. */
+lbm_status lbm_frontal_area(const float *rec, const int64_t *tree_start, int32_t n_trees, double h, float *area,
+                            void *stream);
+
+typedef struct {
+    const float *rec;           /* device: branch records of lbm_tree_batch */
+    const int64_t *tree_start;  /* device: n_trees + 1 offsets */
+    int32_t n_trees;
+    const double *re_h;         /* host: Re_H values (1 .. 32) */
+    int32_t n_re;
+    double intensity;           /* inflow I_u in [0, 0.2]: network input and cylinder curve */
+    double re_d_lo, re_d_hi;    /* surrogate: branch Re_D range of its training data */
+    const float *area;          /* device: A_x / H^2 per tree */
+    float *cd;                  /* device: n_trees x n_re drag coefficients (row per tree) */
+} lbm_sweep_desc;
+
+/* C_D of every tree at every Re_H from the surrogate (Eqs. (2), (4) with the
+ * network's branch force coefficient y_b in place of C_d sin^3(alpha)):
+ * C_D = sum_b y_b L_b D_b / A_x.  Outside [re_d_lo, re_d_hi] the network is
+ * evaluated at the clamped Re_D and scaled by the cylinder curve's ratio
+ * C_d(Re_D) / C_d(Re_D,clamped).  The cylinder curve is the analytic model's
+ * (a synthetic stand-in for the measurements the paper fits): a subcritical
+ * 1 + 10 Re^(-2/3) blended into a post-critical 0.25 + 0.35 / (1 + exp(-(ln Re -
+ * ln(20 Re_cr)) / 0.8)) by 1 / (1 + exp((ln Re - ln Re_cr) / 0.12)), Re_cr =
+ * 2.7e5 for uniform inflow and 1.4e4 at I_u = 8 % (log-linear in between).
+ * Matrix cores, one wave per tree. */
+lbm_status lbm_surrogate_sweep(lbm_mlp *m, const lbm_sweep_desc *d);
+/* The analytic model of Eqs. (2) and (4), C_D = sum_b C_d(Re_b) L_b D_b
+ * sin^3(alpha_b) / A_x, on the same inputs (re_d_lo / re_d_hi unused). */
+lbm_status lbm_analytic_sweep(const lbm_sweep_desc *d, void *stream);
+
 /* Host-only surrogate features of a tree's branches at Re_H (rows of 5 floats
  * in feat): log10(Re_H D / H), the angle alpha between the branch axis and the
  * flow (+x) in degrees, the generation, the inflow intensity, and the height

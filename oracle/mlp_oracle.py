@@ -27,6 +27,8 @@ Loss: mean over the batch of (y - t)^2 on the standardised target
 (t = (y_target - y_mean) / y_std).  Optimiser: Adam (Kingma and Ba 2015) with
 bias correction.
 """
+import math
+
 import numpy as np
 
 N_IN, N_H = 5, 64
@@ -103,3 +105,22 @@ def adam_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mh = m / (1.0 - beta1 ** t)
     vh = v / (1.0 - beta2 ** t)
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def tree_cd_sweep(p, scale, yscale, feat_fixed, lgd, w, re_h, intensity, lo, hi, area, cylinder_cd):
+    """Surrogate C_D of one tree at each Re_H (inference form): for each branch
+    the features (log10 Re_D clamped to [log10 lo, log10 hi], alpha,
+    generation, I_u, midpoint height / H), the network output in target units,
+    scaled by C_d(Re_D) / C_d(Re_D,clamped) outside the range; then
+    sum_b y_b w_b / area.  feat_fixed: (n, 3) alpha, generation, height;
+    lgd: log10(D / H); w: L D / H^2."""
+    out = []
+    for r in np.atleast_1d(re_h):
+        lre = math.log10(r) + lgd
+        lc = np.clip(lre, math.log10(lo), math.log10(hi))
+        X = np.column_stack([lc, feat_fixed[:, 0], feat_fixed[:, 1], np.full(len(lgd), intensity), feat_fixed[:, 2]])
+        y, _ = forward(p, X, scale=scale, weights_bf16=True, act_bf16=True)
+        y = y * yscale[1] + yscale[0]
+        y = y * cylinder_cd(10.0 ** lre, intensity) / cylinder_cd(10.0 ** lc, intensity)
+        out.append(np.sum(y * w) / area)
+    return np.array(out)

@@ -114,6 +114,10 @@ def lib():
         "lbm_mlp_train": [_P, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64,
                           C.POINTER(C.c_float)],
         "lbm_mlp_predict": [_P, _P, C.c_int64, _P],
+        "lbm_tree_batch": [C.c_void_p, C.c_uint64, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
+        "lbm_frontal_area": [_P, _P, C.c_int32, C.c_double, _P, _P],
+        "lbm_surrogate_sweep": [_P, _P],
+        "lbm_analytic_sweep": [_P, _P],
         "lbm_branch_features": [C.POINTER(Branch), C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_float), _dp],
         "lbm_inflow_modes": [C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp],
         "lbm_plan_levels": [C.POINTER(GridDesc), C.POINTER(Branch), C.c_int32, C.POINTER(RefineDesc),
@@ -263,6 +267,53 @@ def _fptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_float))
 
 
+class SweepDesc(C.Structure):
+    _fields_ = [("rec", _P), ("tree_start", _P), ("n_trees", C.c_int32), ("re_h", _dp), ("n_re", C.c_int32),
+                ("intensity", C.c_double), ("re_d_lo", C.c_double), ("re_d_hi", C.c_double), ("area", _P),
+                ("cd", _P)]
+
+
+def tree_batch(params, seed0, orders):
+    """Branch records (n_branches, 10) float32 and offsets (n_trees + 1) int64
+    of seeded trees (lbm_tree_batch)."""
+    orders = np.ascontiguousarray(orders, dtype=np.int32)
+    n = len(orders)
+    start = np.empty(n + 1, np.int64)
+    _check(lib().lbm_tree_batch(C.byref(params), seed0, n, orders.ctypes.data, 0, None, start.ctypes.data))
+    rec = np.empty((int(start[-1]), 10), np.float32)
+    _check(lib().lbm_tree_batch(C.byref(params), seed0, n, orders.ctypes.data, rec.shape[0], rec.ctypes.data,
+                                start.ctypes.data))
+    return rec, start
+
+
+def _dptr_t(a):
+    assert a.is_cuda and a.is_contiguous()
+    return C.c_void_p(a.data_ptr())
+
+
+def frontal_area(rec, start, h, area, stream=None):
+    """A_x / H^2 per tree into the torch tensor area (device arrays)."""
+    _check(lib().lbm_frontal_area(_dptr_t(rec), _dptr_t(start), start.shape[0] - 1, float(h), _dptr_t(area), stream))
+    return area
+
+
+def _sweep_desc(rec, start, area, cd, re_h, intensity, re_d_range):
+    re_h = np.ascontiguousarray(re_h, dtype=np.float64)
+    d = SweepDesc()
+    d.rec, d.tree_start, d.n_trees = _dptr_t(rec), _dptr_t(start), start.shape[0] - 1
+    d.re_h, d.n_re = _dptr(re_h), len(re_h)
+    d.intensity = intensity
+    d.re_d_lo, d.re_d_hi = re_d_range
+    d.area, d.cd = _dptr_t(area), _dptr_t(cd)
+    return d, re_h
+
+
+def analytic_sweep(rec, start, area, cd, re_h, intensity=0.0, stream=None):
+    d, keep = _sweep_desc(rec, start, area, cd, re_h, intensity, (1.0, 1.0))
+    _check(lib().lbm_analytic_sweep(C.byref(d), stream))
+    return cd
+
+
 class Mlp:
     """Owns one lbm_mlp handle (the per-branch drag surrogate network).  Device
     arrays are torch CUDA tensors (float32, contiguous); the library computes on
@@ -319,6 +370,11 @@ class Mlp:
         _check(lib().lbm_mlp_train(self.h, self._dev(x), self._dev(t), x.shape[0], epochs, batch, float(lr), seed,
                                    _fptr(losses)))
         return losses
+
+    def sweep(self, rec, start, area, cd, re_h, intensity=0.0, re_d_range=(1.0, 1e3)):
+        d, keep = _sweep_desc(rec, start, area, cd, re_h, intensity, re_d_range)
+        _check(lib().lbm_surrogate_sweep(self.h, C.byref(d)))
+        return cd
 
     def predict(self, x, out):
         _check(lib().lbm_mlp_predict(self.h, self._dev(x), x.shape[0], self._dev(out)))

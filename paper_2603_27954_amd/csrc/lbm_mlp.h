@@ -38,19 +38,36 @@ hipError_t launch_mlp_round(const MlpDev &d, hipStream_t s);
 // y = network(x) for n rows of raw features, in output units (matrix cores, BF16 operands)
 hipError_t launch_mlp_predict(const MlpDev &d, const float *x, int64_t n, float *y, hipStream_t s);
 
-// Branch-wise drag sums of many trees at many Re_H (see lbm_surrogate_sweep).
+// Branch records of a batch of trees (lengths in units of the tree height
+// H): log10(D/H), alpha (deg), generation, midpoint height / H, L D / H^2, and
+// the branch axis projected on the (y, z) plane with the radius: y0, z0, y1,
+// z1, D / 2.
+constexpr int SWEEP_REC = 10;
+constexpr int SWEEP_MAX_RE = 32;
+constexpr int AREA_PIX = 640;  // frontal-area raster edge (pixels)
+
+// Branch-wise drag sums of many trees at many Re_H.
 struct SweepArgs {
-    const float *feat;     // per branch: lgd (log10 D/H), alpha (deg), generation, zmid / H, L D / H^2
-    const int64_t *tree_start;  // n_trees + 1 branch offsets
+    const float *rec;          // SWEEP_REC floats per branch
+    const int64_t *tree_start; // n_trees + 1 branch offsets
     int n_trees;
-    const float *lg_re;    // log10 Re_H values
+    float lg_re[SWEEP_MAX_RE]; // log10 Re_H values
     int n_re;
     float intensity;
-    float lg_lo, lg_hi;    // training envelope of log10 Re_D
-    float re_cr;           // critical Re_D of the cylinder curve for this intensity
-    const float *area;     // per tree A_x / H^2
-    float *cd;             // n_trees x n_re
+    float lg_lo, lg_hi;        // training envelope of log10 Re_D (surrogate only)
+    float re_cr;               // critical Re_D of the cylinder curve for this intensity
+    const float *area;         // per tree A_x / H^2
+    float *cd;                 // n_trees x n_re
 };
+// surrogate: sum_b y_b L_b D_b / A_x with y_b from the network (extrapolated
+// through the cylinder curve outside the envelope)
 hipError_t launch_tree_sweep(const MlpDev &d, const SweepArgs &a, hipStream_t s);
+// analytic model: sum_b C_d(Re_b) L_b D_b sin^3(alpha_b) / A_x
+hipError_t launch_analytic_sweep(const SweepArgs &a, hipStream_t s);
+// frontal area of each tree (units of H^2): union of the branches' projected
+// capsules rasterised with pixel edge h (units of H); -1 when the tree does
+// not fit AREA_PIX pixels per side
+hipError_t launch_frontal_area(const float *rec, const int64_t *tree_start, int n_trees, float h, float *area,
+                               hipStream_t s);
 
 }  // namespace lbm

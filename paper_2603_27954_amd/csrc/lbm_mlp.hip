@@ -300,6 +300,163 @@ __global__ void __launch_bounds__(256) k_mlp_predict(MlpDev d, const float *x, i
     }
 }
 
+// ---------------------------------------------------------------------------
+// branch-wise drag sums over many trees
+// ---------------------------------------------------------------------------
+
+// Cylinder drag curve of the analytic model (a synthetic stand-in for the
+// fitted measurements the paper does not print): a subcritical correlation
+// 1 + 10 Re^(-2/3) blended into a post-critical branch
+// 0.25 + 0.35 / (1 + exp(-(ln Re - ln(20 Re_cr)) / 0.8)) by the weight
+// 1 / (1 + exp((ln Re - ln Re_cr) / 0.12)).
+__device__ __forceinline__ float cylinder_cd(float lg_re, float ln_rc)
+{
+    const float lr = lg_re * 2.302585093f;
+    const float sub = 1.0f + 10.0f * expf(-(2.0f / 3.0f) * lr);
+    const float post = 0.25f + 0.35f / (1.0f + expf(-(lr - (ln_rc + 2.995732274f)) / 0.8f));
+    const float w = 1.0f / (1.0f + expf((lr - ln_rc) / 0.12f));
+    return w * sub + (1.0f - w) * post;
+}
+
+__device__ __forceinline__ float wave_sum_f(float v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// One wave per tree: for each Re_H, tiles of 32 branches on the matrix cores;
+// per-lane sums in tile order, then a fixed shuffle tree.  The branch records
+// of a tree stay in cache across the Re_H loop.
+__global__ void __launch_bounds__(64) k_tree_sweep(MlpDev d, SweepArgs a)
+{
+    __shared__ float sb[192];
+    load_bias(d, sb);
+    const int lane = threadIdx.x;
+    MlpRegs r;
+    load_regs(d, r, lane);
+    const int tree = blockIdx.x;
+    const int64_t b0 = a.tree_start[tree], b1 = a.tree_start[tree + 1];
+    const float b3 = d.wr[MLP_B3], ym = d.sc[10], ys = d.sc[11];
+    const float ln_rc = logf(a.re_cr), inv = 1.0f / a.area[tree];
+    const int kh = 4 * (lane >> 5);
+    for (int q = 0; q < a.n_re; ++q) {
+        float acc = 0.0f;
+        for (int64_t t0 = b0; t0 < b1; t0 += 32) {
+            const int64_t br = t0 + (lane & 31);
+            const bool valid = br < b1;
+            const float *rc = a.rec + (valid ? br : b0) * SWEEP_REC;
+            const float lre = a.lg_re[q] + rc[0];
+            const float lc = fminf(fmaxf(lre, a.lg_lo), a.lg_hi);
+            // lanes < 32 carry features 0..3 of their branch, lanes >= 32 feature 4
+            bf16x4 bop;
+            for (int j = 0; j < 4; ++j) {
+                const int k = kh + j;
+                const float v = k == 0 ? lc : k == 1 ? rc[1] : k == 2 ? rc[2] : k == 3 ? a.intensity : rc[3];
+                bop[j] = (short)bf16_bits(k < MLP_IN ? (v - d.sc[k]) / d.sc[MLP_IN + k] : 0.0f);
+            }
+            float y = (mlp_tile(r, bop, sb, lane) + b3) * ys + ym;
+            if (lre != lc)
+                y *= cylinder_cd(lre, ln_rc) / cylinder_cd(lc, ln_rc);
+            acc = fmaf((lane < 32 && valid) ? y : 0.0f, rc[4], acc);
+        }
+        const float sum = wave_sum_f(acc);
+        if (lane == 0)
+            a.cd[(size_t)tree * a.n_re + q] = sum * inv;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_analytic_sweep(SweepArgs a)
+{
+    const int lane = threadIdx.x, tree = blockIdx.x;
+    const int64_t b0 = a.tree_start[tree], b1 = a.tree_start[tree + 1];
+    const float ln_rc = logf(a.re_cr), inv = 1.0f / a.area[tree];
+    for (int q = 0; q < a.n_re; ++q) {
+        float acc = 0.0f;
+        for (int64_t br = b0 + lane; br < b1; br += 64) {
+            const float *rc = a.rec + br * SWEEP_REC;
+            const float sn = sinf(rc[1] * 0.01745329252f);
+            acc = fmaf(cylinder_cd(a.lg_re[q] + rc[0], ln_rc), rc[4] * sn * sn * sn, acc);
+        }
+        const float sum = wave_sum_f(acc);
+        if (lane == 0)
+            a.cd[(size_t)tree * a.n_re + q] = sum * inv;
+    }
+}
+
+// Union of the projected capsules (segment (y0, z0)-(y1, z1), radius r) on a
+// pixel grid of edge h anchored at the tree's lower (y, z) bound; a pixel is
+// covered when its centre lies within r of a segment.
+__global__ void __launch_bounds__(256) k_frontal_area(const float *rec, const int64_t *tree_start, float h,
+                                                      float *area)
+{
+    constexpr int WORDS = AREA_PIX * AREA_PIX / 32;
+    __shared__ uint32_t bits[WORDS];
+    __shared__ float red[4][256];
+    const int tid = threadIdx.x, tree = blockIdx.x;
+    const int64_t b0 = tree_start[tree], b1 = tree_start[tree + 1];
+    float ylo = 1e30f, yhi = -1e30f, zlo = 1e30f, zhi = -1e30f;
+    for (int64_t b = b0 + tid; b < b1; b += 256) {
+        const float *rc = rec + b * SWEEP_REC;
+        const float rr = rc[9];
+        ylo = fminf(ylo, fminf(rc[5], rc[7]) - rr);
+        yhi = fmaxf(yhi, fmaxf(rc[5], rc[7]) + rr);
+        zlo = fminf(zlo, fminf(rc[6], rc[8]) - rr);
+        zhi = fmaxf(zhi, fmaxf(rc[6], rc[8]) + rr);
+    }
+    red[0][tid] = ylo, red[1][tid] = -yhi, red[2][tid] = zlo, red[3][tid] = -zhi;
+    for (int i = tid; i < WORDS; i += 256)
+        bits[i] = 0u;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o)
+            for (int k = 0; k < 4; ++k)
+                red[k][tid] = fminf(red[k][tid], red[k][tid + o]);
+        __syncthreads();
+    }
+    ylo = red[0][0], yhi = -red[1][0], zlo = red[2][0], zhi = -red[3][0];
+    const int ny = (int)ceilf((yhi - ylo) / h), nz = (int)ceilf((zhi - zlo) / h);
+    __syncthreads();
+    if (ny > AREA_PIX || nz > AREA_PIX || b1 <= b0) {
+        if (tid == 0)
+            area[tree] = -1.0f;
+        return;
+    }
+    for (int64_t b = b0; b < b1; ++b) {
+        const float *rc = rec + b * SWEEP_REC;
+        const float y0 = rc[5], z0 = rc[6], y1 = rc[7], z1 = rc[8], rr = rc[9];
+        const float dy = y1 - y0, dz = z1 - z0, l2 = dy * dy + dz * dz;
+        const int py0 = max(0, (int)floorf((fminf(y0, y1) - rr - ylo) / h));
+        const int py1 = min(ny - 1, (int)floorf((fmaxf(y0, y1) + rr - ylo) / h));
+        const int pz0 = max(0, (int)floorf((fminf(z0, z1) - rr - zlo) / h));
+        const int pz1 = min(nz - 1, (int)floorf((fmaxf(z0, z1) + rr - zlo) / h));
+        const int wy = py1 - py0 + 1, np = wy * (pz1 - pz0 + 1);
+        for (int p = tid; p < np; p += 256) {
+            const int py = py0 + p % wy, pz = pz0 + p / wy;
+            const float cy = ylo + (py + 0.5f) * h - y0, cz = zlo + (pz + 0.5f) * h - z0;
+            const float tt = l2 > 0.0f ? fminf(fmaxf((cy * dy + cz * dz) / l2, 0.0f), 1.0f) : 0.0f;
+            const float ey = cy - tt * dy, ez = cz - tt * dz;
+            if (ey * ey + ez * ez <= rr * rr) {
+                const int bit = pz * AREA_PIX + py;
+                atomicOr(&bits[bit >> 5], 1u << (bit & 31));
+            }
+        }
+    }
+    __syncthreads();
+    float cnt = 0.0f;
+    for (int i = tid; i < WORDS; i += 256)
+        cnt += (float)__popc(bits[i]);
+    red[0][tid] = cnt;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o)
+            red[0][tid] += red[0][tid + o];
+        __syncthreads();
+    }
+    if (tid == 0)
+        area[tree] = red[0][0] * h * h;
+}
+
 }  // namespace
 
 hipError_t launch_mlp_grad(const MlpDev &d, const float *x, const float *t, const int32_t *idx, int64_t base,
@@ -343,6 +500,29 @@ hipError_t launch_mlp_predict(const MlpDev &d, const float *x, int64_t n, float 
     return hipGetLastError();
 }
 
-hipError_t launch_tree_sweep(const MlpDev &, const SweepArgs &, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_tree_sweep(const MlpDev &d, const SweepArgs &a, hipStream_t s)
+{
+    if (a.n_trees <= 0 || a.n_re <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_tree_sweep, dim3(a.n_trees), dim3(64), 0, s, d, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_analytic_sweep(const SweepArgs &a, hipStream_t s)
+{
+    if (a.n_trees <= 0 || a.n_re <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_analytic_sweep, dim3(a.n_trees), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_frontal_area(const float *rec, const int64_t *tree_start, int n_trees, float h, float *area,
+                               hipStream_t s)
+{
+    if (n_trees <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_frontal_area, dim3(n_trees), dim3(256), 0, s, rec, tree_start, h, area);
+    return hipGetLastError();
+}
 
 }  // namespace lbm

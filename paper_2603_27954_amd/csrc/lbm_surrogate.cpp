@@ -309,6 +309,122 @@ lbm_status lbm_branch_features(const lbm_branch *b, int32_t n, double re_h, doub
     return LBM_OK;
 }
 
+lbm_status lbm_tree_batch(const lbm_tree_params *base, uint64_t seed0, int32_t n_trees, const int32_t *orders,
+                          int64_t cap, float *rec, int64_t *tree_start)
+{
+    if (!base || n_trees <= 0 || !tree_start || base->m < 1 || base->m > 4)
+        return mfail(LBM_E_INVALID, "bad arguments");
+    tree_start[0] = 0;
+    for (int i = 0; i < n_trees; ++i) {
+        const int order = orders ? orders[i] : base->order;
+        if (order < 0 || order > 12)
+            return mfail(LBM_E_INVALID, "tree order out of range");
+        int64_t c = 0, pw = 1;
+        for (int k = 0; k <= order; ++k, pw *= base->m)
+            c += pw;
+        tree_start[i + 1] = tree_start[i] + c;
+    }
+    if (!rec)
+        return LBM_OK;
+    if (tree_start[n_trees] > cap)
+        return mfail(LBM_E_INVALID, "record capacity too small (tree_start[n_trees] holds the need)");
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+    for (int i = 0; i < n_trees; ++i) {
+        lbm_tree_params p = *base;
+        p.order = orders ? orders[i] : base->order;
+        p.seed = seed0 + (uint64_t)i;
+        std::vector<lbm_branch> b;
+        tree_generate(p, b);
+        const int n = (int)b.size();
+        if (n != (int)(tree_start[i + 1] - tree_start[i])) {
+            bad = 1;
+            continue;
+        }
+        const double com[3] = {0.0, 0.0, 0.0};
+        tree_place(b.data(), n, 1.0, com);
+        const double zb = b[0].p0[2];
+        for (int j = 0; j < n; ++j) {
+            const lbm_branch &q = b[j];
+            const double dx = q.p1[0] - q.p0[0], dy = q.p1[1] - q.p0[1], dz = q.p1[2] - q.p0[2];
+            const double L = std::sqrt(dx * dx + dy * dy + dz * dz), D = q.diameter;
+            float *r = rec + (tree_start[i] + j) * SWEEP_REC;
+            r[0] = (float)std::log10(D);
+            r[1] = (float)(std::acos(std::min(1.0, std::fabs(dx) / L)) * (180.0 / M_PI));
+            r[2] = (float)q.generation;
+            r[3] = (float)(0.5 * (q.p0[2] + q.p1[2]) - zb);
+            r[4] = (float)(L * D);
+            r[5] = (float)q.p0[1];
+            r[6] = (float)q.p0[2];
+            r[7] = (float)q.p1[1];
+            r[8] = (float)q.p1[2];
+            r[9] = (float)(0.5 * D);
+        }
+    }
+    return bad ? mfail(LBM_E_INVALID, "tree generator returned an unexpected branch count") : LBM_OK;
+}
+
+lbm_status lbm_frontal_area(const float *rec, const int64_t *tree_start, int32_t n_trees, double h, float *area,
+                            void *stream)
+{
+    if (!rec || !tree_start || !area || n_trees < 0 || !(h > 0.0))
+        return mfail(LBM_E_INVALID, "bad arguments");
+    MHIP(launch_frontal_area(rec, tree_start, n_trees, (float)h, area, (hipStream_t)stream));
+    MHIP(hipStreamSynchronize((hipStream_t)stream));
+    return LBM_OK;
+}
+
+static lbm_status sweep_args(const lbm_sweep_desc *d, SweepArgs &a)
+{
+    if (!d || !d->rec || !d->tree_start || !d->area || !d->cd || d->n_trees < 0 || !d->re_h || d->n_re <= 0 ||
+        d->n_re > SWEEP_MAX_RE || d->intensity < 0.0 || d->intensity > 0.2)
+        return mfail(LBM_E_INVALID, "bad sweep description");
+    a = SweepArgs{};
+    a.rec = d->rec;
+    a.tree_start = d->tree_start;
+    a.n_trees = d->n_trees;
+    for (int q = 0; q < d->n_re; ++q) {
+        if (!(d->re_h[q] > 0.0))
+            return mfail(LBM_E_INVALID, "Re_H must be > 0");
+        a.lg_re[q] = (float)std::log10(d->re_h[q]);
+    }
+    a.n_re = d->n_re;
+    a.intensity = (float)d->intensity;
+    a.lg_lo = (float)std::log10(std::max(d->re_d_lo, 1e-30));
+    a.lg_hi = (float)std::log10(std::max(d->re_d_hi, 1e-30));
+    // critical Re_D: 2.7e5 for uniform inflow, 1.4e4 at I_u = 8 %, log-linear in between
+    a.re_cr = (float)(2.7e5 * std::pow(1.4e4 / 2.7e5, d->intensity / 0.08));
+    a.area = d->area;
+    a.cd = d->cd;
+    return LBM_OK;
+}
+
+lbm_status lbm_surrogate_sweep(lbm_mlp *m, const lbm_sweep_desc *d)
+{
+    if (!m)
+        return mfail(LBM_E_INVALID, "null handle");
+    SweepArgs a;
+    lbm_status st = sweep_args(d, a);
+    if (st != LBM_OK)
+        return st;
+    if (!(d->re_d_lo > 0.0) || !(d->re_d_hi >= d->re_d_lo))
+        return mfail(LBM_E_INVALID, "training envelope must satisfy 0 < re_d_lo <= re_d_hi");
+    MHIP(launch_tree_sweep(m->d, a, m->stream));
+    MHIP(hipStreamSynchronize(m->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_analytic_sweep(const lbm_sweep_desc *d, void *stream)
+{
+    SweepArgs a;
+    lbm_status st = sweep_args(d, a);
+    if (st != LBM_OK)
+        return st;
+    MHIP(launch_analytic_sweep(a, (hipStream_t)stream));
+    MHIP(hipStreamSynchronize((hipStream_t)stream));
+    return LBM_OK;
+}
+
 lbm_status lbm_mlp_predict(lbm_mlp *m, const float *x, int64_t n, float *y)
 {
     if (!m || !x || !y || n < 0)

@@ -167,3 +167,25 @@ def test_inflow_modes_match_oracle(lt, seed, n, dx, length):
     assert np.allclose(m["sigma"], o.sigma, rtol=1e-13, atol=1e-15)
     assert np.allclose(m["psi"], o.psi, rtol=1e-15, atol=0)
     assert np.allclose(m["amp"], o.amp, rtol=1e-11, atol=0)
+
+
+def test_tree_batch_records_match_oracle(lt):
+    """Branch records of the many-tree sweep (seeded three-child trees at unit
+    height) against the oracle's own trees and geometry."""
+    from oracle import analytic_oracle as A
+    params = lt.tree_params(3, 3, 1.0, 0.3, [0.7] * 3, [0.7] * 3, [0.0, 120.0, 240.0], [35.0] * 3, [90.0] * 3,
+                            jitter=5.0, seed=0)
+    orders = [1, 2, 3, 4, 0, 2]
+    rec, start = lt.tree_batch(params, 500, orders)
+    assert list(np.diff(start)) == [sum(3 ** k for k in range(o + 1)) for o in orders]
+    for i, o in enumerate(orders):
+        b = O.build_tree(O.seeded3_tree_params(o, 500 + i), 1.0, [0.0, 0.0, 0.0])
+        L, D, alpha, zmid = A.branch_geometry(b)
+        r = rec[start[i]:start[i + 1]].astype(np.float64)
+        assert np.allclose(r[:, 0], np.log10(D), atol=1e-6)
+        assert np.allclose(r[:, 1], np.degrees(alpha), atol=2e-4)
+        assert np.array_equal(r[:, 2], b[:, 7])
+        assert np.allclose(r[:, 3], zmid - b[0, 2], atol=1e-6)
+        assert np.allclose(r[:, 4], L * D, rtol=1e-6)
+        assert np.allclose(r[:, 5:9], b[:, [1, 2, 4, 5]], atol=1e-6)
+        assert np.allclose(r[:, 9], 0.5 * D, rtol=1e-6)

@@ -149,3 +149,45 @@ def test_surrogate_beats_analytic_on_held_out_lbm(gpu):
           flush=True)
     assert err_s.mean() < 0.03
     assert err_s.mean() < err_a.mean()
+
+
+@pytest.mark.parametrize("intensity", [0.0, 0.08])
+def test_many_tree_sweeps_match_oracle(gpu, intensity):
+    """Frontal areas (rasterised capsule projections), the analytic model's
+    C_D (Eqs. (2), (4)) and the surrogate's C_D with its extrapolation outside
+    the training envelope, per tree and per Re_H, against the oracle."""
+    import torch
+
+    import oracle as O
+    from oracle import analytic_oracle as A
+    params = gpu.tree_params(3, 3, 1.0, 0.3, [0.7] * 3, [0.7] * 3, [0.0, 120.0, 240.0], [35.0] * 3, [90.0] * 3,
+                             jitter=5.0, seed=0)
+    orders = [1, 2, 3, 4, 5, 0, 3, 2]
+    rec, start = gpu.tree_batch(params, 700, orders)
+    rd, sd = torch.from_numpy(rec).cuda(), torch.from_numpy(start).cuda()
+    n = len(orders)
+    area = torch.empty(n, dtype=torch.float32, device="cuda")
+    h = 1.0 / 256
+    gpu.frontal_area(rd, sd, h, area)
+    ag = area.cpu().numpy().astype(np.float64)
+    re_h = 10.0 ** np.linspace(3, 9, 25)
+    cd_a = torch.empty((n, len(re_h)), dtype=torch.float32, device="cuda")
+    gpu.analytic_sweep(rd, sd, area, cd_a, re_h, intensity)
+    m, p, *_ = _setup(gpu, seed=8)
+    sc = (np.array([2.0, 45.0, 2.0, 0.04, 0.5]), np.array([0.5, 30.0, 1.5, 0.04, 0.3]))
+    cd_s = torch.empty((n, len(re_h)), dtype=torch.float32, device="cuda")
+    env = (20.0, 800.0)
+    m.sweep(rd, sd, area, cd_s, re_h, intensity, env)
+    cd_a, cd_s = cd_a.cpu().numpy(), cd_s.cpu().numpy()
+    for i, o in enumerate(orders):
+        b = O.build_tree(O.seeded3_tree_params(o, 700 + i), 1.0, [0.0, 0.0, 0.0])
+        ao = A.projected_area(b, h)
+        assert abs(ag[i] - ao) <= 2e-3 * ao, f"tree {i}: area {ag[i]} vs {ao}"
+        want_a = A.tree_cd_est(b, re_h, 1.0, ag[i], intensity)
+        assert np.allclose(cd_a[i], want_a, rtol=2e-4), f"tree {i} analytic"
+        L, D, alpha, zmid = A.branch_geometry(b)
+        fixed = np.column_stack([np.degrees(alpha), b[:, 7], zmid - b[0, 2]])
+        want_s = M.tree_cd_sweep(p.astype(np.float64), sc, (1.1, 0.7), fixed, np.log10(D), L * D, re_h, intensity,
+                                 env[0], env[1], ag[i], A.cylinder_cd)
+        err = np.abs(cd_s[i] - want_s) / np.abs(want_s)
+        assert err.max() < 5e-3, f"tree {i} surrogate: {err.max():.2e}"
