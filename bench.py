@@ -174,6 +174,102 @@ def amr_leg(lt, torch, steps, warmup):
     return res
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+MLP_FLOP = 8960  # 2 x (5 x 64 + 64 x 64 + 64) per inference
+
+
+def surrogate_leg(lt, torch, n_trees, chunk=1 << 17):
+    """Learned per-branch drag surrogate: trained on per-branch forces from LBM
+    runs of seeded trees (orders 1-3, Re_H 100-800, I_u 0 and 8 %), checked on
+    held-out seeds, then swept over n_trees seeded trees (orders 1-6 in turn) at
+    25 Re_H from 1e3 to 1e9 on the matrix cores, with the analytic model
+    (Eqs. (2), (4)) on the same trees."""
+    from paper_2603_27954_amd import surrogate as S
+    stream = STREAM
+    t0 = time.time()
+
+    def runs(seeds_by_order):
+        out = []
+        for order, seeds in seeds_by_order.items():
+            for re_h in (100.0, 200.0, 400.0, 800.0):
+                for iu in (0.0, 0.08):
+                    for seed in seeds:
+                        out.append(S.lbm_samples(order, seed, re_h, iu, stream=stream.cuda_stream))
+        return out
+
+    train = runs({1: range(1000, 1016), 2: range(1100, 1108), 3: range(1200, 1204)})
+    held = runs({1: range(1057, 1060), 2: range(1127, 1130), 3: range(1212, 1215)})
+    lbm_s = time.time() - t0
+    X = np.concatenate([r["feat"] for r in train])
+    Y = np.concatenate([r["y"] for r in train])
+    m = lt.Mlp(seed=3, stream=stream.cuda_stream)
+    m.set_scaling(X.mean(0), np.maximum(X.std(0), 1e-3), Y.mean(), Y.std())
+    t1 = time.time()
+    losses = m.train(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), epochs=40, batch=256, lr=2e-3,
+                     seed=17)
+    train_s = time.time() - t1
+    err = [abs(S.tree_cd(m, r["feat"], r["ld"], r["area_x"]) - r["cd"]) / r["cd"] for r in held]
+    re_d = 10.0 ** X[:, 0]
+    env = (float(re_d.min()), float(re_d.max()))
+    params = lt.tree_params(3, 1, 1.0, 0.3, [0.7] * 3, [0.7] * 3, [0.0, 120.0, 240.0], [35.0] * 3, [90.0] * 3,
+                            jitter=5.0, seed=0)
+    re_h = 10.0 ** np.linspace(3.0, 9.0, 25)
+    orders = 1 + (np.arange(n_trees) % 6)
+    sweep_ms = analytic_ms = area_ms = gen_s = 0.0
+    n_branch = 0
+    sum_s = np.zeros(len(re_h))
+    sum_a = np.zeros(len(re_h))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for c0 in range(0, n_trees, chunk):
+        o = orders[c0:c0 + chunk]
+        tg = time.time()
+        rec, start = lt.tree_batch(params, 1 + c0, o)
+        gen_s += time.time() - tg
+        rd, sd = torch.from_numpy(rec).cuda(), torch.from_numpy(start).cuda()
+        area = torch.empty(len(o), dtype=torch.float32, device="cuda")
+        cd = torch.empty((len(o), len(re_h)), dtype=torch.float32, device="cuda")
+        cda = torch.empty_like(cd)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        lt.frontal_area(rd, sd, 1.0 / 256, area, stream.cuda_stream)
+        e1.record(stream)
+        e1.synchronize()
+        area_ms += e0.elapsed_time(e1)
+        e0.record(stream)
+        m.sweep(rd, sd, area, cd, re_h, 0.0, env)
+        e1.record(stream)
+        e1.synchronize()
+        sweep_ms += e0.elapsed_time(e1)
+        e0.record(stream)
+        lt.analytic_sweep(rd, sd, area, cda, re_h, 0.0, stream.cuda_stream)
+        e1.record(stream)
+        e1.synchronize()
+        analytic_ms += e0.elapsed_time(e1)
+        n_branch += len(rec)
+        sum_s += cd.double().sum(0).cpu().numpy()
+        sum_a += cda.double().sum(0).cpu().numpy()
+        del rd, sd, area, cd, cda
+    inferences = n_branch * len(re_h)
+    tflops = MLP_FLOP * inferences / (sweep_ms * 1e-3) / 1e12
+    m.close()
+    return {
+        "training": {"lbm_runs": len(train), "samples": int(len(X)), "lbm_seconds": round(lbm_s, 1),
+                     "epochs": 40, "train_seconds": round(train_s, 2), "final_loss": float(losses[-1]),
+                     "re_d_envelope": [round(env[0], 2), round(env[1], 1)]},
+        "held_out": {"runs": len(held), "cd_rel_err_mean": round(float(np.mean(err)), 4),
+                     "cd_rel_err_max": round(float(np.max(err)), 4)},
+        "sweep": {"trees": n_trees, "branches": n_branch, "re_h": [1e3, 1e9, len(re_h)], "inferences": inferences,
+                  "surrogate_ms": round(sweep_ms, 2), "inferences_per_s": round(inferences / (sweep_ms * 1e-3), 1),
+                  "analytic_ms": round(analytic_ms, 2), "frontal_area_ms": round(area_ms, 2),
+                  "host_tree_generation_s": round(gen_s, 2),
+                  "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4),
+                               "flop_per_inference": MLP_FLOP, "dtype": "bf16 operands, fp32 accumulate"},
+                  "mean_cd_surrogate": [round(v / n_trees, 4) for v in sum_s],
+                  "mean_cd_analytic": [round(v / n_trees, 4) for v in sum_a]},
+    }
+
+
 def cpu_leg(lt, arr, nsteps):
     import oracle as O
     b = lt.branches_to_numpy(arr)
@@ -206,6 +302,9 @@ def main():
     ap.add_argument("--no-amr", action="store_true", help="skip the three-level AMR leg")
     ap.add_argument("--amr-steps", type=int, default=40)
     ap.add_argument("--amr-only", action="store_true", help="run only the three-level AMR leg (profiling)")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the drag-surrogate leg")
+    ap.add_argument("--surrogate-trees", type=int, default=1_000_000)
+    ap.add_argument("--surrogate-only", action="store_true", help="run only the drag-surrogate leg (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 512 MiB device copy (torch) as the reference dispatch "
                          "for the HBM byte counters")
@@ -235,6 +334,9 @@ def main():
     TUNE = not args.no_tune
     if args.amr_only:
         print(json.dumps({"amr_3level": amr_leg(lt, torch, args.amr_steps, 4)}), flush=True)
+        return
+    if args.surrogate_only:
+        print(json.dumps({"surrogate": surrogate_leg(lt, torch, args.surrogate_trees)}), flush=True)
         return
     arr = build_tree(lt)
     r32 = r16 = None
@@ -299,6 +401,8 @@ def main():
                          "seeded tree H=256, Re_H=2e4, FP32, bands 16/32 + 1H wake")
         a["coarse_steps"] = args.amr_steps
         out["amr_3level"] = a
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg(lt, torch, args.surrogate_trees)
     print(json.dumps(out), flush=True)
 
 

@@ -333,6 +333,8 @@ typedef struct {
     int64_t leaf_cells[4];        /* leaf cells per level (solid included) */
     int64_t collided_cells[4];    /* cells collided per level sub-step (leaf + band + ghost) */
     int64_t updated_cells[4];     /* leaf fluid cells per level (what MLUPS counts) */
+    int64_t work_blocks[4];       /* blocks (dense: 256-cell tiles) holding cells to collide */
+    int64_t work_tiles[4];        /* of those, B^2-cell z-slices holding cells to collide */
     int64_t links, solid_cells;
     int64_t pop_bytes;            /* population storage of every level in d->storage */
 } lbm_plan;

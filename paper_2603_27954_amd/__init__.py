@@ -57,7 +57,8 @@ class RefineDesc(C.Structure):
 class Plan(C.Structure):
     _fields_ = [("levels", C.c_int32), ("block_edge", C.c_int32), ("lattice", (C.c_int32 * 3) * 4),
                 ("blocks", C.c_int64 * 4), ("leaf_cells", C.c_int64 * 4), ("collided_cells", C.c_int64 * 4),
-                ("updated_cells", C.c_int64 * 4), ("links", C.c_int64), ("solid_cells", C.c_int64),
+                ("updated_cells", C.c_int64 * 4), ("work_blocks", C.c_int64 * 4), ("work_tiles", C.c_int64 * 4),
+                ("links", C.c_int64), ("solid_cells", C.c_int64),
                 ("pop_bytes", C.c_int64)]
 
 
@@ -427,7 +428,8 @@ def plan_levels(branches, refine=None, maps=False, **desc):
     res = {"levels": out.levels, "block_edge": out.block_edge,
            "lattice": [tuple(out.lattice[l]) for l in range(L)], "blocks": list(out.blocks[:L]),
            "leaf_cells": list(out.leaf_cells[:L]), "collided_cells": list(out.collided_cells[:L]),
-           "updated_cells": list(out.updated_cells[:L]),
+           "updated_cells": list(out.updated_cells[:L]), "work_blocks": list(out.work_blocks[:L]),
+           "work_tiles": list(out.work_tiles[:L]),
            "links": out.links, "solid_cells": out.solid_cells, "pop_bytes": out.pop_bytes}
     if maps:
         res["maps"] = arrs

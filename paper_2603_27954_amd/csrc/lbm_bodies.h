@@ -300,13 +300,15 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return t;
 }
 
-// Per-branch sum of the link forces of segment b (links sorted by branch) in
-// a fixed order (lane tree, then waves in order): thread 0 stores it in
-// sample[3b..3b+2] and adds it to acc_branch.
-__device__ __forceinline__ void branch_segment_sum(const float *lforce, const int *seg, int b, double *sample,
-                                                   double *acc_branch, double *sh)
+// The links are sorted by branch and each branch's run of links is cut into
+// pieces of at most LINK_PIECE links.  One work-group sums one piece in a
+// fixed order (lane tree, then waves in order) and thread 0 stores the sum in
+// piece_sum[3p .. 3p + 2].
+
+__device__ __forceinline__ void link_piece_sum(const float *lforce, const int *pstart, int p, double *piece_sum,
+                                               double *sh)
 {
-    const int s0 = seg[b], s1 = seg[b + 1];
+    const int s0 = pstart[p], s1 = pstart[p + 1];
     double v[3] = {0.0, 0.0, 0.0};
     for (int l = s0 + (int)threadIdx.x; l < s1; l += 256) {
         v[0] += (double)lforce[3 * (size_t)l];
@@ -315,29 +317,44 @@ __device__ __forceinline__ void branch_segment_sum(const float *lforce, const in
     }
     for (int a = 0; a < 3; ++a) {
         const double t = block_sum<256>(v[a], sh);
-        if (threadIdx.x == 0) {
-            sample[3 * b + a] = t;
-            acc_branch[3 * b + a] += t;
-        }
+        if (threadIdx.x == 0)
+            piece_sum[3 * p + a] = t;
     }
 }
 
-// Total of the per-branch sums in branch order (one thread): added to
-// acc_total and appended to the sample ring at the device-held position
-// ring_pos, which a replayed graph or persistent launch advances itself.
-__device__ __forceinline__ void branch_total(const double *sample, int nseg, double *acc_total, double *ring,
-                                             unsigned long long *ring_pos)
+// Per-branch sums from the pieces of each branch, in piece order (the pieces of
+// branch s are segp[s] .. segp[s + 1]), stored in sample and added to
+// acc_branch; then the total over the branches in branch order (thread 0)
+// is added to acc_total and appended to the sample ring at the device-held
+// position ring_pos, which a replayed graph advances itself.  Called by the
+// whole work-group.
+__device__ __forceinline__ void branch_totals(const double *piece_sum, const int *segp, int nseg, double *sample,
+                                              double *acc_branch, double *acc_total, double *ring,
+                                              unsigned long long *ring_pos)
 {
-    double t[3] = {0.0, 0.0, 0.0};
-    for (int i = 0; i < nseg; ++i)
-        for (int a = 0; a < 3; ++a)
-            t[a] += __builtin_nontemporal_load(&sample[3 * i + a]);
-    const unsigned long long slot = *ring_pos % RING;
-    for (int a = 0; a < 3; ++a) {
-        acc_total[a] += t[a];
-        ring[3 * slot + a] = t[a];
+    for (int s = threadIdx.x; s < nseg; s += blockDim.x) {
+        double t[3] = {0.0, 0.0, 0.0};
+        for (int q = segp[s]; q < segp[s + 1]; ++q)
+            for (int a = 0; a < 3; ++a)
+                t[a] += __builtin_nontemporal_load(&piece_sum[3 * q + a]);
+        for (int a = 0; a < 3; ++a) {
+            sample[3 * s + a] = t[a];
+            acc_branch[3 * s + a] += t[a];
+        }
     }
-    *ring_pos += 1ull;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < nseg; ++i)
+            for (int a = 0; a < 3; ++a)
+                t[a] += sample[3 * i + a];
+        const unsigned long long slot = *ring_pos % RING;
+        for (int a = 0; a < 3; ++a) {
+            acc_total[a] += t[a];
+            ring[3 * slot + a] = t[a];
+        }
+        *ring_pos += 1ull;
+    }
 }
 
 // ---------------------------------------------------------------------------

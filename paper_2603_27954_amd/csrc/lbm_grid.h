@@ -33,8 +33,11 @@ struct lbm_grid {
     uint8_t *d_dir = nullptr;
     float *d_q = nullptr;
     int n_links = 0;
-    int *d_seg = nullptr;
-    int nseg = 0;
+    int nseg = 0;                   // branches + 1 (links owned by no branch)
+    int *d_pstart = nullptr;        // link pieces: npieces + 1 offsets
+    int *d_segp = nullptr;          // pieces of segment s: segp[s] .. segp[s + 1]
+    int npieces = 0;
+    double *d_piece_sum = nullptr;  // 3 per piece
     float *d_lforce = nullptr;
     double *d_sample = nullptr, *d_acc_branch = nullptr, *d_acc_total = nullptr, *d_ring = nullptr;
     unsigned *d_counter = nullptr;

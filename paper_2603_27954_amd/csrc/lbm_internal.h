@@ -16,6 +16,8 @@ constexpr int NB_OUTLET = -3;  // x >= nx: zero-gradient ghost plane
 constexpr uint32_t FULL_MASK = 0xFFFFFFFFu;
 // force samples kept on the device (ring of total-force triples)
 constexpr int RING = 65536;
+// links per piece of the force reduction (one work-group each)
+constexpr int LINK_PIECE = 2048;
 
 // Arguments of the collide-and-stream kernel of one level.
 constexpr int DENSE_TILE = 256;  // cells per work item of a dense level
@@ -82,8 +84,9 @@ struct Phase {
     const float *m0, *m1;
     float *out;
     const float *lforce;
-    const int *seg;
-    int nseg;
+    const int *pstart, *segp;
+    int npieces, nseg;
+    double *piece_sum;
     double *sample, *acc_branch, *acc_total, *ring;
     unsigned long long *ring_pos;
 };
@@ -138,9 +141,11 @@ hipError_t launch_links(int storage, int odd_done, const LinkArgs &a, hipStream_
 hipError_t launch_init(int unit, int storage, void *pop, size_t dir_elems, const uint2 *work,
                        int n, const uint32_t *masks, float u_in, hipStream_t s);
 hipError_t launch_fill_sink_and_all(int storage, void *pop, size_t dir_elems, hipStream_t s);
-hipError_t launch_branch_reduce(const float *lforce, const int *seg, int nseg, double *sample,
-                                double *acc_branch, double *acc_total, double *ring,
-                                unsigned long long *ring_pos, unsigned *counter, hipStream_t s);
+// force sums of one sample: link pieces (pstart, npieces + 1 offsets) summed by
+// one work-group each, then per branch (pieces segp[s] .. segp[s + 1]) and in total
+hipError_t launch_branch_reduce(const float *lforce, const int *pstart, int npieces, const int *segp, int nseg,
+                                double *piece_sum, double *sample, double *acc_branch, double *acc_total,
+                                double *ring, unsigned long long *ring_pos, unsigned *counter, hipStream_t s);
 // element addresses (dense: x + nx (y + ny z); blocks: block * B^3 + local)
 hipError_t launch_gather(int B, int storage, int odd, const CollideArgs &a, const uint32_t *cells,
                          int n, double *out_f, size_t out_stride, hipStream_t s);

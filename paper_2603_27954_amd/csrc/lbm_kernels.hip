@@ -100,36 +100,40 @@ hipError_t launch_links(int storage, int odd_done, const LinkArgs &a, hipStream_
     return hipGetLastError();
 }
 
-// One work-group per branch segment; the last work-group to finish forms the
-// total (branch order) and resets the arrival counter.
-__global__ void __launch_bounds__(256) k_branch_reduce(const float *lforce, const int *seg, int nseg,
-                                                       double *sample, double *acc_branch,
-                                                       double *acc_total, double *ring,
-                                                       unsigned long long *ring_pos, unsigned *counter)
+// One work-group per link piece; the last work-group to finish forms the
+// per-branch sums and the total and resets the arrival counter.
+__global__ void __launch_bounds__(256) k_branch_reduce(const float *lforce, const int *pstart, int npieces,
+                                                       const int *segp, int nseg, double *piece_sum,
+                                                       double *sample, double *acc_branch, double *acc_total,
+                                                       double *ring, unsigned long long *ring_pos,
+                                                       unsigned *counter)
 {
     __shared__ double sh[4];
     __shared__ bool last;
-    branch_segment_sum(lforce, seg, blockIdx.x, sample, acc_branch, sh);
+    link_piece_sum(lforce, pstart, blockIdx.x, piece_sum, sh);
     if (threadIdx.x == 0) {
         __threadfence();
-        last = atomicAdd(counter, 1u) == (unsigned)nseg - 1;
+        last = atomicAdd(counter, 1u) == (unsigned)npieces - 1;
     }
     __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        branch_total(sample, nseg, acc_total, ring, ring_pos);
-        *counter = 0u;
+    if (last) {
+        if (threadIdx.x == 0)
+            __threadfence();
+        __syncthreads();
+        branch_totals(piece_sum, segp, nseg, sample, acc_branch, acc_total, ring, ring_pos);
+        if (threadIdx.x == 0)
+            *counter = 0u;
     }
 }
 
-hipError_t launch_branch_reduce(const float *lforce, const int *seg, int nseg, double *sample,
-                                double *acc_branch, double *acc_total, double *ring,
-                                unsigned long long *ring_pos, unsigned *counter, hipStream_t s)
+hipError_t launch_branch_reduce(const float *lforce, const int *pstart, int npieces, const int *segp, int nseg,
+                                double *piece_sum, double *sample, double *acc_branch, double *acc_total,
+                                double *ring, unsigned long long *ring_pos, unsigned *counter, hipStream_t s)
 {
-    if (nseg == 0)
+    if (npieces == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_branch_reduce, dim3(nseg), dim3(256), 0, s, lforce, seg, nseg, sample,
-                       acc_branch, acc_total, ring, ring_pos, counter);
+    hipLaunchKernelGGL(k_branch_reduce, dim3(npieces), dim3(256), 0, s, lforce, pstart, npieces, segp, nseg,
+                       piece_sum, sample, acc_branch, acc_total, ring, ring_pos, counter);
     return hipGetLastError();
 }
 

@@ -83,11 +83,10 @@ __device__ __forceinline__ void run_item(const Phase &p, int it, int *nb, double
             link_update<S, false>(p.la, t);
         break;
     case PH_BRANCH_SUM:
-        branch_segment_sum(p.lforce, p.seg, it, p.sample, p.acc_branch, sh);
+        link_piece_sum(p.lforce, p.pstart, it, p.piece_sum, sh);
         break;
     case PH_BRANCH_TOTAL:
-        if (threadIdx.x == 0)
-            branch_total(p.sample, p.nseg, p.acc_total, p.ring, p.ring_pos);
+        branch_totals(p.piece_sum, p.segp, p.nseg, p.sample, p.acc_branch, p.acc_total, p.ring, p.ring_pos);
         break;
     case PH_AMR_MOMENTS:
         if (p.odd)

@@ -213,28 +213,30 @@ static lbm_status finest_links(lbm_grid *g, int odd_done)
     }
     if (sample) {
         // the device ring position advances exactly when the reduction runs
-        if (g->n_links > 0 && g->nseg > 0) {
+        if (g->n_links > 0 && g->npieces > 0) {
             if (g->rec) {
                 Phase p = new_phase(PH_BRANCH_SUM);
                 p.lforce = g->d_lforce;
-                p.seg = g->d_seg;
-                p.nseg = g->nseg;
-                p.sample = g->d_sample;
-                p.acc_branch = g->d_acc_branch;
-                p.items = g->nseg;
+                p.pstart = g->d_pstart;
+                p.npieces = g->npieces;
+                p.piece_sum = g->d_piece_sum;
+                p.items = g->npieces;
                 g->rec->push_back(p);
                 Phase t = new_phase(PH_BRANCH_TOTAL);
-                t.sample = g->d_sample;
+                t.piece_sum = g->d_piece_sum;
+                t.segp = g->d_segp;
                 t.nseg = g->nseg;
+                t.sample = g->d_sample;
+                t.acc_branch = g->d_acc_branch;
                 t.acc_total = g->d_acc_total;
                 t.ring = g->d_ring;
                 t.ring_pos = g->d_ring_pos;
                 t.items = 1;
                 g->rec->push_back(t);
             } else {
-                HIPX(g, launch_branch_reduce(g->d_lforce, g->d_seg, g->nseg, g->d_sample, g->d_acc_branch,
-                                             g->d_acc_total, g->d_ring, g->d_ring_pos, g->d_counter,
-                                             g->stream));
+                HIPX(g, launch_branch_reduce(g->d_lforce, g->d_pstart, g->npieces, g->d_segp, g->nseg,
+                                             g->d_piece_sum, g->d_sample, g->d_acc_branch, g->d_acc_total,
+                                             g->d_ring, g->d_ring_pos, g->d_counter, g->stream));
             }
             g->ring_count++;
         }
@@ -896,10 +898,20 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
         }
         for (int s = 0; s < g->nseg; ++s)
             seg[s + 1] += seg[s];
+        // pieces of at most LINK_PIECE links within each branch's run
+        std::vector<int> pstart(1, 0), segp(g->nseg + 1, 0);
+        for (int s = 0; s < g->nseg; ++s) {
+            for (int l = seg[s]; l < seg[s + 1]; l += LINK_PIECE)
+                pstart.push_back(std::min(l + LINK_PIECE, seg[s + 1]));
+            segp[s + 1] = (int)pstart.size() - 1;
+        }
+        g->npieces = (int)pstart.size() - 1;
         g->n_links = nl;
         if ((st = upload(g, &g->d_af, af)) != LBM_OK || (st = upload(g, &g->d_ap, ap)) != LBM_OK ||
             (st = upload(g, &g->d_am, am)) != LBM_OK || (st = upload(g, &g->d_dir, dr)) != LBM_OK ||
-            (st = upload(g, &g->d_q, q)) != LBM_OK || (st = upload(g, &g->d_seg, seg)) != LBM_OK)
+            (st = upload(g, &g->d_q, q)) != LBM_OK || (st = upload(g, &g->d_pstart, pstart)) != LBM_OK ||
+            (st = upload(g, &g->d_segp, segp)) != LBM_OK ||
+            (st = dalloc(g, &g->d_piece_sum, (size_t)3 * std::max(g->npieces, 1))) != LBM_OK)
             return st;
         if ((st = dalloc(g, &g->d_lforce, (size_t)3 * std::max(nl, 1))) != LBM_OK ||
             (st = dalloc(g, &g->d_sample, (size_t)3 * g->nseg)) != LBM_OK ||
@@ -1323,6 +1335,16 @@ lbm_status lbm_plan_levels(const lbm_grid_desc *d, const lbm_branch *b, int32_t 
         out->leaf_cells[l] = v.leaf_cells;
         out->collided_cells[l] = v.collided_cells;
         out->updated_cells[l] = v.updated_cells;
+        out->work_blocks[l] = (int64_t)v.h_work.size();
+        const int unit = v.dense ? DENSE_TILE : B * B * B, slice = v.dense ? DENSE_TILE : B * B;
+        for (const uint2 &w : v.h_work) {
+            for (int t = 0; t < unit / slice; ++t) {
+                bool any = w.y == FULL_MASK;
+                for (int c = t * slice; c < (t + 1) * slice && !any; ++c)
+                    any = (v.h_masks[(size_t)w.y * (unit / 32) + (c >> 5)] >> (c & 31)) & 1u;
+                out->work_tiles[l] += any;
+            }
+        }
         const size_t elems = v.dense ? (size_t)v.nx * v.ny * v.nz : (size_t)(v.nb + 1) * B * B * B;
         out->pop_bytes += (int64_t)(elems * 27 * eb);
         out->lattice[l][0] = v.nbx;
