@@ -90,7 +90,7 @@ def run_storage(lt, torch, arr, storage, steps, warmup, drag_every):
     g.close()
     return {"ms": ms, "cells": cells, "mlups": cells * steps / (ms * 1e-3) / 1e6, "kernel": kt,
             "links": info["links"], "cd_mean": d["cd"], "device_bytes": info["device_bytes"],
-            "tune": {"occ_even": info["occ_even"], "occ_odd": info["occ_odd"]}}
+            "tune": {"occ_even": info["occ_even"], "occ_odd": info["occ_odd"], "xcd_group": info["xcd_group"]}}
 
 
 def cd_after(lt, torch, arr, storage, nsteps):

@@ -145,6 +145,7 @@ typedef struct {
     int32_t persist_wgs;      /* work-groups of the persistent launch (all resident) */
     int32_t persist_graph;    /* 1: the persistent launch replays from a captured graph */
     int64_t collided_cells[4];/* cells collided per level sub-step (leaf + band + ghost, solid excluded) */
+    int32_t xcd_group;        /* consecutive collide tiles per XCD run (1 = plain dispatch order) */
 } lbm_info;
 
 /* ---- lifecycle ------------------------------------------------------------ */

@@ -74,7 +74,8 @@ class Info(C.Structure):
                 ("omega1", C.c_double * 4), ("height", C.c_double), ("area_x", C.c_double),
                 ("nu_finest", C.c_double), ("device_bytes", C.c_size_t), ("tile_cells", C.c_int32),
                 ("threads", C.c_int32), ("occ_even", C.c_int32), ("occ_odd", C.c_int32),
-                ("persist_wgs", C.c_int32), ("persist_graph", C.c_int32), ("collided_cells", C.c_int64 * 4)]
+                ("persist_wgs", C.c_int32), ("persist_graph", C.c_int32), ("collided_cells", C.c_int64 * 4),
+                ("xcd_group", C.c_int32)]
 
 
 _lib = None
@@ -503,7 +504,7 @@ class Grid:
                 "nu_finest": i.nu_finest, "device_bytes": i.device_bytes, "tile_cells": i.tile_cells,
                 "threads": i.threads, "occ_even": i.occ_even, "occ_odd": i.occ_odd,
                 "persist_wgs": i.persist_wgs, "persist_graph": i.persist_graph,
-                "collided_cells": list(i.collided_cells)}
+                "collided_cells": list(i.collided_cells), "xcd_group": i.xcd_group}
 
     def get_populations(self, level=0):
         nx, ny, nz = self.level_shape(level)

@@ -47,6 +47,7 @@ struct lbm_grid {
     int64_t coarse_steps = 0, finest_steps = 0;
     int threads = 256, tile = 0;
     int occ_even = 0, occ_odd = 0;  // waves per SIMD cap of the collide kernel (0 = none)
+    int xcd_group = 1;              // tiles per XCD run of the collide kernels
     size_t device_bytes = 0;
     std::vector<void *> allocs;
     unsigned long long *d_ring_pos = nullptr;  // device copy of ring_count (slot of the next sample)

@@ -30,6 +30,7 @@ struct CollideArgs {
     const uint32_t *masks;    // B^3/32 words per masked block
     int n_work;
     int parts;                // work-groups per block (block layout)
+    int xcd_group;            // consecutive tiles per XCD run (1 = plain order)
     int dense;                // 1: level stored as x-pencils over its whole box
     int nx;                   // level box along x (cells)
     float om1, om2;

@@ -22,17 +22,33 @@
 
 namespace lbm {
 
+// Work-groups are dispatched round-robin over the 8 XCDs (work-group b runs on
+// XCD b % 8), and each XCD has its own L2.  With group size K (a.xcd_group),
+// work-group b takes item s 8K + (b % 8) K + j, where s = b / 8K and
+// j = (b % 8K) / 8.  Each XCD then walks runs of K consecutive tiles, so the
+// cache line two neighbouring tiles of a run share (the x-shifted boundary of
+// the odd step) is fetched into one L2 rather than two.  The runs interleave
+// over the XCDs, which keeps the concurrently active addresses compact.  K = 1
+// is the plain order.  The grid is a multiple of 8K; surplus work-groups exit.
+__device__ __forceinline__ int xcd_item(int b, int k)
+{
+    const int span = 8 * k, s = b / span, r = b - s * span;
+    return s * span + (r & 7) * k + (r >> 3);
+}
+
 template <typename S, bool ODD, bool ROWWAVE>
 __global__ void __launch_bounds__(256) k_collide_dense(const CollideArgs a)
 {
-    collide_dense_item<S, ODD, ROWWAVE>(a, blockIdx.x);
+    collide_dense_item<S, ODD, ROWWAVE>(a, xcd_item(blockIdx.x, a.xcd_group));
 }
 
 template <int B, typename S, bool ODD>
 __global__ void __launch_bounds__(256) k_collide_block(const CollideArgs a)
 {
     __shared__ int nb[27];
-    collide_block_item<B, S, ODD>(a, blockIdx.x, nb);
+    const int wg = xcd_item(blockIdx.x, a.xcd_group);
+    if (wg < a.n_work * a.parts)
+        collide_block_item<B, S, ODD>(a, wg, nb);
 }
 
 template <typename S>
@@ -40,16 +56,19 @@ static hipError_t launch_collide_s(int B, int odd, const CollideArgs &a, int thr
 {
     if (a.n_work == 0)
         return hipSuccess;
+    // grids rounded up to a multiple of 8K (see xcd_item); surplus work-groups exit
+    const int span = 8 * a.xcd_group;
     if (a.dense) {
+        const dim3 grid((a.n_work + span - 1) / span * span);
         if (!odd)
-            hipLaunchKernelGGL((k_collide_dense<S, false, false>), dim3(a.n_work), dim3(DENSE_TILE), lds, s, a);
+            hipLaunchKernelGGL((k_collide_dense<S, false, false>), grid, dim3(DENSE_TILE), lds, s, a);
         else if (a.nx % 64 == 0)
-            hipLaunchKernelGGL((k_collide_dense<S, true, true>), dim3(a.n_work), dim3(DENSE_TILE), lds, s, a);
+            hipLaunchKernelGGL((k_collide_dense<S, true, true>), grid, dim3(DENSE_TILE), lds, s, a);
         else
-            hipLaunchKernelGGL((k_collide_dense<S, true, false>), dim3(a.n_work), dim3(DENSE_TILE), lds, s, a);
+            hipLaunchKernelGGL((k_collide_dense<S, true, false>), grid, dim3(DENSE_TILE), lds, s, a);
         return hipGetLastError();
     }
-    const dim3 grid(a.n_work * a.parts), blk(threads);
+    const dim3 grid((a.n_work * a.parts + span - 1) / span * span), blk(threads);
     if (B == 16) {
         if (odd)
             hipLaunchKernelGGL((k_collide_block<16, S, true>), grid, blk, lds, s, a);

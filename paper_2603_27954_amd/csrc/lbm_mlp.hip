@@ -9,11 +9,12 @@
 // Training is deterministic: each work-group sums the gradient of a fixed
 // chunk of samples in a fixed order, and the chunks are added in chunk order.
 //
-// Inference maps 32 samples onto the N dimension of the 32x32x8 BF16 MFMA, with
-// neurons on M.  The 16 accumulator registers of lane l hold rows
-// 8 (i / 4) + 4 (l / 32) + (i % 4) of column l % 32.  That is exactly the B
-// operand (k = 4 (l / 32) + j, column l % 32) of the next layer's k-steps, so
-// the hidden activations pass from layer to layer without leaving the lane.
+// Inference maps 32 samples onto the N dimension of the 32x32x16 BF16 MFMA
+// (gfx950), with neurons on M.  The 16 accumulator registers of lane l hold
+// rows 8 (i / 4) + 4 (l / 32) + (i % 4) of column l % 32.  Taking the next
+// layer's K-slots in the matching (permuted) neuron order makes those registers
+// its B operands, so the hidden activations pass from layer to layer without
+// leaving the lane.
 #include "lbm_mlp.h"
 
 #include <algorithm>
@@ -209,52 +210,61 @@ __global__ void k_mlp_round(MlpDev d)
 // inference on the matrix cores
 // ---------------------------------------------------------------------------
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ int acc_row(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
 
-// Network weights held in registers by one wave (A operands) and the biases
-// and output weights in LDS.
+__device__ __forceinline__ __bf16 bf16_of(uint32_t bits) { return __builtin_bit_cast(__bf16, (uint16_t)bits); }
+
+// Network weights held in registers by one wave (A operands of the
+// 32x32x16 BF16 MFMA: lane l holds row l % 32 and the 8 K-slots
+// 8 (l / 32) .. 8 (l / 32) + 7), and the biases and output weights in LDS.
+// Layer 2's K-slot (s, h, j) of K-step s in 0..3 stands for input neuron
+// 16 s + 4 h + (j < 4 ? j : j + 4).  These are the neurons that lane half h
+// holds in accumulator registers 8 (s % 2) .. 8 (s % 2) + 7 of layer 1's tile
+// s / 2, so the B operands are those registers as they are.
 struct MlpRegs {
-    bf16x4 a1[2], a2[2][8];
+    bf16x8 a1[2], a2[2][4];
 };
+
+__device__ __forceinline__ int l2_neuron(int s, int h, int j) { return 16 * s + 4 * h + (j < 4 ? j : j + 4); }
 
 __device__ __forceinline__ void load_regs(const MlpDev &d, MlpRegs &r, int lane)
 {
-    const int m = lane & 31, kh = 4 * (lane >> 5);
+    const int m = lane & 31, h = lane >> 5;
     for (int t = 0; t < 2; ++t) {
-        r.a1[t] = *reinterpret_cast<const bf16x4 *>(d.w1b + (32 * t + m) * 8 + kh);
-        for (int s = 0; s < 8; ++s)
-            r.a2[t][s] = *reinterpret_cast<const bf16x4 *>(d.w2b + (32 * t + m) * 64 + 8 * s + kh);
+        for (int j = 0; j < 8; ++j)
+            r.a1[t][j] = bf16_of(h == 0 ? d.w1b[(32 * t + m) * 8 + j] : 0u);
+        for (int s = 0; s < 4; ++s)
+            for (int j = 0; j < 8; ++j)
+                r.a2[t][s][j] = bf16_of(d.w2b[(32 * t + m) * 64 + l2_neuron(s, h, j)]);
     }
 }
 
 // y (scaled output units, before b3) of the sample of column lane % 32, given
-// its scaled features in b1 (B operand of the first layer); sb = b1[64],
-// b2[64], w3[64] in LDS.  Both lanes of a column return the same value.
-__device__ __forceinline__ float mlp_tile(const MlpRegs &r, bf16x4 b1, const float *sb, int lane)
+// its scaled features as the B operand of the first layer (lane half 0 holds
+// features 0..4 and zeros, half 1 zeros); sb = b1[64], b2[64], w3[64] in LDS.
+// Both lanes of a column return the same value.
+__device__ __forceinline__ float mlp_tile(const MlpRegs &r, bf16x8 b1, const float *sb, int lane)
 {
     f32x16 c1[2];
     for (int t = 0; t < 2; ++t) {
         for (int i = 0; i < 16; ++i)
             c1[t][i] = sb[32 * t + acc_row(i, lane)];
-        c1[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(r.a1[t], b1, c1[t], 0, 0, 0);
+        c1[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a1[t], b1, c1[t], 0, 0, 0);
     }
-    bf16x4 b2[8];
-    for (int t = 0; t < 2; ++t)
-        for (int q = 0; q < 4; ++q)
-            for (int j = 0; j < 4; ++j) {
-                const float h = fmaxf(c1[t][4 * q + j], 0.0f);
-                b2[4 * t + q][j] = (short)bf16_bits(h);
-            }
+    bf16x8 b2[4];
+    for (int s = 0; s < 4; ++s)
+        for (int j = 0; j < 8; ++j)
+            b2[s][j] = bf16_of(bf16_bits(fmaxf(c1[s >> 1][8 * (s & 1) + j], 0.0f)));
     float y = 0.0f;
     for (int t = 0; t < 2; ++t) {
         f32x16 c2;
         for (int i = 0; i < 16; ++i)
             c2[i] = sb[64 + 32 * t + acc_row(i, lane)];
-        for (int s = 0; s < 8; ++s)
-            c2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(r.a2[t][s], b2[s], c2, 0, 0, 0);
+        for (int s = 0; s < 4; ++s)
+            c2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a2[t][s], b2[s], c2, 0, 0, 0);
         for (int i = 0; i < 16; ++i)
             y = fmaf(sb[128 + 32 * t + acc_row(i, lane)], fmaxf(c2[i], 0.0f), y);
     }
@@ -286,13 +296,13 @@ __global__ void __launch_bounds__(256) k_mlp_predict(MlpDev d, const float *x, i
     const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t tile = wave; tile < tiles; tile += waves) {
         const int64_t row = tile * 32 + (lane & 31);
-        bf16x4 b1;
-        for (int j = 0; j < 4; ++j) {
-            const int k = 4 * (lane >> 5) + j;
+        bf16x8 b1;
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * (lane >> 5) + j;
             float v = 0.0f;
             if (k < MLP_IN && row < n)
                 v = (x[row * MLP_IN + k] - mean[k]) * inv[k];
-            b1[j] = (short)bf16_bits(v);
+            b1[j] = bf16_of(bf16_bits(v));
         }
         const float out = mlp_tile(r, b1, sb, lane);
         if (lane < 32 && row < n)
@@ -339,7 +349,7 @@ __global__ void __launch_bounds__(64) k_tree_sweep(MlpDev d, SweepArgs a)
     const int64_t b0 = a.tree_start[tree], b1 = a.tree_start[tree + 1];
     const float b3 = d.wr[MLP_B3], ym = d.sc[10], ys = d.sc[11];
     const float ln_rc = logf(a.re_cr), inv = 1.0f / a.area[tree];
-    const int kh = 4 * (lane >> 5);
+    const bool feat_lane = lane < 32;  // lane half 0 carries the features
     for (int q = 0; q < a.n_re; ++q) {
         float acc = 0.0f;
         for (int64_t t0 = b0; t0 < b1; t0 += 32) {
@@ -348,12 +358,10 @@ __global__ void __launch_bounds__(64) k_tree_sweep(MlpDev d, SweepArgs a)
             const float *rc = a.rec + (valid ? br : b0) * SWEEP_REC;
             const float lre = a.lg_re[q] + rc[0];
             const float lc = fminf(fmaxf(lre, a.lg_lo), a.lg_hi);
-            // lanes < 32 carry features 0..3 of their branch, lanes >= 32 feature 4
-            bf16x4 bop;
-            for (int j = 0; j < 4; ++j) {
-                const int k = kh + j;
-                const float v = k == 0 ? lc : k == 1 ? rc[1] : k == 2 ? rc[2] : k == 3 ? a.intensity : rc[3];
-                bop[j] = (short)bf16_bits(k < MLP_IN ? (v - d.sc[k]) / d.sc[MLP_IN + k] : 0.0f);
+            bf16x8 bop;
+            for (int j = 0; j < 8; ++j) {
+                const float v = j == 0 ? lc : j == 1 ? rc[1] : j == 2 ? rc[2] : j == 3 ? a.intensity : rc[3];
+                bop[j] = bf16_of(bf16_bits((feat_lane && j < MLP_IN) ? (v - d.sc[j]) / d.sc[MLP_IN + j] : 0.0f));
             }
             float y = (mlp_tile(r, bop, sb, lane) + b3) * ys + ym;
             if (lre != lc)
@@ -422,25 +430,48 @@ __global__ void __launch_bounds__(256) k_frontal_area(const float *rec, const in
             area[tree] = -1.0f;
         return;
     }
-    for (int64_t b = b0; b < b1; ++b) {
+    // a branch's pixel box and the test of pixel p of it
+    struct Box {
+        float y0, z0, dy, dz, l2, rr;
+        int py0, pz0, wy, np;
+    };
+    auto box_of = [&](int64_t b) {
         const float *rc = rec + b * SWEEP_REC;
-        const float y0 = rc[5], z0 = rc[6], y1 = rc[7], z1 = rc[8], rr = rc[9];
-        const float dy = y1 - y0, dz = z1 - z0, l2 = dy * dy + dz * dz;
-        const int py0 = max(0, (int)floorf((fminf(y0, y1) - rr - ylo) / h));
-        const int py1 = min(ny - 1, (int)floorf((fmaxf(y0, y1) + rr - ylo) / h));
-        const int pz0 = max(0, (int)floorf((fminf(z0, z1) - rr - zlo) / h));
-        const int pz1 = min(nz - 1, (int)floorf((fmaxf(z0, z1) + rr - zlo) / h));
-        const int wy = py1 - py0 + 1, np = wy * (pz1 - pz0 + 1);
-        for (int p = tid; p < np; p += 256) {
-            const int py = py0 + p % wy, pz = pz0 + p / wy;
-            const float cy = ylo + (py + 0.5f) * h - y0, cz = zlo + (pz + 0.5f) * h - z0;
-            const float tt = l2 > 0.0f ? fminf(fmaxf((cy * dy + cz * dz) / l2, 0.0f), 1.0f) : 0.0f;
-            const float ey = cy - tt * dy, ez = cz - tt * dz;
-            if (ey * ey + ez * ez <= rr * rr) {
-                const int bit = pz * AREA_PIX + py;
-                atomicOr(&bits[bit >> 5], 1u << (bit & 31));
-            }
+        Box x;
+        x.y0 = rc[5], x.z0 = rc[6], x.rr = rc[9];
+        x.dy = rc[7] - x.y0, x.dz = rc[8] - x.z0, x.l2 = x.dy * x.dy + x.dz * x.dz;
+        x.py0 = max(0, (int)floorf((fminf(x.y0, rc[7]) - x.rr - ylo) / h));
+        const int py1 = min(ny - 1, (int)floorf((fmaxf(x.y0, rc[7]) + x.rr - ylo) / h));
+        x.pz0 = max(0, (int)floorf((fminf(x.z0, rc[8]) - x.rr - zlo) / h));
+        const int pz1 = min(nz - 1, (int)floorf((fmaxf(x.z0, rc[8]) + x.rr - zlo) / h));
+        x.wy = py1 - x.py0 + 1;
+        x.np = x.wy * (pz1 - x.pz0 + 1);
+        return x;
+    };
+    auto mark = [&](const Box &x, int p) {
+        const int py = x.py0 + p % x.wy, pz = x.pz0 + p / x.wy;
+        const float cy = ylo + (py + 0.5f) * h - x.y0, cz = zlo + (pz + 0.5f) * h - x.z0;
+        const float tt = x.l2 > 0.0f ? fminf(fmaxf((cy * x.dy + cz * x.dz) / x.l2, 0.0f), 1.0f) : 0.0f;
+        const float ey = cy - tt * x.dy, ez = cz - tt * x.dz;
+        if (ey * ey + ez * ez <= x.rr * x.rr) {
+            const int bit = pz * AREA_PIX + py;
+            atomicOr(&bits[bit >> 5], 1u << (bit & 31));
         }
+    };
+    constexpr int SMALL = 64;
+    // small branches: one thread each
+    for (int64_t b = b0 + tid; b < b1; b += 256) {
+        const Box x = box_of(b);
+        if (x.np <= SMALL)
+            for (int p = 0; p < x.np; ++p)
+                mark(x, p);
+    }
+    // large branches: the work-group shares each one
+    for (int64_t b = b0; b < b1; ++b) {
+        const Box x = box_of(b);
+        if (x.np > SMALL)
+            for (int p = tid; p < x.np; p += 256)
+                mark(x, p);
     }
     __syncthreads();
     float cnt = 0.0f;

@@ -94,6 +94,7 @@ static CollideArgs collide_args(lbm_grid *g, int l)
     a.nx = v.nx;
     const int cells = g->B * g->B * g->B;
     a.parts = std::max(1, cells / std::max(1, g->tile));
+    a.xcd_group = std::max(1, g->xcd_group);
     a.om1 = (float)v.om1;
     a.om2 = 1.0f;
     a.galilean = (g->d.flags & LBM_F_NO_GALILEAN) ? 0 : 1;
@@ -1119,6 +1120,7 @@ lbm_status lbm_get_info(const lbm_grid *g, lbm_info *out)
     out->occ_even = g->occ_even;
     out->occ_odd = g->occ_odd;
     out->persist_wgs = persist_grid_size(g);
+    out->xcd_group = g->xcd_group;
     bool pg = false;
     for (const lbm_grid::StepGraph &sg : g->graphs)
         pg = pg || (sg.d_phases && sg.exec);

@@ -1,8 +1,8 @@
 // Autotuner of the collide kernel: times candidate launch shapes over whole
 // coarse steps on the live grid -- work-group size and cells per work-group of
-// the block levels, and a cap on resident waves per SIMD (through reserved
-// LDS) for the even and the odd step -- keeps the fastest and restores the
-// grid state afterwards.  Choices are cached in a text file keyed by the grid
+// the block levels, a cap on resident waves per SIMD (through reserved LDS)
+// for the even and the odd step, and the run length of tiles per XCD -- keeps
+// the fastest and restores the grid state afterwards.  Choices are cached in a text file keyed by the grid
 // shape.
 #include <hip/hip_runtime.h>
 
@@ -26,7 +26,7 @@ std::string tune_key(const lbm_grid *g)
 }
 
 struct Choice {
-    int threads, tile, occ_even, occ_odd;
+    int threads, tile, occ_even, occ_odd, xcd;
 };
 
 bool cache_lookup(const char *path, const std::string &key, Choice *c)
@@ -39,7 +39,7 @@ bool cache_lookup(const char *path, const std::string &key, Choice *c)
     char k[200];
     Choice v{};
     bool hit = false;
-    while (std::fscanf(f, "%199s %d %d %d %d", k, &v.threads, &v.tile, &v.occ_even, &v.occ_odd) == 5)
+    while (std::fscanf(f, "%199s %d %d %d %d %d", k, &v.threads, &v.tile, &v.occ_even, &v.occ_odd, &v.xcd) == 6)
         if (key == k) {
             *c = v;
             hit = true;
@@ -64,6 +64,7 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
         g->tile = cached.tile;
         g->occ_even = cached.occ_even;
         g->occ_odd = cached.occ_odd;
+        g->xcd_group = cached.xcd;
         return LBM_OK;
     }
     const size_t eb = grid_storage_bytes(g->d.storage);
@@ -86,7 +87,7 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     for (int l = 0; l < g->L; ++l)
         steps[l] = g->lv[l].steps;
     const int64_t cs = g->coarse_steps, fs = g->finest_steps, sm = g->samples, rc = g->ring_count;
-    const Choice old{g->threads, g->tile, g->occ_even, g->occ_odd};
+    const Choice old{g->threads, g->tile, g->occ_even, g->occ_odd, g->xcd_group};
 
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
@@ -98,11 +99,12 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
         g->tile = c.tile;
         g->occ_even = c.occ_even;
         g->occ_odd = c.occ_odd;
+        g->xcd_group = c.xcd;
         lbm_status s2 = grid_coarse_step(g);
         if (s2 == LBM_OK)
             s2 = grid_coarse_step(g);
         (void)hipEventRecord(e0, g->stream);
-        for (int r = 0; r < 4 && s2 == LBM_OK; ++r)
+        for (int r = 0; r < 8 && s2 == LBM_OK; ++r)
             s2 = grid_coarse_step(g);
         (void)hipEventRecord(e1, g->stream);
         (void)hipEventSynchronize(e1);
@@ -118,18 +120,22 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     if (g->L > 1)
         for (int threads : {64, 128, 256})
             for (int tile = cells; tile >= threads && tile >= cells / 16; tile /= 2)
-                cand.push_back({threads, tile, best.occ_even, best.occ_odd});
+                cand.push_back({threads, tile, best.occ_even, best.occ_odd, best.xcd});
     else
         cand.push_back(best);
-    for (int pass = 0; pass < 3 && st == LBM_OK; ++pass) {
+    for (int pass = 0; pass < 4 && st == LBM_OK; ++pass) {
         if (pass == 1) {
             cand.clear();
             for (int occ : {0, 2, 3, 4, 6})
-                cand.push_back({best.threads, best.tile, occ, best.occ_odd});
+                cand.push_back({best.threads, best.tile, occ, best.occ_odd, best.xcd});
         } else if (pass == 2) {
             cand.clear();
             for (int occ : {0, 2, 3, 4})
-                cand.push_back({best.threads, best.tile, best.occ_even, occ});
+                cand.push_back({best.threads, best.tile, best.occ_even, occ, best.xcd});
+        } else if (pass == 3) {
+            cand.clear();
+            for (int k : {1, 4, 16})
+                cand.push_back({best.threads, best.tile, best.occ_even, best.occ_odd, k});
         }
         for (const Choice &c : cand) {
             float ms = 0.0f;
@@ -166,12 +172,14 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     g->tile = use.tile;
     g->occ_even = use.occ_even;
     g->occ_odd = use.occ_odd;
+    g->xcd_group = use.xcd;
     if (st != LBM_OK)
         return st;
     if (cache_path) {
         FILE *f = std::fopen(cache_path, "a");
         if (f) {
-            std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), use.threads, use.tile, use.occ_even, use.occ_odd);
+            std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), use.threads, use.tile, use.occ_even, use.occ_odd,
+                         use.xcd);
             std::fclose(f);
         }
     }
