@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 STREAM = None
 TUNE = True
+TUNE_CACHE = None  # file of tuned launch shapes shared by runs (None: tune afresh)
 NX, NY, NZ, H = 512, 256, 256, 128.0
 RE_H, U_IN = 2500.0, 0.05
 
@@ -72,7 +73,7 @@ def run_storage(lt, torch, arr, storage, steps, warmup, drag_every):
                 stream=stream.cuda_stream)
     g.set_geometry(arr)
     if TUNE:
-        g.autotune()  # launch shapes picked by timing candidates on this grid (state restored)
+        g.autotune(TUNE_CACHE)  # launch shapes picked by timing candidates on this grid (state restored)
     info = g.info()
     g.step(warmup)
     torch.cuda.synchronize()
@@ -132,7 +133,8 @@ def amr_leg(lt, torch, steps, warmup):
     stream = STREAM
     arr = amr_tree(lt)
     res = {}
-    cache = os.path.join(tempfile.mkdtemp(), "tune.txt")  # both modes use the tiles tuned once
+    # both modes use the tiles tuned once
+    cache = TUNE_CACHE or os.path.join(tempfile.mkdtemp(), "tune.txt")
     for mode, flags in (("eager", 0), ("graph", lt.LBM_F_GRAPH)):
         g = lt.Grid(AMR["nx"], AMR["ny"], AMR["nz"], u_in=U_IN, re_h=AMR["re_h"], block_edge=16, levels=3,
                     storage="fp32", drag_every=1, flags=flags, stream=stream.cuda_stream)
@@ -168,6 +170,8 @@ def amr_leg(lt, torch, steps, warmup):
                            "updates_per_coarse_step": upd, "links": info["links"], "branches": info["branches"],
                            "device_gb": round(info["device_bytes"] / 1e9, 2), "setup_s": round(setup, 1),
                            "tile_cells": info["tile_cells"], "threads": info["threads"],
+                           "tuned": {"occ_even": info["occ_even"], "occ_odd": info["occ_odd"],
+                                     "xcd_group": info["xcd_group"]},
                            "effective_finest_cells": AMR["nx"] * AMR["ny"] * AMR["nz"]}
         res[mode] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
         g.close()
@@ -299,6 +303,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--storage", choices=["both", "fp32", "fp16"], default="both")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune-cache", default=None,
+                    help="file that keeps the tuned launch shapes; a later run with the same file reuses them")
     ap.add_argument("--no-amr", action="store_true", help="skip the three-level AMR leg")
     ap.add_argument("--amr-steps", type=int, default=40)
     ap.add_argument("--amr-only", action="store_true", help="run only the three-level AMR leg (profiling)")
@@ -330,8 +336,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    global TUNE
+    global TUNE, TUNE_CACHE
     TUNE = not args.no_tune
+    TUNE_CACHE = args.tune_cache
     if args.amr_only:
         print(json.dumps({"amr_3level": amr_leg(lt, torch, args.amr_steps, 4)}), flush=True)
         return

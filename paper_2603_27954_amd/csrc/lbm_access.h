@@ -179,4 +179,68 @@ __device__ __forceinline__ void store_pre(const CollideArgs &a, uint32_t elem, c
         stp<S>(a.pop[k], block_neighbour<B>(a, elem, qcx(k), qcy(k), qcz(k)), g[qopp(k)]);
 }
 
+// Post-collision populations of one cell stored where the collide kernel of
+// the same A-A parity stores them (even: population k into slot opp(k) of the
+// cell; odd: into slot k of x + c_k), for the directions k set in mask only.
+template <int B, typename S, bool ODD>
+__device__ __forceinline__ void store_post_masked(const CollideArgs &a, uint32_t elem, const float (&g)[NQ],
+                                                  uint32_t mask)
+{
+    if (!ODD) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            if ((mask >> k) & 1u)
+                stp<S>(a.pop[qopp(k)], elem, g[k]);
+        return;
+    }
+    if (a.dense) {
+        const int nx = a.nx, ny = a.ny, nz = a.nz;
+        const int x = (int)(elem % (uint32_t)nx);
+        const uint32_t yz = elem / (uint32_t)nx;
+        const int y = (int)(yz % (uint32_t)ny), z = (int)(yz / (uint32_t)ny);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            if ((mask >> k) & 1u) {
+                const int xs = wrapi(x + qcx(k), nx), ys = wrapi(y + qcy(k), ny), zs = wrapi(z + qcz(k), nz);
+                stp<S>(a.pop[k], (uint32_t)xs + (uint32_t)nx * ((uint32_t)ys + (uint32_t)ny * zs), g[k]);
+            }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        if ((mask >> k) & 1u)
+            stp<S>(a.pop[k], block_neighbour<B>(a, elem, qcx(k), qcy(k), qcz(k)), g[k]);
+}
+
+// store_pre for the populations k with k % parts == part only
+template <int B, typename S, bool ODD>
+__device__ __forceinline__ void store_pre_part(const CollideArgs &a, uint32_t elem, const float (&g)[NQ], int part,
+                                               int parts)
+{
+    if (!ODD) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            if (k % parts == part)
+                stp<S>(a.pop[k], elem, g[k]);
+        return;
+    }
+    if (a.dense) {
+        const int nx = a.nx, ny = a.ny, nz = a.nz;
+        const int x = (int)(elem % (uint32_t)nx);
+        const uint32_t yz = elem / (uint32_t)nx;
+        const int y = (int)(yz % (uint32_t)ny), z = (int)(yz / (uint32_t)ny);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            if (k % parts == part) {
+                const int xs = wrapi(x + qcx(k), nx), ys = wrapi(y + qcy(k), ny), zs = wrapi(z + qcz(k), nz);
+                stp<S>(a.pop[k], (uint32_t)xs + (uint32_t)nx * ((uint32_t)ys + (uint32_t)ny * zs), g[qopp(k)]);
+            }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        if (k % parts == part)
+            stp<S>(a.pop[k], block_neighbour<B>(a, elem, qcx(k), qcy(k), qcz(k)), g[qopp(k)]);
+}
+
 }  // namespace lbm

@@ -25,10 +25,11 @@ __global__ void __launch_bounds__(256) k_amr_moments(const CollideArgs a, const 
 
 template <int B, typename S, bool ODD>
 __global__ void __launch_bounds__(256) k_amr_prolong(const CollideArgs fine, const uint32_t *ghosts,
-                                                     const int32_t *src, int n, int nsrc, const float *m0,
-                                                     const float *m1, float om1, float dt)
+                                                     const uint32_t *gmask, const int32_t *src, int n, int nsrc,
+                                                     const float *m0, const float *m1, float om1, float dt)
 {
-    amr_prolong_item<B, S, ODD>(fine, ghosts, src, n, nsrc, m0, m1, om1, dt, blockIdx.x * blockDim.x + threadIdx.x);
+    amr_prolong_item<B, S, ODD>(fine, ghosts, gmask, src, n, nsrc, m0, m1, om1, dt,
+                                blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <int B, typename S, bool ODD_C, bool ODD_F>
@@ -56,21 +57,22 @@ static void moments_t(int odd, const CollideArgs &a, const uint32_t *cells, int 
 }
 
 template <int B, typename S>
-static void prolong_t(int odd, const CollideArgs &f, const uint32_t *ghosts, const int32_t *src, int n, int nsrc,
+static void prolong_t(int odd, const CollideArgs &f, const uint32_t *ghosts, const uint32_t *gmask,
+                      const int32_t *src, int n, int nsrc,
                       const float *m0, const float *m1, float om1, float dt, hipStream_t s)
 {
     const dim3 grid((n + 255) / 256), blk(256);
     if (odd)
-        hipLaunchKernelGGL((k_amr_prolong<B, S, true>), grid, blk, 0, s, f, ghosts, src, n, nsrc, m0, m1, om1, dt);
+        hipLaunchKernelGGL((k_amr_prolong<B, S, true>), grid, blk, 0, s, f, ghosts, gmask, src, n, nsrc, m0, m1, om1, dt);
     else
-        hipLaunchKernelGGL((k_amr_prolong<B, S, false>), grid, blk, 0, s, f, ghosts, src, n, nsrc, m0, m1, om1, dt);
+        hipLaunchKernelGGL((k_amr_prolong<B, S, false>), grid, blk, 0, s, f, ghosts, gmask, src, n, nsrc, m0, m1, om1, dt);
 }
 
 template <int B, typename S>
 static void restrict_t(int odd_c, int odd_f, const CollideArgs &c, const CollideArgs &f, const uint32_t *band,
                        const uint32_t *child, int n, float om_c, float dt_c, float om_f, float dt_f, hipStream_t s)
 {
-    const dim3 grid((n + 255) / 256), blk(256);
+    const dim3 grid((8 * n + 255) / 256), blk(256);  // eight lanes per band cell
 #define LBM_RS(OC, OF) \
     hipLaunchKernelGGL((k_amr_restrict<B, S, OC, OF>), grid, blk, 0, s, c, f, band, child, n, om_c, dt_c, om_f, dt_f)
     if (odd_c && odd_f) LBM_RS(true, true);
@@ -103,12 +105,12 @@ hipError_t launch_amr_moments(int B, int storage, int odd, const CollideArgs &a,
 }
 
 hipError_t launch_amr_prolong(int B, int storage, int odd, const CollideArgs &fine, const uint32_t *ghosts,
-                              const int32_t *src, int n, int nsrc, const float *m0, const float *m1, float om1,
+                              const uint32_t *gmask, const int32_t *src, int n, int nsrc, const float *m0, const float *m1, float om1,
                               float dt, hipStream_t s)
 {
     if (n == 0)
         return hipSuccess;
-    LBM_DISPATCH(prolong_t, odd, fine, ghosts, src, n, nsrc, m0, m1, om1, dt, s);
+    LBM_DISPATCH(prolong_t, odd, fine, ghosts, gmask, src, n, nsrc, m0, m1, om1, dt, s);
     return hipGetLastError();
 }
 

@@ -358,9 +358,10 @@ __device__ __forceinline__ void branch_totals(const double *piece_sum, const int
 }
 
 // ---------------------------------------------------------------------------
-// coarse/fine transfer in moment space (one interface cell per thread t)
+// coarse/fine transfer in moment space
 // ---------------------------------------------------------------------------
 
+// one source cell per thread t; its record goes to out[MOM_REC t ..]
 template <int B, typename S, bool ODD>
 __device__ __forceinline__ void amr_moments_item(const CollideArgs &a, const uint32_t *cells, int n, float om1,
                                                  float dt, float *out, int t)
@@ -370,36 +371,59 @@ __device__ __forceinline__ void amr_moments_item(const CollideArgs &a, const uin
     float g[NQ];
     load_pre<B, S, ODD>(a, cells[t], g);
     const Transfer tr = to_transfer(forward_moments(g), om1, dt);
-    out[0 * (size_t)n + t] = tr.drho;
-    out[1 * (size_t)n + t] = tr.ux;
-    out[2 * (size_t)n + t] = tr.uy;
-    out[3 * (size_t)n + t] = tr.uz;
-#pragma unroll
-    for (int v = 0; v < 6; ++v)
-        out[(4 + v) * (size_t)n + t] = tr.d[v];
+    float4 *o = reinterpret_cast<float4 *>(out + (size_t)MOM_REC * t);
+    o[0] = make_float4(tr.drho, tr.ux, tr.uy, tr.uz);
+    o[1] = make_float4(tr.d[0], tr.d[1], tr.d[2], tr.d[3]);
+    o[2] = make_float4(tr.d[4], tr.d[5], 0.0f, 0.0f);
 }
 
+__device__ __forceinline__ void mom_load(const float *m, int s, float (&x)[12])
+{
+    const float4 *r = reinterpret_cast<const float4 *>(m + (size_t)MOM_REC * s);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float4 v = r[k];
+        x[4 * k] = v.x, x[4 * k + 1] = v.y, x[4 * k + 2] = v.z, x[4 * k + 3] = v.w;
+    }
+}
+
+// One fine ghost cell per thread t.  The ghost's rebuilt pre-collision state
+// is collided here as the level's own step would collide it (rates and
+// Galilean flag of fine), and its post-collision populations are stored where
+// that step stores them: the ghost cells are not in the level's work lists.
+// Only the populations that stream into collided cells (bits of gmask[t]) are
+// stored.  Run before or after the level's collide launch of the same step:
+// the two touch disjoint slots.
 template <int B, typename S, bool ODD>
 __device__ __forceinline__ void amr_prolong_item(const CollideArgs &fine, const uint32_t *ghosts,
-                                                 const int32_t *src, int n, int nsrc, const float *m0,
-                                                 const float *m1, float om1, float dt, int t)
+                                                 const uint32_t *gmask, const int32_t *src, int n, int nsrc,
+                                                 const float *m0, const float *m1, float om1, float dt, int t)
 {
+    (void)nsrc;
     if (t >= n)
         return;
     float v[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k)
         v[k] = 0.0f;
+    const int4 *sp = reinterpret_cast<const int4 *>(src + 8 * (size_t)t);
+    const int4 s0 = sp[0], s1 = sp[1];
+    const int sq[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const float w = ((q & 1) ? 0.25f : 0.75f) * ((q & 2) ? 0.25f : 0.75f) * ((q & 4) ? 0.25f : 0.75f);
-        const int s = src[8 * (size_t)t + q];
+        float x[12];
+        mom_load(m0, sq[q], x);
+        if (m1) {
+            float y[12];
+            mom_load(m1, sq[q], y);
 #pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            const float x0 = m0[k * (size_t)nsrc + s];
-            const float x = m1 ? 0.5f * (x0 + m1[k * (size_t)nsrc + s]) : x0;
-            v[k] = fmaf(w, x, v[k]);
+            for (int k = 0; k < 10; ++k)
+                x[k] = 0.5f * (x[k] + y[k]);
         }
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+            v[k] = fmaf(w, x[k], v[k]);
     }
     Transfer tr;
     tr.drho = v[0];
@@ -411,50 +435,62 @@ __device__ __forceinline__ void amr_prolong_item(const CollideArgs &fine, const 
         tr.d[k] = v[4 + k];
     float g[NQ];
     back_transform(from_transfer(tr, om1, dt), g);
-    store_pre<B, S, ODD>(fine, ghosts[t], g);
+    collide(g, fine.om1, fine.om2, fine.galilean != 0);
+    store_post_masked<B, S, ODD>(fine, ghosts[t], g, gmask[t]);
 }
 
+// Eight lanes per coarse band cell (t >> 3), lane q = t & 7 holding child q:
+// consecutive band cells run along x, so each population load of a wave
+// covers whole rows of the fine level.  The children's sums meet over a
+// butterfly of the eight lanes (fixed order); every lane rebuilds the cell and
+// stores the populations k with k % 8 == q.  Launch 8 n threads.
 template <int B, typename S, bool ODD_C, bool ODD_F>
 __device__ __forceinline__ void amr_restrict_item(const CollideArgs &coarse, const CollideArgs &fine,
                                                   const uint32_t *band, const uint32_t *child, int n, float om_c,
                                                   float dt_c, float om_f, float dt_f, int t)
 {
-    if (t >= n)
-        return;
-    float drho = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f, d[6] = {0, 0, 0, 0, 0, 0};
-    int cnt = 0;
-    for (int q = 0; q < 8; ++q) {
-        const uint32_t c = child[8 * (size_t)t + q];
-        if (c == FULL_MASK)
-            continue;
+    const int cell = t >> 3, q = t & 7;
+    if (cell >= n)
+        return;  // whole groups of eight leave together
+    float v[11];
+#pragma unroll
+    for (int k = 0; k < 11; ++k)
+        v[k] = 0.0f;
+    const uint32_t c = child[(size_t)t];
+    if (c != FULL_MASK) {
         float g[NQ];
         load_pre<B, S, ODD_F>(fine, c, g);
         const Transfer tr = to_transfer(forward_moments(g), om_f, dt_f);
         const float rho = 1.0f + tr.drho;
-        drho += tr.drho;
-        mx = fmaf(rho, tr.ux, mx);
-        my = fmaf(rho, tr.uy, my);
-        mz = fmaf(rho, tr.uz, mz);
+        v[0] = tr.drho;
+        v[1] = rho * tr.ux;
+        v[2] = rho * tr.uy;
+        v[3] = rho * tr.uz;
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            d[k] += tr.d[k];
-        ++cnt;
+            v[4 + k] = tr.d[k];
+        v[10] = 1.0f;
     }
-    if (cnt == 0)
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1)
+#pragma unroll
+        for (int k = 0; k < 11; ++k)
+            v[k] += __shfl_xor(v[k], m, 8);
+    if (v[10] == 0.0f)
         return;
-    const float ic = 1.0f / (float)cnt;
+    const float ic = 1.0f / v[10];
     Transfer tr;
-    tr.drho = drho * ic;
-    const float irho = 1.0f / (float)cnt / (1.0f + tr.drho);
-    tr.ux = mx * irho;
-    tr.uy = my * irho;
-    tr.uz = mz * irho;
+    tr.drho = v[0] * ic;
+    const float irho = ic / (1.0f + tr.drho);
+    tr.ux = v[1] * irho;
+    tr.uy = v[2] * irho;
+    tr.uz = v[3] * irho;
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-        tr.d[k] = d[k] * ic;
+        tr.d[k] = v[4 + k] * ic;
     float g[NQ];
     back_transform(from_transfer(tr, om_c, dt_c), g);
-    store_pre<B, S, ODD_C>(coarse, band[t], g);
+    store_pre_part<B, S, ODD_C>(coarse, band[cell], g, q, 8);
 }
 
 }  // namespace lbm

@@ -16,6 +16,8 @@ constexpr int NB_OUTLET = -3;  // x >= nx: zero-gradient ghost plane
 constexpr uint32_t FULL_MASK = 0xFFFFFFFFu;
 // force samples kept on the device (ring of total-force triples)
 constexpr int RING = 65536;
+// coarse/fine transfer record of one source cell: drho, ux, uy, uz, D (6), two pad floats
+constexpr int MOM_REC = 12;
 // links per piece of the force reduction (one work-group each)
 constexpr int LINK_PIECE = 2048;
 
@@ -81,6 +83,7 @@ struct Phase {
     LinkArgs la;
     const uint32_t *cells;
     const int32_t *src;
+    const uint32_t *gmask;  // prolongation: stored directions per ghost
     const uint32_t *child;
     const float *m0, *m1;
     float *out;
@@ -161,7 +164,7 @@ hipError_t launch_mass(int B, int storage, int odd, const CollideArgs &a, const 
 hipError_t launch_amr_moments(int B, int storage, int odd, const CollideArgs &a, const uint32_t *cells, int n,
                               float om1, float dt, float *out, hipStream_t s);
 hipError_t launch_amr_prolong(int B, int storage, int odd, const CollideArgs &fine, const uint32_t *ghosts,
-                              const int32_t *src, int n, int nsrc, const float *m0, const float *m1, float om1,
+                              const uint32_t *gmask, const int32_t *src, int n, int nsrc, const float *m0, const float *m1, float om1,
                               float dt, hipStream_t s);
 hipError_t launch_amr_restrict(int B, int storage, int odd_c, int odd_f, const CollideArgs &coarse,
                                const CollideArgs &fine, const uint32_t *band, const uint32_t *child, int n,

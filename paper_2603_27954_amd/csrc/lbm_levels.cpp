@@ -394,7 +394,8 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
                 const bool sol = finest && (k == 1 || k == 2) && finest_solid(x, y, z);
                 if (k == 1 || k == 2)
                     v.leaf_cells += k == 1;
-                if ((k == 1 || k == 2 || k == 4) && !sol) {
+                // ghost cells (4) are collided by the prolongation itself
+                if ((k == 1 || k == 2) && !sol) {
                     mw[c >> 5] |= 1u << (c & 31);
                     ++nw;
                 }
@@ -433,7 +434,13 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
                 bad = true;
             return (uint32_t)std::max<int64_t>(e, 0);
         };
+        // prolongation sources hold the coarse level's pre-collision state:
+        // active or band cells, never ghosts (which hold post-collision data)
+        bool bad_src = false;
         auto src_of = [&](int x, int y, int z) -> int32_t {
+            const int k = cell_class(l, x, y, z);
+            if (k != 1 && k != 2)
+                bad_src = true;
             const uint32_t e = addr_of(C, x, y, z);
             auto it = src_index.find(e);
             if (it != src_index.end())
@@ -453,12 +460,36 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
                 if (cell_class(l + 1, x, y, z) != 4)
                     continue;
                 pr.h_ghost.push_back((uint32_t)bi * cells + c);
+                uint32_t gm = 0;
+                for (int k = 0; k < 27; ++k) {
+                    const int t = cell_class(l + 1, x + k % 3 - 1, y + (k / 3) % 3 - 1, z + k / 9 - 1);
+                    if (t == 1 || t == 2)
+                        gm |= 1u << k;
+                }
+                pr.h_ghost_mask.push_back(gm);
                 const int P[3] = {x >> 1, y >> 1, z >> 1};
                 const int s[3] = {(x & 1) ? 1 : -1, (y & 1) ? 1 : -1, (z & 1) ? 1 : -1};
                 for (int q = 0; q < 8; ++q)
                     pr.h_ghost_src.push_back(src_of(P[0] + (q & 1) * s[0], P[1] + ((q >> 1) & 1) * s[1],
                                                     P[2] + ((q >> 2) & 1) * s[2]));
             }
+        }
+        // source cells in address order (coalesced moment loads); the ghost
+        // stencils follow the renumbering
+        {
+            std::vector<int32_t> order(pr.h_src.size()), rank(pr.h_src.size());
+            for (size_t i = 0; i < order.size(); ++i)
+                order[i] = (int32_t)i;
+            std::sort(order.begin(), order.end(),
+                      [&](int32_t a, int32_t b) { return pr.h_src[a] < pr.h_src[b]; });
+            std::vector<uint32_t> sorted(order.size());
+            for (size_t i = 0; i < order.size(); ++i) {
+                sorted[i] = pr.h_src[order[i]];
+                rank[order[i]] = (int32_t)i;
+            }
+            pr.h_src.swap(sorted);
+            for (int32_t &v : pr.h_ghost_src)
+                v = rank[v];
         }
         // coarse band cells and their children
         auto band_cell = [&](int x, int y, int z) {
@@ -482,6 +513,10 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
                 }
         if (bad) {
             *msg = "internal: a coarse/fine stencil cell is not held by its level";
+            return LBM_E_INVALID;
+        }
+        if (bad_src) {
+            *msg = "internal: a prolongation source is not an active or band cell of the coarse level";
             return LBM_E_INVALID;
         }
     }
@@ -508,11 +543,12 @@ lbm_status amr_upload(AmrPlan &plan, std::vector<DevLevel> &lv, int B, const All
         if ((st = put((void **)&pr.d_src, pr.h_src.data(), pr.h_src.size() * 4)) != LBM_OK ||
             (st = put((void **)&pr.d_ghost, pr.h_ghost.data(), pr.h_ghost.size() * 4)) != LBM_OK ||
             (st = put((void **)&pr.d_ghost_src, pr.h_ghost_src.data(), pr.h_ghost_src.size() * 4)) != LBM_OK ||
+            (st = put((void **)&pr.d_ghost_mask, pr.h_ghost_mask.data(), pr.h_ghost_mask.size() * 4)) != LBM_OK ||
             (st = put((void **)&pr.d_band, pr.h_band.data(), pr.h_band.size() * 4)) != LBM_OK ||
             (st = put((void **)&pr.d_band_child, pr.h_band_child.data(), pr.h_band_child.size() * 4)) != LBM_OK)
             return st;
         for (int k = 0; k < 2; ++k)
-            if ((st = alloc((void **)&pr.d_mom[k], std::max<size_t>(pr.h_src.size() * 10 * sizeof(float), 16))) != LBM_OK)
+            if ((st = alloc((void **)&pr.d_mom[k], std::max<size_t>(pr.h_src.size() * MOM_REC * sizeof(float), 16))) != LBM_OK)
                 return st;
     }
     return LBM_OK;

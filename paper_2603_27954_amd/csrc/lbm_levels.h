@@ -19,15 +19,18 @@ struct AmrPair {
     // stencil (weights 3/4 for o = 0, 1/4 for o = 1 per axis)
     std::vector<uint32_t> h_ghost;
     std::vector<int32_t> h_ghost_src;
+    // per ghost, bit k set when its post-collision population k streams into
+    // a collided cell (active or band) of level l + 1; only those are stored
+    std::vector<uint32_t> h_ghost_mask;
     // coarse band cells (covered, within two cells of the coarse leaf region)
     // and their eight fine children (cell addresses on level l + 1)
     std::vector<uint32_t> h_band;
     std::vector<uint32_t> h_band_child;
     // device copies
-    uint32_t *d_src = nullptr, *d_ghost = nullptr, *d_band = nullptr;
+    uint32_t *d_src = nullptr, *d_ghost = nullptr, *d_ghost_mask = nullptr, *d_band = nullptr;
     int32_t *d_ghost_src = nullptr;
     uint32_t *d_band_child = nullptr;
-    float *d_mom[2] = {nullptr, nullptr};  // 10 floats per source cell at T and T+1
+    float *d_mom[2] = {nullptr, nullptr};  // MOM_REC floats per source cell at T and T+1
 };
 
 struct AmrPlan {

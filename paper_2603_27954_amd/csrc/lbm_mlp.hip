@@ -248,6 +248,11 @@ __device__ __forceinline__ void load_regs(const MlpDev &d, MlpRegs &r, int lane)
 // Both lanes of a column return the same value.
 __device__ __forceinline__ float mlp_tile(const MlpRegs &r, bf16x8 b1, const float *sb, int lane)
 {
+    // an offset the compiler cannot see through: the 192 LDS values are read
+    // per tile instead of being held in registers across a caller's loop
+    int o = 0;
+    asm volatile("" : "+s"(o));
+    sb += o;
     f32x16 c1[2];
     for (int t = 0; t < 2; ++t) {
         for (int i = 0; i < 16; ++i)
@@ -257,7 +262,7 @@ __device__ __forceinline__ float mlp_tile(const MlpRegs &r, bf16x8 b1, const flo
     bf16x8 b2[4];
     for (int s = 0; s < 4; ++s)
         for (int j = 0; j < 8; ++j)
-            b2[s][j] = bf16_of(bf16_bits(fmaxf(c1[s >> 1][8 * (s & 1) + j], 0.0f)));
+            b2[s][j] = (__bf16)fmaxf(c1[s >> 1][8 * (s & 1) + j], 0.0f);  // round to nearest even
     float y = 0.0f;
     for (int t = 0; t < 2; ++t) {
         f32x16 c2;
@@ -302,7 +307,7 @@ __global__ void __launch_bounds__(256) k_mlp_predict(MlpDev d, const float *x, i
             float v = 0.0f;
             if (k < MLP_IN && row < n)
                 v = (x[row * MLP_IN + k] - mean[k]) * inv[k];
-            b1[j] = bf16_of(bf16_bits(v));
+            b1[j] = (__bf16)v;
         }
         const float out = mlp_tile(r, b1, sb, lane);
         if (lane < 32 && row < n)
@@ -319,12 +324,18 @@ __global__ void __launch_bounds__(256) k_mlp_predict(MlpDev d, const float *x, i
 // 1 + 10 Re^(-2/3) blended into a post-critical branch
 // 0.25 + 0.35 / (1 + exp(-(ln Re - ln(20 Re_cr)) / 0.8)) by the weight
 // 1 / (1 + exp((ln Re - ln Re_cr) / 0.12)).
+// Evaluated with the hardware exp2 and reciprocal (about 1 ulp each): the
+// exponents are formed in log2 units, Re^(-2/3) = 2^(-(2/3) log2 Re).
 __device__ __forceinline__ float cylinder_cd(float lg_re, float ln_rc)
 {
-    const float lr = lg_re * 2.302585093f;
-    const float sub = 1.0f + 10.0f * expf(-(2.0f / 3.0f) * lr);
-    const float post = 0.25f + 0.35f / (1.0f + expf(-(lr - (ln_rc + 2.995732274f)) / 0.8f));
-    const float w = 1.0f / (1.0f + expf((lr - ln_rc) / 0.12f));
+    constexpr float LOG2_10 = 3.321928095f, LOG2_E = 1.442695041f;
+    const float l2 = lg_re * LOG2_10;           // log2 Re
+    const float l2c = ln_rc * LOG2_E;           // log2 Re_cr
+    const float sub = 1.0f + 10.0f * __builtin_amdgcn_exp2f(-(2.0f / 3.0f) * l2);
+    // ln(20) = 2.995732274; 1 / 0.8 and 1 / 0.12 as products
+    const float post = 0.25f + 0.35f * __builtin_amdgcn_rcpf(
+        1.0f + __builtin_amdgcn_exp2f(-(l2 - l2c - 2.995732274f * LOG2_E) * 1.25f));
+    const float w = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f((l2 - l2c) * (1.0f / 0.12f)));
     return w * sub + (1.0f - w) * post;
 }
 
@@ -335,12 +346,16 @@ __device__ __forceinline__ float wave_sum_f(float v)
     return v;
 }
 
-// One wave per tree: for each Re_H, tiles of 32 branches on the matrix cores;
-// per-lane sums in tile order, then a fixed shuffle tree.  The branch records
-// of a tree stay in cache across the Re_H loop.
-__global__ void __launch_bounds__(64) k_tree_sweep(MlpDev d, SweepArgs a)
+// One wave per tree.  Tiles of 32 branches run on the matrix cores; for each
+// tile the four Re-independent features are scaled once and the Re_H values
+// follow, each changing only the first feature.  Each lane keeps its sum per
+// Re_H in LDS, adding tiles in order; a fixed shuffle tree ends each sum.
+// Outside the training envelope the network's value at the envelope edge is
+// carried along the cylinder curve: y C_d(Re_D) / C_d(edge).
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_tree_sweep(MlpDev d, SweepArgs a)
 {
     __shared__ float sb[192];
+    __shared__ float acc[SWEEP_MAX_RE][64];
     load_bias(d, sb);
     const int lane = threadIdx.x;
     MlpRegs r;
@@ -348,27 +363,37 @@ __global__ void __launch_bounds__(64) k_tree_sweep(MlpDev d, SweepArgs a)
     const int tree = blockIdx.x;
     const int64_t b0 = a.tree_start[tree], b1 = a.tree_start[tree + 1];
     const float b3 = d.wr[MLP_B3], ym = d.sc[10], ys = d.sc[11];
+    const float m0 = d.sc[0], s0 = d.sc[MLP_IN];
     const float ln_rc = logf(a.re_cr), inv = 1.0f / a.area[tree];
+    const float inv_lo = 1.0f / cylinder_cd(a.lg_lo, ln_rc), inv_hi = 1.0f / cylinder_cd(a.lg_hi, ln_rc);
+    const float inv_s0 = 1.0f / s0;
     const bool feat_lane = lane < 32;  // lane half 0 carries the features
-    for (int q = 0; q < a.n_re; ++q) {
-        float acc = 0.0f;
-        for (int64_t t0 = b0; t0 < b1; t0 += 32) {
-            const int64_t br = t0 + (lane & 31);
-            const bool valid = br < b1;
-            const float *rc = a.rec + (valid ? br : b0) * SWEEP_REC;
-            const float lre = a.lg_re[q] + rc[0];
+    for (int q = 0; q < a.n_re; ++q)
+        acc[q][lane] = 0.0f;
+    for (int64_t t0 = b0; t0 < b1; t0 += 32) {
+        const int64_t br = t0 + (lane & 31);
+        const bool valid = br < b1;
+        const float *rc = a.rec + (valid ? br : b0) * SWEEP_REC;
+        const float lgd = rc[0], wgt = (feat_lane && valid) ? rc[4] : 0.0f;
+        bf16x8 bop;
+        bop[0] = (__bf16)0.0f;
+        bop[1] = (__bf16)(feat_lane ? (rc[1] - d.sc[1]) / d.sc[MLP_IN + 1] : 0.0f);
+        bop[2] = (__bf16)(feat_lane ? (rc[2] - d.sc[2]) / d.sc[MLP_IN + 2] : 0.0f);
+        bop[3] = (__bf16)(feat_lane ? (a.intensity - d.sc[3]) / d.sc[MLP_IN + 3] : 0.0f);
+        bop[4] = (__bf16)(feat_lane ? (rc[3] - d.sc[4]) / d.sc[MLP_IN + 4] : 0.0f);
+        bop[5] = bop[6] = bop[7] = (__bf16)0.0f;
+        for (int q = 0; q < a.n_re; ++q) {
+            const float lre = a.lg_re[q] + lgd;
             const float lc = fminf(fmaxf(lre, a.lg_lo), a.lg_hi);
-            bf16x8 bop;
-            for (int j = 0; j < 8; ++j) {
-                const float v = j == 0 ? lc : j == 1 ? rc[1] : j == 2 ? rc[2] : j == 3 ? a.intensity : rc[3];
-                bop[j] = bf16_of(bf16_bits((feat_lane && j < MLP_IN) ? (v - d.sc[j]) / d.sc[MLP_IN + j] : 0.0f));
-            }
+            bop[0] = (__bf16)(feat_lane ? (lc - m0) * inv_s0 : 0.0f);
             float y = (mlp_tile(r, bop, sb, lane) + b3) * ys + ym;
             if (lre != lc)
-                y *= cylinder_cd(lre, ln_rc) / cylinder_cd(lc, ln_rc);
-            acc = fmaf((lane < 32 && valid) ? y : 0.0f, rc[4], acc);
+                y *= cylinder_cd(lre, ln_rc) * (lre > lc ? inv_hi : inv_lo);
+            acc[q][lane] = fmaf(y, wgt, acc[q][lane]);
         }
-        const float sum = wave_sum_f(acc);
+    }
+    for (int q = 0; q < a.n_re; ++q) {
+        const float sum = wave_sum_f(acc[q][lane]);
         if (lane == 0)
             a.cd[(size_t)tree * a.n_re + q] = sum * inv;
     }
@@ -401,6 +426,8 @@ __global__ void __launch_bounds__(256) k_frontal_area(const float *rec, const in
     constexpr int WORDS = AREA_PIX * AREA_PIX / 32;
     __shared__ uint32_t bits[WORDS];
     __shared__ float red[4][256];
+    __shared__ float box[256][6];
+    __shared__ int boxi[256][2], pend[256], wsum[4];
     const int tid = threadIdx.x, tree = blockIdx.x;
     const int64_t b0 = tree_start[tree], b1 = tree_start[tree + 1];
     float ylo = 1e30f, yhi = -1e30f, zlo = 1e30f, zhi = -1e30f;
@@ -430,48 +457,75 @@ __global__ void __launch_bounds__(256) k_frontal_area(const float *rec, const in
             area[tree] = -1.0f;
         return;
     }
-    // a branch's pixel box and the test of pixel p of it
-    struct Box {
-        float y0, z0, dy, dz, l2, rr;
-        int py0, pz0, wy, np;
-    };
-    auto box_of = [&](int64_t b) {
-        const float *rc = rec + b * SWEEP_REC;
-        Box x;
-        x.y0 = rc[5], x.z0 = rc[6], x.rr = rc[9];
-        x.dy = rc[7] - x.y0, x.dz = rc[8] - x.z0, x.l2 = x.dy * x.dy + x.dz * x.dz;
-        x.py0 = max(0, (int)floorf((fminf(x.y0, rc[7]) - x.rr - ylo) / h));
-        const int py1 = min(ny - 1, (int)floorf((fmaxf(x.y0, rc[7]) + x.rr - ylo) / h));
-        x.pz0 = max(0, (int)floorf((fminf(x.z0, rc[8]) - x.rr - zlo) / h));
-        const int pz1 = min(nz - 1, (int)floorf((fmaxf(x.z0, rc[8]) + x.rr - zlo) / h));
-        x.wy = py1 - x.py0 + 1;
-        x.np = x.wy * (pz1 - x.pz0 + 1);
-        return x;
-    };
-    auto mark = [&](const Box &x, int p) {
-        const int py = x.py0 + p % x.wy, pz = x.pz0 + p / x.wy;
-        const float cy = ylo + (py + 0.5f) * h - x.y0, cz = zlo + (pz + 0.5f) * h - x.z0;
-        const float tt = x.l2 > 0.0f ? fminf(fmaxf((cy * x.dy + cz * x.dz) / x.l2, 0.0f), 1.0f) : 0.0f;
-        const float ey = cy - tt * x.dy, ez = cz - tt * x.dz;
-        if (ey * ey + ez * ez <= x.rr * x.rr) {
-            const int bit = pz * AREA_PIX + py;
-            atomicOr(&bits[bit >> 5], 1u << (bit & 31));
+    // Branches go in chunks of 256, one per thread: each thread puts its
+    // branch's pixel box in LDS, a work-group scan of the boxes' pixel counts
+    // lays the chunk's pixels out in one index range, and the threads test
+    // that range with stride 256 (a thread's pixel index only grows, so it
+    // finds the owning branch by walking forward).
+    for (int64_t c0 = b0; c0 < b1; c0 += 256) {
+        const int64_t b = c0 + tid;
+        int np = 0;
+        if (b < b1) {
+            const float *rc = rec + b * SWEEP_REC;
+            const float y0 = rc[5], z0 = rc[6], y1 = rc[7], z1 = rc[8], rr = rc[9];
+            const int py0 = max(0, (int)floorf((fminf(y0, y1) - rr - ylo) / h));
+            const int py1 = min(ny - 1, (int)floorf((fmaxf(y0, y1) + rr - ylo) / h));
+            const int pz0 = max(0, (int)floorf((fminf(z0, z1) - rr - zlo) / h));
+            const int pz1 = min(nz - 1, (int)floorf((fmaxf(z0, z1) + rr - zlo) / h));
+            const int wy = max(0, py1 - py0 + 1), wz = max(0, pz1 - pz0 + 1);
+            np = wy * wz;
+            const float dy = y1 - y0, dz = z1 - z0;
+            box[tid][0] = y0;
+            box[tid][1] = z0;
+            box[tid][2] = dy;
+            box[tid][3] = dz;
+            const float l2 = dy * dy + dz * dz;
+            box[tid][4] = l2 > 0.0f ? 1.0f / l2 : 0.0f;
+            box[tid][5] = rr * rr;
+            boxi[tid][0] = py0 | (pz0 << 16);
+            boxi[tid][1] = wy;
         }
-    };
-    constexpr int SMALL = 64;
-    // small branches: one thread each
-    for (int64_t b = b0 + tid; b < b1; b += 256) {
-        const Box x = box_of(b);
-        if (x.np <= SMALL)
-            for (int p = 0; p < x.np; ++p)
-                mark(x, p);
-    }
-    // large branches: the work-group shares each one
-    for (int64_t b = b0; b < b1; ++b) {
-        const Box x = box_of(b);
-        if (x.np > SMALL)
-            for (int p = tid; p < x.np; p += 256)
-                mark(x, p);
+        // inclusive scan of np over the work-group
+        const int lane = tid & 63, wave = tid >> 6;
+        int v = np;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(v, o, 64);
+            if (lane >= o)
+                v += u;
+        }
+        if (lane == 63)
+            wsum[wave] = v;
+        __syncthreads();
+        int off = 0;
+        for (int w = 0; w < wave; ++w)
+            off += wsum[w];
+        pend[tid] = off + v;  // end of this branch's pixel range
+        const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+        int j = 0;
+        for (int p = tid; p < total; p += 256) {
+            while (pend[j] <= p)
+                ++j;
+            const int q = p - (j ? pend[j - 1] : 0);
+            const int wy = boxi[j][1];
+            int pz = (int)((float)q / (float)wy);
+            if (pz * wy > q)
+                --pz;
+            else if ((pz + 1) * wy <= q)
+                ++pz;
+            const int py = (boxi[j][0] & 0xFFFF) + q - pz * wy;
+            pz += boxi[j][0] >> 16;
+            const float cy = ylo + (py + 0.5f) * h - box[j][0], cz = zlo + (pz + 0.5f) * h - box[j][1];
+            const float dy = box[j][2], dz = box[j][3];
+            const float tt = fminf(fmaxf((cy * dy + cz * dz) * box[j][4], 0.0f), 1.0f);
+            const float ey = cy - tt * dy, ez = cz - tt * dz;
+            if (ey * ey + ez * ez <= box[j][5]) {
+                const int bit = pz * AREA_PIX + py;
+                atomicOr(&bits[bit >> 5], 1u << (bit & 31));
+            }
+        }
+        __syncthreads();  // the boxes are refilled by the next chunk
     }
     __syncthreads();
     float cnt = 0.0f;

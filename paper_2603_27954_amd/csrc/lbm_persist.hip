@@ -96,9 +96,9 @@ __device__ __forceinline__ void run_item(const Phase &p, int it, int *nb, double
         break;
     case PH_AMR_PROLONG:
         if (p.odd)
-            amr_prolong_item<B, S, true>(p.a, p.cells, p.src, p.n, p.nsrc, p.m0, p.m1, p.om1, p.dt, t);
+            amr_prolong_item<B, S, true>(p.a, p.cells, p.gmask, p.src, p.n, p.nsrc, p.m0, p.m1, p.om1, p.dt, t);
         else
-            amr_prolong_item<B, S, false>(p.a, p.cells, p.src, p.n, p.nsrc, p.m0, p.m1, p.om1, p.dt, t);
+            amr_prolong_item<B, S, false>(p.a, p.cells, p.gmask, p.src, p.n, p.nsrc, p.m0, p.m1, p.om1, p.dt, t);
         break;
     case PH_AMR_RESTRICT:
         if (p.odd && p.odd2)

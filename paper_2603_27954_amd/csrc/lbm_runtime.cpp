@@ -287,6 +287,7 @@ static lbm_status amr_prolong(lbm_grid *g, int l, int sub)
         p.a = a;
         p.cells = pr.d_ghost;
         p.src = pr.d_ghost_src;
+        p.gmask = pr.d_ghost_mask;
         p.n = (int)pr.h_ghost.size();
         p.nsrc = (int)pr.h_src.size();
         p.m0 = pr.d_mom[0];
@@ -298,7 +299,7 @@ static lbm_status amr_prolong(lbm_grid *g, int l, int sub)
             g->rec->push_back(p);
         return LBM_OK;
     }
-    HIPX(g, launch_amr_prolong(g->B, g->d.storage, (int)(f.steps & 1), a, pr.d_ghost, pr.d_ghost_src,
+    HIPX(g, launch_amr_prolong(g->B, g->d.storage, (int)(f.steps & 1), a, pr.d_ghost, pr.d_ghost_mask, pr.d_ghost_src,
                                (int)pr.h_ghost.size(), (int)pr.h_src.size(), pr.d_mom[0],
                                sub ? pr.d_mom[1] : nullptr, (float)f.om1, level_dt(g, l + 1), g->stream));
     return LBM_OK;
@@ -323,7 +324,7 @@ static lbm_status amr_restrict(lbm_grid *g, int l)
         p.dt = level_dt(g, l);
         p.om2 = (float)f.om1;
         p.dt2 = level_dt(g, l + 1);
-        p.items = (p.n + 255) / 256;
+        p.items = (8 * p.n + 255) / 256;
         if (p.n > 0)
             g->rec->push_back(p);
         return LBM_OK;

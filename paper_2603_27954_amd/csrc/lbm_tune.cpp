@@ -134,7 +134,7 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
                 cand.push_back({best.threads, best.tile, best.occ_even, occ, best.xcd});
         } else if (pass == 3) {
             cand.clear();
-            for (int k : {1, 4, 16})
+            for (int k : {1, 4, 16, 64, 256})
                 cand.push_back({best.threads, best.tile, best.occ_even, best.occ_odd, k});
         }
         for (const Choice &c : cand) {
