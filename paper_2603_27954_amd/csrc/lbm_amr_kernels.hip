@@ -32,13 +32,18 @@ __global__ void __launch_bounds__(256) k_amr_prolong(const CollideArgs fine, con
                                 blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// 64 band cells per 256-thread work-group: two passes of eight lanes per cell,
+// then wave 0 rebuilds all 64
+constexpr int RESTRICT_WG = 64;
+
 template <int B, typename S, bool ODD_C, bool ODD_F>
 __global__ void __launch_bounds__(256) k_amr_restrict(const CollideArgs coarse, const CollideArgs fine,
                                                       const uint32_t *band, const uint32_t *child, int n, float om_c,
                                                       float dt_c, float om_f, float dt_f)
 {
-    amr_restrict_item<B, S, ODD_C, ODD_F>(coarse, fine, band, child, n, om_c, dt_c, om_f, dt_f,
-                                          blockIdx.x * blockDim.x + threadIdx.x);
+    __shared__ float rec[11][RESTRICT_WG];
+    amr_restrict_item<B, S, ODD_C, ODD_F, 256, RESTRICT_WG>(coarse, fine, band, child, n, om_c, dt_c, om_f, dt_f,
+                                                            blockIdx.x, rec);
 }
 
 // ---------------------------------------------------------------------------
@@ -72,7 +77,7 @@ template <int B, typename S>
 static void restrict_t(int odd_c, int odd_f, const CollideArgs &c, const CollideArgs &f, const uint32_t *band,
                        const uint32_t *child, int n, float om_c, float dt_c, float om_f, float dt_f, hipStream_t s)
 {
-    const dim3 grid((8 * n + 255) / 256), blk(256);  // eight lanes per band cell
+    const dim3 grid((n + RESTRICT_WG - 1) / RESTRICT_WG), blk(256);
 #define LBM_RS(OC, OF) \
     hipLaunchKernelGGL((k_amr_restrict<B, S, OC, OF>), grid, blk, 0, s, c, f, band, child, n, om_c, dt_c, om_f, dt_f)
     if (odd_c && odd_f) LBM_RS(true, true);

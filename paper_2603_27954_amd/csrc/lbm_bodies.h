@@ -12,6 +12,33 @@ namespace lbm {
 // collide and stream: dense (x-pencil) levels
 // ---------------------------------------------------------------------------
 
+// The collision of one cell (as collide()), writing first the coarse/fine
+// transfer record of the cell's pre-collision state when the level keeps
+// records and the cell is a prolongation source.
+__device__ __forceinline__ void write_record(float *out, int r, const Transfer &tr)
+{
+    float4 *o = reinterpret_cast<float4 *>(out + (size_t)MOM_REC * r);
+    o[0] = make_float4(tr.drho, tr.ux, tr.uy, tr.uz);
+    o[1] = make_float4(tr.d[0], tr.d[1], tr.d[2], tr.d[3]);
+    o[2] = make_float4(tr.d[4], tr.d[5], 0.0f, 0.0f);
+}
+
+// record index of cell own (-1: none); loaded before the populations so that
+// its latency overlaps theirs
+__device__ __forceinline__ int record_of(const CollideArgs &a, uint32_t own)
+{
+    return a.mom_idx ? a.mom_idx[own] : -1;
+}
+
+__device__ __forceinline__ void collide_rec(float (&g)[NQ], const CollideArgs &a, int r)
+{
+    Moments m = forward_moments(g);
+    if (r >= 0)
+        write_record(a.mom_out, r, to_transfer(m, a.om1, a.mom_dt));
+    relax_second(m, a.om1, a.om2, a.galilean != 0);
+    back_transform(m, g);
+}
+
 // Odd step when every wavefront lies in one x-row (nx a multiple of 64): y and
 // z are wave-uniform, so the eight neighbour-row offsets live in scalar
 // registers and each direction addresses (scalar base + row offset) + one of
@@ -29,6 +56,7 @@ __device__ __forceinline__ void dense_odd_rowwave(const CollideArgs &a, uint32_t
     const int zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
     const uint32_t vx[3] = {x == 0 ? own + (uint32_t)nx - 1u : own - 1u, own,
                             x == nx - 1 ? own + 1u - (uint32_t)nx : own + 1u};
+    const int rec = record_of(a, own);
     float g[NQ];
     const S *bk[NQ];
 #pragma unroll
@@ -50,7 +78,7 @@ __device__ __forceinline__ void dense_odd_rowwave(const CollideArgs &a, uint32_t
                 g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)tz * ny + ty];
         }
     }
-    collide(g, a.om1, a.om2, a.galilean != 0);
+    collide_rec(g, a, rec);
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
         const bool leaves = (at_in && qcx(k) == -1) || (at_out && qcx(k) == 1);
@@ -92,10 +120,11 @@ __device__ __forceinline__ void collide_dense_item(const CollideArgs &a, int ite
     float g[NQ];
 
     if (!ODD) {
+        const int rec = record_of(a, own);
 #pragma unroll
         for (int k = 0; k < NQ; ++k)
             g[k] = ldp_nt<S>(a.pop[k], own);
-        collide(g, a.om1, a.om2, a.galilean != 0);
+        collide_rec(g, a, rec);
 #pragma unroll
         for (int k = 0; k < NQ; ++k)
             stp_nt<S>(a.pop[qopp(k)], own, g[k]);
@@ -114,6 +143,7 @@ __device__ __forceinline__ void collide_dense_item(const CollideArgs &a, int ite
         return;
     }
     // odd: population opp(k) comes from slot k of x + c_k, f*_k goes back there
+    const int rec = record_of(a, own);
     const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
     const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
     const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
@@ -136,7 +166,7 @@ __device__ __forceinline__ void collide_dense_item(const CollideArgs &a, int ite
                 g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)tz * ny + ty];
         }
     }
-    collide(g, a.om1, a.om2, a.galilean != 0);
+    collide_rec(g, a, rec);
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
         const bool leaves = (at_in && qcx(k) == -1) || (at_out && qcx(k) == 1);
@@ -171,12 +201,13 @@ __device__ __forceinline__ void cell_update_block(const CollideArgs &a, int blk,
     constexpr int LB = B == 16 ? 4 : 3;
     const int x = c & (B - 1), y = (c >> LB) & (B - 1), z = c >> (2 * LB);
     const uint32_t own = (uint32_t)blk * CELLS + c;
+    const int rec = record_of(a, own);
     float g[NQ];
     if (!ODD) {
 #pragma unroll
         for (int k = 0; k < NQ; ++k)
             g[k] = ldp_nt<S>(a.pop[k], own);
-        collide(g, a.om1, a.om2, a.galilean != 0);
+        collide_rec(g, a, rec);
 #pragma unroll
         for (int k = 0; k < NQ; ++k)
             stp_nt<S>(a.pop[qopp(k)], own, g[k]);
@@ -192,7 +223,7 @@ __device__ __forceinline__ void cell_update_block(const CollideArgs &a, int blk,
 #pragma unroll
     for (int k = 0; k < NQ; ++k)
         g[qopp(k)] = ldp<S>(a.pop[k], addr[k]);
-    collide(g, a.om1, a.om2, a.galilean != 0);
+    collide_rec(g, a, rec);
 #pragma unroll
     for (int k = 0; k < NQ; ++k)
         stp<S>(a.pop[k], addr[k], g[k]);
@@ -300,11 +331,29 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return t;
 }
 
+// Work-group sums of three values at once (256 threads): lane tree within each
+// wave, then the waves in order; the result is in thread 0.  sh holds 12 doubles.
+__device__ __forceinline__ void block_sum3(double (&v)[3], double *sh)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        v[a] = wave_sum(v[a]);
+        if (lane == 0)
+            sh[4 * a + wv] = v[a];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            v[a] = ((sh[4 * a] + sh[4 * a + 1]) + sh[4 * a + 2]) + sh[4 * a + 3];
+    __syncthreads();
+}
+
 // The links are sorted by branch and each branch's run of links is cut into
 // pieces of at most LINK_PIECE links.  One work-group sums one piece in a
 // fixed order (lane tree, then waves in order) and thread 0 stores the sum in
 // piece_sum[3p .. 3p + 2].
-
 __device__ __forceinline__ void link_piece_sum(const float *lforce, const int *pstart, int p, double *piece_sum,
                                                double *sh)
 {
@@ -315,43 +364,41 @@ __device__ __forceinline__ void link_piece_sum(const float *lforce, const int *p
         v[1] += (double)lforce[3 * (size_t)l + 1];
         v[2] += (double)lforce[3 * (size_t)l + 2];
     }
-    for (int a = 0; a < 3; ++a) {
-        const double t = block_sum<256>(v[a], sh);
-        if (threadIdx.x == 0)
-            piece_sum[3 * p + a] = t;
-    }
+    block_sum3(v, sh);
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a)
+            piece_sum[3 * p + a] = v[a];
 }
 
 // Per-branch sums from the pieces of each branch, in piece order (the pieces of
 // branch s are segp[s] .. segp[s + 1]), stored in sample and added to
-// acc_branch; then the total over the branches in branch order (thread 0)
-// is added to acc_total and appended to the sample ring at the device-held
-// position ring_pos, which a replayed graph advances itself.  Called by the
-// whole work-group.
+// acc_branch; then the total over the branches (thread t adds branches t,
+// t + 256, ... in order, then block_sum3) is added to acc_total and appended
+// to the sample ring at the device-held position ring_pos, which a replayed
+// graph advances itself.  Called by the whole work-group (256 threads) after
+// an acquire of the piece sums.
 __device__ __forceinline__ void branch_totals(const double *piece_sum, const int *segp, int nseg, double *sample,
                                               double *acc_branch, double *acc_total, double *ring,
-                                              unsigned long long *ring_pos)
+                                              unsigned long long *ring_pos, double *sh)
 {
-    for (int s = threadIdx.x; s < nseg; s += blockDim.x) {
+    double tot[3] = {0.0, 0.0, 0.0};
+    for (int s = threadIdx.x; s < nseg; s += 256) {
         double t[3] = {0.0, 0.0, 0.0};
         for (int q = segp[s]; q < segp[s + 1]; ++q)
             for (int a = 0; a < 3; ++a)
-                t[a] += __builtin_nontemporal_load(&piece_sum[3 * q + a]);
+                t[a] += piece_sum[3 * q + a];
         for (int a = 0; a < 3; ++a) {
             sample[3 * s + a] = t[a];
             acc_branch[3 * s + a] += t[a];
+            tot[a] += t[a];
         }
     }
-    __syncthreads();
+    block_sum3(tot, sh);
     if (threadIdx.x == 0) {
-        double t[3] = {0.0, 0.0, 0.0};
-        for (int i = 0; i < nseg; ++i)
-            for (int a = 0; a < 3; ++a)
-                t[a] += sample[3 * i + a];
         const unsigned long long slot = *ring_pos % RING;
         for (int a = 0; a < 3; ++a) {
-            acc_total[a] += t[a];
-            ring[3 * slot + a] = t[a];
+            acc_total[a] += tot[a];
+            ring[3 * slot + a] = tot[a];
         }
         *ring_pos += 1ull;
     }
@@ -370,11 +417,7 @@ __device__ __forceinline__ void amr_moments_item(const CollideArgs &a, const uin
         return;
     float g[NQ];
     load_pre<B, S, ODD>(a, cells[t], g);
-    const Transfer tr = to_transfer(forward_moments(g), om1, dt);
-    float4 *o = reinterpret_cast<float4 *>(out + (size_t)MOM_REC * t);
-    o[0] = make_float4(tr.drho, tr.ux, tr.uy, tr.uz);
-    o[1] = make_float4(tr.d[0], tr.d[1], tr.d[2], tr.d[3]);
-    o[2] = make_float4(tr.d[4], tr.d[5], 0.0f, 0.0f);
+    write_record(out, t, to_transfer(forward_moments(g), om1, dt));
 }
 
 __device__ __forceinline__ void mom_load(const float *m, int s, float (&x)[12])
@@ -439,58 +482,72 @@ __device__ __forceinline__ void amr_prolong_item(const CollideArgs &fine, const 
     store_post_masked<B, S, ODD>(fine, ghosts[t], g, gmask[t]);
 }
 
-// Eight lanes per coarse band cell (t >> 3), lane q = t & 7 holding child q:
-// consecutive band cells run along x, so each population load of a wave
-// covers whole rows of the fine level.  The children's sums meet over a
-// butterfly of the eight lanes (fixed order); every lane rebuilds the cell and
-// stores the populations k with k % 8 == q.  Launch 8 n threads.
-template <int B, typename S, bool ODD_C, bool ODD_F>
+// One work-group item of NT threads covers the coarse band cells
+// it * CELLS .. + CELLS - 1 (CELLS <= NT) in two stages.  Stage 1, passes of
+// NT / 8 cells: eight lanes per cell, lane
+// q = t & 7 holding child q; consecutive band cells run along x, so each
+// population load of a wave covers whole rows of the fine level.  The
+// children's sums meet over a butterfly of the eight lanes (fixed order) and
+// go to the LDS record rec[.][cell].  Stage 2: threads 0 .. CELLS - 1, one per
+// cell, rebuild the cells and store their populations.  Called by the whole
+// work-group.
+template <int B, typename S, bool ODD_C, bool ODD_F, int NT, int CELLS>
 __device__ __forceinline__ void amr_restrict_item(const CollideArgs &coarse, const CollideArgs &fine,
                                                   const uint32_t *band, const uint32_t *child, int n, float om_c,
-                                                  float dt_c, float om_f, float dt_f, int t)
+                                                  float dt_c, float om_f, float dt_f, int it, float (*rec)[CELLS])
 {
-    const int cell = t >> 3, q = t & 7;
-    if (cell >= n)
-        return;  // whole groups of eight leave together
-    float v[11];
-#pragma unroll
-    for (int k = 0; k < 11; ++k)
-        v[k] = 0.0f;
-    const uint32_t c = child[(size_t)t];
-    if (c != FULL_MASK) {
-        float g[NQ];
-        load_pre<B, S, ODD_F>(fine, c, g);
-        const Transfer tr = to_transfer(forward_moments(g), om_f, dt_f);
-        const float rho = 1.0f + tr.drho;
-        v[0] = tr.drho;
-        v[1] = rho * tr.ux;
-        v[2] = rho * tr.uy;
-        v[3] = rho * tr.uz;
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            v[4 + k] = tr.d[k];
-        v[10] = 1.0f;
-    }
-#pragma unroll
-    for (int m = 1; m < 8; m <<= 1)
+    static_assert(CELLS <= NT && (8 * CELLS) % NT == 0, "whole passes of NT / 8 cells");
+    const int tid = (int)threadIdx.x, q = tid & 7;
+    const int base = it * CELLS;
+    for (int pass = 0; pass < 8 * CELLS / NT; ++pass) {
+        const int local = pass * (NT / 8) + (tid >> 3), cell = base + local;
+        float v[11];
 #pragma unroll
         for (int k = 0; k < 11; ++k)
-            v[k] += __shfl_xor(v[k], m, 8);
-    if (v[10] == 0.0f)
-        return;
-    const float ic = 1.0f / v[10];
-    Transfer tr;
-    tr.drho = v[0] * ic;
-    const float irho = ic / (1.0f + tr.drho);
-    tr.ux = v[1] * irho;
-    tr.uy = v[2] * irho;
-    tr.uz = v[3] * irho;
+            v[k] = 0.0f;
+        const uint32_t c = cell < n ? child[8 * (size_t)cell + q] : FULL_MASK;
+        if (c != FULL_MASK) {
+            float g[NQ];
+            load_pre<B, S, ODD_F>(fine, c, g);
+            const Transfer tr = to_transfer(forward_moments(g), om_f, dt_f);
+            const float rho = 1.0f + tr.drho;
+            v[0] = tr.drho;
+            v[1] = rho * tr.ux;
+            v[2] = rho * tr.uy;
+            v[3] = rho * tr.uz;
 #pragma unroll
-    for (int k = 0; k < 6; ++k)
-        tr.d[k] = v[4 + k] * ic;
-    float g[NQ];
-    back_transform(from_transfer(tr, om_c, dt_c), g);
-    store_pre_part<B, S, ODD_C>(coarse, band[cell], g, q, 8);
+            for (int k = 0; k < 6; ++k)
+                v[4 + k] = tr.d[k];
+            v[10] = 1.0f;
+        }
+#pragma unroll
+        for (int m = 1; m < 8; m <<= 1)
+#pragma unroll
+            for (int k = 0; k < 11; ++k)
+                v[k] += __shfl_xor(v[k], m, 8);
+        if (q == 0)
+#pragma unroll
+            for (int k = 0; k < 11; ++k)
+                rec[k][local] = v[k];
+    }
+    __syncthreads();
+    const int cell = base + tid;
+    if (tid < CELLS && cell < n && rec[10][tid] != 0.0f) {
+        const float ic = 1.0f / rec[10][tid];
+        Transfer tr;
+        tr.drho = rec[0][tid] * ic;
+        const float irho = ic / (1.0f + tr.drho);
+        tr.ux = rec[1][tid] * irho;
+        tr.uy = rec[2][tid] * irho;
+        tr.uz = rec[3][tid] * irho;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            tr.d[k] = rec[4 + k][tid] * ic;
+        float g[NQ];
+        back_transform(from_transfer(tr, om_c, dt_c), g);
+        store_pre<B, S, ODD_C>(coarse, band[cell], g);
+    }
+    __syncthreads();  // rec is refilled by the next item
 }
 
 }  // namespace lbm

@@ -18,6 +18,9 @@ constexpr uint32_t FULL_MASK = 0xFFFFFFFFu;
 constexpr int RING = 65536;
 // coarse/fine transfer record of one source cell: drho, ux, uy, uz, D (6), two pad floats
 constexpr int MOM_REC = 12;
+// coarse band cells per work-group item of the restriction in the persistent
+// launch (one per thread of its 256-thread work-groups)
+constexpr int RESTRICT_CELLS = 256;
 // links per piece of the force reduction (one work-group each)
 constexpr int LINK_PIECE = 2048;
 
@@ -44,6 +47,13 @@ struct CollideArgs {
     const float *in_prev;     // inlet fluctuation plane used at t-1 (3*ny*nz) or null
     const float *in_cur;      // inlet fluctuation plane used at t, or null
     float *gbuf;              // outlet ghost copies, 27*ny*nz
+    // coarse/fine transfer records of the level's prolongation sources, taken
+    // from the pre-collision state inside the collide launch: mom_idx[cell] is
+    // the source index (or -1), the record goes to mom_out[MOM_REC * index];
+    // mom_idx null: no records
+    const int32_t *mom_idx;
+    float *mom_out;
+    float mom_dt;             // level step in finest time units
 };
 
 // Arguments of the interpolated bounce-back kernel (finest level).

@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(256) k_branch_reduce(const float *lforce, cons
                                                        double *ring, unsigned long long *ring_pos,
                                                        unsigned *counter)
 {
-    __shared__ double sh[4];
+    __shared__ double sh[12];
     __shared__ bool last;
     link_piece_sum(lforce, pstart, blockIdx.x, piece_sum, sh);
     if (threadIdx.x == 0) {
@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(256) k_branch_reduce(const float *lforce, cons
         if (threadIdx.x == 0)
             __threadfence();
         __syncthreads();
-        branch_totals(piece_sum, segp, nseg, sample, acc_branch, acc_total, ring, ring_pos);
+        branch_totals(piece_sum, segp, nseg, sample, acc_branch, acc_total, ring, ring_pos, sh);
         if (threadIdx.x == 0)
             *counter = 0u;
     }

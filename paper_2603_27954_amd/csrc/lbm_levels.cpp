@@ -526,7 +526,6 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
 lbm_status amr_upload(AmrPlan &plan, std::vector<DevLevel> &lv, int B, const Alloc &alloc, hipStream_t s,
                       std::string *msg)
 {
-    (void)lv;
     (void)B;
     for (AmrPair &pr : plan.pairs) {
         auto put = [&](void **dst, const void *src, size_t bytes) -> lbm_status {
@@ -550,6 +549,19 @@ lbm_status amr_upload(AmrPlan &plan, std::vector<DevLevel> &lv, int B, const All
         for (int k = 0; k < 2; ++k)
             if ((st = alloc((void **)&pr.d_mom[k], std::max<size_t>(pr.h_src.size() * MOM_REC * sizeof(float), 16))) != LBM_OK)
                 return st;
+        {
+            const size_t li = (size_t)(&pr - plan.pairs.data());
+            std::vector<int32_t> idx(lv[li].dir_elems, -1);
+            for (size_t i = 0; i < pr.h_src.size(); ++i)
+                idx[pr.h_src[i]] = (int32_t)i;
+            if ((st = put((void **)&pr.d_mom_idx, idx.data(), idx.size() * 4)) != LBM_OK)
+                return st;
+            // the staging vector dies here: the copy must finish first
+            if (hipStreamSynchronize(s) != hipSuccess) {
+                *msg = "hipStreamSynchronize after the source map upload failed";
+                return LBM_E_DEVICE;
+            }
+        }
     }
     return LBM_OK;
 }

@@ -31,6 +31,7 @@ struct AmrPair {
     int32_t *d_ghost_src = nullptr;
     uint32_t *d_band_child = nullptr;
     float *d_mom[2] = {nullptr, nullptr};  // MOM_REC floats per source cell at T and T+1
+    int32_t *d_mom_idx = nullptr;          // per cell address of level l: source index or -1
 };
 
 struct AmrPlan {

@@ -56,7 +56,7 @@ __device__ __forceinline__ bool wait_done(unsigned *done, unsigned need, unsigne
 }
 
 template <int B, typename S>
-__device__ __forceinline__ void run_item(const Phase &p, int it, int *nb, double *sh)
+__device__ __forceinline__ void run_item(const Phase &p, int it, int *nb, double *sh, float (*rrec)[RESTRICT_CELLS])
 {
     const int t = it * 256 + (int)threadIdx.x;
     switch (p.kind) {
@@ -86,7 +86,7 @@ __device__ __forceinline__ void run_item(const Phase &p, int it, int *nb, double
         link_piece_sum(p.lforce, p.pstart, it, p.piece_sum, sh);
         break;
     case PH_BRANCH_TOTAL:
-        branch_totals(p.piece_sum, p.segp, p.nseg, p.sample, p.acc_branch, p.acc_total, p.ring, p.ring_pos);
+        branch_totals(p.piece_sum, p.segp, p.nseg, p.sample, p.acc_branch, p.acc_total, p.ring, p.ring_pos, sh);
         break;
     case PH_AMR_MOMENTS:
         if (p.odd)
@@ -102,13 +102,13 @@ __device__ __forceinline__ void run_item(const Phase &p, int it, int *nb, double
         break;
     case PH_AMR_RESTRICT:
         if (p.odd && p.odd2)
-            amr_restrict_item<B, S, true, true>(p.a, p.b, p.cells, p.child, p.n, p.om1, p.dt, p.om2, p.dt2, t);
+            amr_restrict_item<B, S, true, true, 256, RESTRICT_CELLS>(p.a, p.b, p.cells, p.child, p.n, p.om1, p.dt, p.om2, p.dt2, it, rrec);
         else if (p.odd)
-            amr_restrict_item<B, S, true, false>(p.a, p.b, p.cells, p.child, p.n, p.om1, p.dt, p.om2, p.dt2, t);
+            amr_restrict_item<B, S, true, false, 256, RESTRICT_CELLS>(p.a, p.b, p.cells, p.child, p.n, p.om1, p.dt, p.om2, p.dt2, it, rrec);
         else if (p.odd2)
-            amr_restrict_item<B, S, false, true>(p.a, p.b, p.cells, p.child, p.n, p.om1, p.dt, p.om2, p.dt2, t);
+            amr_restrict_item<B, S, false, true, 256, RESTRICT_CELLS>(p.a, p.b, p.cells, p.child, p.n, p.om1, p.dt, p.om2, p.dt2, it, rrec);
         else
-            amr_restrict_item<B, S, false, false>(p.a, p.b, p.cells, p.child, p.n, p.om1, p.dt, p.om2, p.dt2, t);
+            amr_restrict_item<B, S, false, false, 256, RESTRICT_CELLS>(p.a, p.b, p.cells, p.child, p.n, p.om1, p.dt, p.om2, p.dt2, it, rrec);
         break;
     default:
         break;
@@ -124,7 +124,8 @@ __global__ void __launch_bounds__(256) k_persist(const Phase *__restrict__ phase
                                                  unsigned *abort_flag)
 {
     __shared__ int nb[27];
-    __shared__ double sh[4];
+    __shared__ double sh[12];
+    __shared__ float rrec[11][RESTRICT_CELLS];
     __shared__ int claim_sh, ok_sh;
     unsigned *claimed = ctr, *done = ctr + n_phases, *left = ctr + 2 * n_phases;
     for (int ph = 0; ph < n_phases; ++ph) {
@@ -141,7 +142,7 @@ __global__ void __launch_bounds__(256) k_persist(const Phase *__restrict__ phase
                 break;
             const int i0 = c * p.chunk, i1 = min(i0 + p.chunk, p.items);
             for (int it = i0; it < i1; ++it)
-                run_item<B, S>(p, it, nb, sh);
+                run_item<B, S>(p, it, nb, sh, rrec);
             // every wave's stores reach the L2, then one agent-scope release
             // writes the L2 back before the chunk is counted
             __builtin_amdgcn_s_waitcnt(0);

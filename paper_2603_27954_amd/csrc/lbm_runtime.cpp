@@ -159,11 +159,23 @@ static lbm_status inflow_planes(lbm_grid *g)
     return LBM_OK;
 }
 
+// level step in finest time units
+static float level_dt(const lbm_grid *g, int l) { return (float)(1 << (g->L - 1 - l)); }
+
+// One step of level l.  A level with a finer neighbour also writes the
+// transfer records of its prolongation sources at time T from the
+// pre-collision state it reads anyway (records slot 0).
 static lbm_status level_collide(lbm_grid *g, int l)
 {
     DevLevel &v = g->lv[l];
     const int odd = (int)(v.steps & 1);
     CollideArgs a = collide_args(g, l);
+    if (l < g->L - 1) {
+        AmrPair &pr = g->amr.pairs[l];
+        a.mom_idx = pr.d_mom_idx;
+        a.mom_out = pr.d_mom[0];
+        a.mom_dt = level_dt(g, l);
+    }
     const bool inflow = l == 0 && g->turb && odd;
     if (g->rec && inflow)
         return fail(g, LBM_E_INVALID, "turbulent inflow is not available in the persistent form");
@@ -246,9 +258,6 @@ static lbm_status finest_links(lbm_grid *g, int odd_done)
     return LBM_OK;
 }
 
-// level step in finest time units
-static float level_dt(const lbm_grid *g, int l) { return (float)(1 << (g->L - 1 - l)); }
-
 // transfer quantities of the coarse source cells of pair l into slot 0 (time
 // T, before the coarse step) or 1 (T + 1, after it)
 static lbm_status amr_moments(lbm_grid *g, int l, int slot)
@@ -324,7 +333,7 @@ static lbm_status amr_restrict(lbm_grid *g, int l)
         p.dt = level_dt(g, l);
         p.om2 = (float)f.om1;
         p.dt2 = level_dt(g, l + 1);
-        p.items = (8 * p.n + 255) / 256;
+        p.items = (p.n + RESTRICT_CELLS - 1) / RESTRICT_CELLS;
         if (p.n > 0)
             g->rec->push_back(p);
         return LBM_OK;
@@ -336,15 +345,13 @@ static lbm_status amr_restrict(lbm_grid *g, int l)
 }
 
 // One step of level l and, recursively, the two sub-steps of each finer
-// level (coarse first): moments at T, coarse step, fine ghosts from T, fine
-// sub-step, moments at T+1, fine ghosts from the mean, fine sub-step,
-// restriction into the coarse band.
+// level (coarse first): coarse step (with the transfer records at T), fine
+// ghosts from T, fine sub-step, moments at T+1, fine ghosts from the mean,
+// fine sub-step, restriction into the coarse band.
 static lbm_status advance_level(lbm_grid *g, int l)
 {
     lbm_status st;
     const bool finest = l == g->L - 1;
-    if (!finest && (st = amr_moments(g, l, 0)) != LBM_OK)
-        return st;
     DevLevel &v = g->lv[l];
     const int odd = (int)(v.steps & 1);
     if ((st = level_collide(g, l)) != LBM_OK)
@@ -864,16 +871,28 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
          }, g->stream, &g->err)) != LBM_OK)
         return st;
 
-    // links on the finest level, sorted by branch (segments for the reduction)
+    // links on the finest level, sorted by branch (segments for the reduction),
+    // then by direction and cell address: neighbouring links of a wave then
+    // touch the same population array at nearby addresses
     {
         const DevLevel &fv = g->lv[g->L - 1];
         const int nl = (int)g->links.size();
         std::vector<int32_t> perm(nl);
         std::iota(perm.begin(), perm.end(), 0);
+        std::vector<int64_t> addr(nl);
+        for (int t = 0; t < nl; ++t) {
+            const int64_t c = g->links[t].cell;
+            addr[t] = level_cell_address(fv, g->B, (int)(c % d.nx), (int)((c / d.nx) % d.ny),
+                                         (int)(c / ((int64_t)d.nx * d.ny)));
+        }
         std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) {
             const int ba = g->links[a].branch < 0 ? n_b : g->links[a].branch;
             const int bc = g->links[c].branch < 0 ? n_b : g->links[c].branch;
-            return ba < bc;
+            if (ba != bc)
+                return ba < bc;
+            if (g->links[a].dir != g->links[c].dir)
+                return g->links[a].dir < g->links[c].dir;
+            return addr[a] < addr[c];
         });
         g->link_perm = perm;
         std::vector<uint32_t> af(nl), ap(nl), am(nl);

@@ -4,6 +4,7 @@
 // for the even and the odd step, and the run length of tiles per XCD -- keeps
 // the fastest and restores the grid state afterwards.  Choices are cached in a text file keyed by the grid
 // shape.
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -93,7 +94,9 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     lbm_status st = LBM_OK;
-    // times whole coarse steps (both parities) of candidate c
+    // times whole coarse steps (both parities) of candidate c: the fastest of
+    // three runs of 8 steps, so that one slow run (clock or power state)
+    // does not decide the choice
     auto time_choice = [&](const Choice &c, float *ms) -> lbm_status {
         g->threads = c.threads;
         g->tile = c.tile;
@@ -103,12 +106,17 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
         lbm_status s2 = grid_coarse_step(g);
         if (s2 == LBM_OK)
             s2 = grid_coarse_step(g);
-        (void)hipEventRecord(e0, g->stream);
-        for (int r = 0; r < 8 && s2 == LBM_OK; ++r)
-            s2 = grid_coarse_step(g);
-        (void)hipEventRecord(e1, g->stream);
-        (void)hipEventSynchronize(e1);
-        (void)hipEventElapsedTime(ms, e0, e1);
+        *ms = 1e30f;
+        for (int rep = 0; rep < 3 && s2 == LBM_OK; ++rep) {
+            (void)hipEventRecord(e0, g->stream);
+            for (int r = 0; r < 8 && s2 == LBM_OK; ++r)
+                s2 = grid_coarse_step(g);
+            (void)hipEventRecord(e1, g->stream);
+            (void)hipEventSynchronize(e1);
+            float t = 0.0f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            *ms = std::min(*ms, t);
+        }
         return s2;
     };
     Choice best = old;
