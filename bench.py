@@ -215,6 +215,23 @@ def surrogate_leg(lt, torch, n_trees, chunk=1 << 17):
     err = [abs(S.tree_cd(m, r["feat"], r["ld"], r["area_x"]) - r["cd"]) / r["cd"] for r in held]
     re_d = 10.0 ** X[:, 0]
     env = (float(re_d.min()), float(re_d.max()))
+    sweep = sweep_trees(lt, torch, m, env, n_trees, chunk)
+    m.close()
+    return {
+        "training": {"lbm_runs": len(train), "samples": int(len(X)), "lbm_seconds": round(lbm_s, 1),
+                     "epochs": 40, "train_seconds": round(train_s, 2), "final_loss": float(losses[-1]),
+                     "re_d_envelope": [round(env[0], 2), round(env[1], 1)]},
+        "held_out": {"runs": len(held), "cd_rel_err_mean": round(float(np.mean(err)), 4),
+                     "cd_rel_err_max": round(float(np.max(err)), 4)},
+        "sweep": sweep,
+    }
+
+
+def sweep_trees(lt, torch, m, env, n_trees, chunk=1 << 17):
+    """n_trees seeded trees (orders 1-6 in turn) at 25 Re_H from 1e3 to 1e9:
+    frontal areas, the network m on the matrix cores (training envelope env
+    of Re_D) and the analytic model, timed per kernel on the bench stream."""
+    stream = STREAM
     params = lt.tree_params(3, 1, 1.0, 0.3, [0.7] * 3, [0.7] * 3, [0.0, 120.0, 240.0], [35.0] * 3, [90.0] * 3,
                             jitter=5.0, seed=0)
     re_h = 10.0 ** np.linspace(3.0, 9.0, 25)
@@ -255,23 +272,26 @@ def surrogate_leg(lt, torch, n_trees, chunk=1 << 17):
         del rd, sd, area, cd, cda
     inferences = n_branch * len(re_h)
     tflops = MLP_FLOP * inferences / (sweep_ms * 1e-3) / 1e12
+    return {"trees": n_trees, "branches": n_branch, "re_h": [1e3, 1e9, len(re_h)], "inferences": inferences,
+            "surrogate_ms": round(sweep_ms, 2), "inferences_per_s": round(inferences / (sweep_ms * 1e-3), 1),
+            "analytic_ms": round(analytic_ms, 2), "frontal_area_ms": round(area_ms, 2),
+            "host_tree_generation_s": round(gen_s, 2),
+            "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4),
+                         "flop_per_inference": MLP_FLOP, "dtype": "bf16 operands, fp32 accumulate"},
+            "mean_cd_surrogate": [round(v / n_trees, 4) for v in sum_s],
+            "mean_cd_analytic": [round(v / n_trees, 4) for v in sum_a]}
+
+
+def sweep_only_leg(lt, torch, n_trees):
+    """The many-tree sweep alone, with an untrained network (seeded weights,
+    fixed feature scaling): the same kernels and work as in the surrogate leg,
+    without the LBM training runs (for profiling)."""
+    m = lt.Mlp(seed=3, stream=STREAM.cuda_stream)
+    m.set_scaling(np.array([2.0, 45.0, 2.0, 0.04, 0.5]), np.array([0.5, 30.0, 1.5, 0.04, 0.3]), 1.1, 0.7)
+    out = sweep_trees(lt, torch, m, (4.32, 152.3), n_trees)
     m.close()
-    return {
-        "training": {"lbm_runs": len(train), "samples": int(len(X)), "lbm_seconds": round(lbm_s, 1),
-                     "epochs": 40, "train_seconds": round(train_s, 2), "final_loss": float(losses[-1]),
-                     "re_d_envelope": [round(env[0], 2), round(env[1], 1)]},
-        "held_out": {"runs": len(held), "cd_rel_err_mean": round(float(np.mean(err)), 4),
-                     "cd_rel_err_max": round(float(np.max(err)), 4)},
-        "sweep": {"trees": n_trees, "branches": n_branch, "re_h": [1e3, 1e9, len(re_h)], "inferences": inferences,
-                  "surrogate_ms": round(sweep_ms, 2), "inferences_per_s": round(inferences / (sweep_ms * 1e-3), 1),
-                  "analytic_ms": round(analytic_ms, 2), "frontal_area_ms": round(area_ms, 2),
-                  "host_tree_generation_s": round(gen_s, 2),
-                  "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
-                               "unit": "TFLOP/s", "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4),
-                               "flop_per_inference": MLP_FLOP, "dtype": "bf16 operands, fp32 accumulate"},
-                  "mean_cd_surrogate": [round(v / n_trees, 4) for v in sum_s],
-                  "mean_cd_analytic": [round(v / n_trees, 4) for v in sum_a]},
-    }
+    return out
 
 
 def cpu_leg(lt, arr, nsteps):
@@ -311,6 +331,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the drag-surrogate leg")
     ap.add_argument("--surrogate-trees", type=int, default=1_000_000)
     ap.add_argument("--surrogate-only", action="store_true", help="run only the drag-surrogate leg (profiling)")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="run only the many-tree sweep with an untrained network (profiling its kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 512 MiB device copy (torch) as the reference dispatch "
                          "for the HBM byte counters")
@@ -341,6 +363,9 @@ def main():
     TUNE_CACHE = args.tune_cache
     if args.amr_only:
         print(json.dumps({"amr_3level": amr_leg(lt, torch, args.amr_steps, 4)}), flush=True)
+        return
+    if args.sweep_only:
+        print(json.dumps({"sweep": sweep_only_leg(lt, torch, args.surrogate_trees)}), flush=True)
         return
     if args.surrogate_only:
         print(json.dumps({"surrogate": surrogate_leg(lt, torch, args.surrogate_trees)}), flush=True)
