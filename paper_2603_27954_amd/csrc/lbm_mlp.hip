@@ -246,6 +246,11 @@ __device__ __forceinline__ void load_regs(const MlpDev &d, MlpRegs &r, int lane)
 // its scaled features as the B operand of the first layer (lane half 0 holds
 // features 0..4 and zeros, half 1 zeros); sb = b1[64], b2[64], w3[64] in LDS.
 // Both lanes of a column return the same value.
+// ReLU in one instruction: the median of (x, 0, FLT_MAX) is x for finite x >= 0
+// and 0 for x < 0 (fmaxf on a matrix-core result costs a canonicalising max
+// as well)
+__device__ __forceinline__ float relu(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 3.402823466e38f); }
+
 __device__ __forceinline__ float mlp_tile(const MlpRegs &r, bf16x8 b1, const float *sb, int lane)
 {
     // an offset the compiler cannot see through: the 192 LDS values are read
@@ -262,7 +267,7 @@ __device__ __forceinline__ float mlp_tile(const MlpRegs &r, bf16x8 b1, const flo
     bf16x8 b2[4];
     for (int s = 0; s < 4; ++s)
         for (int j = 0; j < 8; ++j)
-            b2[s][j] = (__bf16)fmaxf(c1[s >> 1][8 * (s & 1) + j], 0.0f);  // round to nearest even
+            b2[s][j] = (__bf16)relu(c1[s >> 1][8 * (s & 1) + j]);  // round to nearest even
     float y = 0.0f;
     for (int t = 0; t < 2; ++t) {
         f32x16 c2;
@@ -271,7 +276,7 @@ __device__ __forceinline__ float mlp_tile(const MlpRegs &r, bf16x8 b1, const flo
         for (int s = 0; s < 4; ++s)
             c2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a2[t][s], b2[s], c2, 0, 0, 0);
         for (int i = 0; i < 16; ++i)
-            y = fmaf(sb[128 + 32 * t + acc_row(i, lane)], fmaxf(c2[i], 0.0f), y);
+            y = fmaf(sb[128 + 32 * t + acc_row(i, lane)], relu(c2[i]), y);
     }
     return y + __shfl_xor(y, 32, 64);
 }
@@ -458,36 +463,33 @@ __global__ void __launch_bounds__(256) k_frontal_area(const float *rec, const in
         return;
     }
     // Branches go in chunks of 256, one per thread: each thread puts its
-    // branch's pixel box in LDS, a work-group scan of the boxes' pixel counts
-    // lays the chunk's pixels out in one index range, and the threads test
-    // that range with stride 256 (a thread's pixel index only grows, so it
-    // finds the owning branch by walking forward).
+    // branch's capsule and pixel-row range in LDS, a work-group scan of the
+    // row counts lays the chunk's rows out in one index range, and the threads
+    // take that range with stride 256 (a thread's row index only grows, so it
+    // finds the owning branch by walking forward).  A capsule is convex, so
+    // its pixels in one row form one span: the union of the spans of its two
+    // end discs and of its straight part, which are solved in closed form.
     for (int64_t c0 = b0; c0 < b1; c0 += 256) {
         const int64_t b = c0 + tid;
-        int np = 0;
+        int nr = 0;
         if (b < b1) {
             const float *rc = rec + b * SWEEP_REC;
             const float y0 = rc[5], z0 = rc[6], y1 = rc[7], z1 = rc[8], rr = rc[9];
-            const int py0 = max(0, (int)floorf((fminf(y0, y1) - rr - ylo) / h));
-            const int py1 = min(ny - 1, (int)floorf((fmaxf(y0, y1) + rr - ylo) / h));
             const int pz0 = max(0, (int)floorf((fminf(z0, z1) - rr - zlo) / h));
             const int pz1 = min(nz - 1, (int)floorf((fmaxf(z0, z1) + rr - zlo) / h));
-            const int wy = max(0, py1 - py0 + 1), wz = max(0, pz1 - pz0 + 1);
-            np = wy * wz;
+            nr = max(0, pz1 - pz0 + 1);
             const float dy = y1 - y0, dz = z1 - z0;
             box[tid][0] = y0;
             box[tid][1] = z0;
             box[tid][2] = dy;
             box[tid][3] = dz;
-            const float l2 = dy * dy + dz * dz;
-            box[tid][4] = l2 > 0.0f ? 1.0f / l2 : 0.0f;
-            box[tid][5] = rr * rr;
-            boxi[tid][0] = py0 | (pz0 << 16);
-            boxi[tid][1] = wy;
+            box[tid][4] = rr;
+            box[tid][5] = sqrtf(dy * dy + dz * dz);
+            boxi[tid][0] = pz0;
         }
-        // inclusive scan of np over the work-group
+        // inclusive scan of the row counts over the work-group
         const int lane = tid & 63, wave = tid >> 6;
-        int v = np;
+        int v = nr;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const int u = __shfl_up(v, o, 64);
@@ -500,29 +502,67 @@ __global__ void __launch_bounds__(256) k_frontal_area(const float *rec, const in
         int off = 0;
         for (int w = 0; w < wave; ++w)
             off += wsum[w];
-        pend[tid] = off + v;  // end of this branch's pixel range
+        pend[tid] = off + v;  // end of this branch's row range
         const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
         __syncthreads();
         int j = 0;
         for (int p = tid; p < total; p += 256) {
             while (pend[j] <= p)
                 ++j;
-            const int q = p - (j ? pend[j - 1] : 0);
-            const int wy = boxi[j][1];
-            int pz = (int)((float)q / (float)wy);
-            if (pz * wy > q)
-                --pz;
-            else if ((pz + 1) * wy <= q)
-                ++pz;
-            const int py = (boxi[j][0] & 0xFFFF) + q - pz * wy;
-            pz += boxi[j][0] >> 16;
-            const float cy = ylo + (py + 0.5f) * h - box[j][0], cz = zlo + (pz + 0.5f) * h - box[j][1];
-            const float dy = box[j][2], dz = box[j][3];
-            const float tt = fminf(fmaxf((cy * dy + cz * dz) * box[j][4], 0.0f), 1.0f);
-            const float ey = cy - tt * dy, ez = cz - tt * dz;
-            if (ey * ey + ez * ez <= box[j][5]) {
-                const int bit = pz * AREA_PIX + py;
-                atomicOr(&bits[bit >> 5], 1u << (bit & 31));
+            const int pz = boxi[j][0] + p - (j ? pend[j - 1] : 0);
+            const float y0 = box[j][0], dy = box[j][2], dz = box[j][3], r = box[j][4], len = box[j][5];
+            const float c = zlo + (pz + 0.5f) * h - box[j][1];  // row height relative to the axis start
+            float lo = 3.0e38f, hi = -3.0e38f;
+            // end discs
+            if (c * c <= r * r) {
+                const float sd = sqrtf(r * r - c * c);
+                lo = fminf(lo, -sd);
+                hi = fmaxf(hi, sd);
+            }
+            const float e = c - dz;
+            if (e * e <= r * r) {
+                const float sd = sqrtf(r * r - e * e);
+                lo = fminf(lo, dy - sd);
+                hi = fmaxf(hi, dy + sd);
+            }
+            // straight part: 0 <= (u dy + c dz) <= L^2 and |u dz - c dy| <= r L
+            if (len > 0.0f) {
+                float ul = -3.0e38f, uh = 3.0e38f;
+                bool ok = true;
+                if (dy != 0.0f) {
+                    const float a0 = -c * dz / dy, a1 = (len * len - c * dz) / dy;
+                    ul = fmaxf(ul, fminf(a0, a1));
+                    uh = fminf(uh, fmaxf(a0, a1));
+                } else {
+                    ok = c * dz >= 0.0f && c * dz <= len * len;
+                }
+                if (dz != 0.0f) {
+                    const float a0 = (c * dy - r * len) / dz, a1 = (c * dy + r * len) / dz;
+                    ul = fmaxf(ul, fminf(a0, a1));
+                    uh = fminf(uh, fmaxf(a0, a1));
+                } else {
+                    ok = ok && fabsf(c * dy) <= r * len;
+                }
+                if (ok && ul <= uh) {
+                    lo = fminf(lo, ul);
+                    hi = fmaxf(hi, uh);
+                }
+            }
+            if (lo > hi)
+                continue;
+            // pixel centres ylo + (py + 0.5) h inside [y0 + lo, y0 + hi]
+            const int pa = max(0, (int)ceilf((y0 + lo - ylo) / h - 0.5f));
+            const int pb = min(ny - 1, (int)floorf((y0 + hi - ylo) / h - 0.5f));
+            if (pa > pb)
+                continue;
+            const int ba = pz * AREA_PIX + pa, bb = pz * AREA_PIX + pb;
+            for (int w = ba >> 5; w <= (bb >> 5); ++w) {
+                uint32_t m = 0xFFFFFFFFu;
+                if (w == (ba >> 5))
+                    m &= 0xFFFFFFFFu << (ba & 31);
+                if (w == (bb >> 5))
+                    m &= 0xFFFFFFFFu >> (31 - (bb & 31));
+                atomicOr(&bits[w], m);
             }
         }
         __syncthreads();  // the boxes are refilled by the next chunk
