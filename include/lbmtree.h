@@ -201,6 +201,14 @@ lbm_status lbm_tree_place(lbm_branch *b, int32_t n, double target_h, const doubl
 lbm_status lbm_get_populations(lbm_grid *g, int32_t level, double *f);
 lbm_status lbm_set_populations(lbm_grid *g, int32_t level, const double *f);
 
+/* FP64 populations of n listed cells of level l, given as indices over the
+ * level's box (x + nx_l (y + ny_l z)): f[i*n + k] for cell cells[k] (host
+ * arrays).  Same values as lbm_get_populations at those cells, without the
+ * dense box (for grids whose finest box is too large to copy whole); cells the
+ * level does not hold, or out of range, read as NaN.  At most 2^26 cells per
+ * call. */
+lbm_status lbm_get_cells(lbm_grid *g, int32_t level, int64_t n, const int64_t *cells, double *f);
+
 /* Dense density and velocity (u[3*cell + a]) of level l; NaN where not held. */
 lbm_status lbm_get_fields(lbm_grid *g, int32_t level, double *rho, double *u);
 

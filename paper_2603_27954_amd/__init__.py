@@ -107,6 +107,7 @@ def lib():
         "lbm_get_links": [_P, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int8), _dp,
                           C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
         "lbm_get_block_map": [_P, C.c_int32, C.POINTER(C.c_int8)],
+        "lbm_get_cells": [_P, C.c_int32, C.c_int64, C.POINTER(C.c_int64), _dp],
         "lbm_mlp_create": [C.c_uint64, C.c_int32, _P, C.POINTER(_P)],
         "lbm_mlp_get_params": [_P, C.POINTER(C.c_float)],
         "lbm_mlp_set_params": [_P, C.POINTER(C.c_float)],
@@ -510,6 +511,15 @@ class Grid:
         nx, ny, nz = self.level_shape(level)
         f = np.empty((27, nx * ny * nz))
         _check(lib().lbm_get_populations(self.h, level, _dptr(f)), self.h)
+        return f
+
+    def get_cells(self, cells, level=0):
+        """FP64 populations (27, n) of the listed cells (indices over the
+        level's box); NaN where the level holds no cell."""
+        c = np.ascontiguousarray(cells, dtype=np.int64)
+        f = np.empty((27, len(c)))
+        _check(lib().lbm_get_cells(self.h, level, len(c), c.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(f)),
+               self.h)
         return f
 
     def set_populations(self, f, level=0):

@@ -1218,6 +1218,63 @@ lbm_status lbm_get_populations(lbm_grid *g, int32_t level, double *f)
     return LBM_OK;
 }
 
+lbm_status lbm_get_cells(lbm_grid *g, int32_t level, int64_t n, const int64_t *cells, double *f)
+{
+    if (!g || (n > 0 && (!cells || !f)) || n < 0)
+        return fail(g, LBM_E_INVALID, "null argument or negative count");
+    if (g->state != 1)
+        return fail(g, LBM_E_STATE, "set_geometry first");
+    if (lbm_status ps = check_persistent(g); ps != LBM_OK)
+        return ps;
+    if (lbm_status pi = prepare_inlet(g); pi != LBM_OK)
+        return pi;
+    if (level < 0 || level >= g->L)
+        return fail(g, LBM_E_INVALID, "level out of range");
+    if (n > (int64_t)1 << 26)
+        return fail(g, LBM_E_INVALID, "more than 2^26 cells in one call");
+    const DevLevel &v = g->lv[level];
+    const int B = g->B;
+    const int64_t N = (int64_t)v.nx * v.ny * v.nz;
+    std::vector<uint32_t> addr;
+    std::vector<int64_t> pos;
+    for (int64_t k = 0; k < n; ++k) {
+        for (int i = 0; i < 27; ++i)
+            f[i * n + k] = NAN;
+        const int64_t c = cells[k];
+        if (c < 0 || c >= N)
+            continue;
+        const int x = (int)(c % v.nx), y = (int)((c / v.nx) % v.ny), z = (int)(c / ((int64_t)v.nx * v.ny));
+        const int8_t kind = v.h_map[(size_t)(x / B) + (size_t)v.nbx * ((size_t)(y / B) + (size_t)v.nby * (z / B))];
+        if (kind != 1 && kind != 2)
+            continue;
+        addr.push_back((uint32_t)level_cell_address(v, B, x, y, z));
+        pos.push_back(k);
+    }
+    if (addr.empty())
+        return LBM_OK;
+    HIPX(g, hipStreamSynchronize(g->stream));
+    const size_t m = addr.size();
+    uint32_t *dc = nullptr;
+    double *dout = nullptr;
+    HIPX(g, hipMalloc((void **)&dc, sizeof(uint32_t) * m));
+    if (hipMalloc((void **)&dout, sizeof(double) * 27 * m) != hipSuccess) {
+        (void)hipFree(dc);
+        return fail(g, LBM_E_DEVICE, "hipMalloc failed");
+    }
+    HIPX(g, hipMemcpyAsync(dc, addr.data(), sizeof(uint32_t) * m, hipMemcpyHostToDevice, g->stream));
+    CollideArgs a = collide_args(g, level);
+    HIPX(g, launch_gather(g->B, g->d.storage, (int)(v.steps & 1), a, dc, (int)m, dout, m, g->stream));
+    std::vector<double> h(27 * m);
+    HIPX(g, hipMemcpyAsync(h.data(), dout, sizeof(double) * h.size(), hipMemcpyDeviceToHost, g->stream));
+    HIPX(g, hipStreamSynchronize(g->stream));
+    (void)hipFree(dout);
+    (void)hipFree(dc);
+    for (size_t t = 0; t < m; ++t)
+        for (int i = 0; i < 27; ++i)
+            f[i * n + pos[t]] = h[i * m + t];
+    return LBM_OK;
+}
+
 lbm_status lbm_set_populations(lbm_grid *g, int32_t level, const double *f)
 {
     if (!g || !f)

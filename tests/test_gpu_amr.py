@@ -16,7 +16,15 @@ CONFIGS = {
     "three_level_b8": dict(L=3, B=8, box=(256, 128, 128), com=(96.0, 64.0, 64.0), band=[0, 2, 0],
                            wake=[0, 0, 0]),
     "two_level_b16": dict(L=2, B=16, box=(128, 128, 128), com=(48.0, 64.0, 64.0), band=[0, 4], wake=[0, 0]),
+    # four levels (the smallest box whose refined blocks keep one coarse block
+    # from the faces): coarse 64x32x32, finest 512x256x256
+    "four_level_b8": dict(L=4, B=8, box=(512, 256, 256), com=(192.0, 128.0, 128.0), band=[0, 4, 2, 0],
+                          wake=[0, 0, 0, 0]),
 }
+# FP16 deviation storage: one rounding of deviations of O(0.05) to 11 bits per
+# stored population and sub-step, 3e-5 (as on the uniform grid), summed over
+# the finest sub-steps done
+TOL_STEP = {"fp32": 4e-6, "fp16": 3e-5}
 
 
 def _setup(gpu, name, storage="fp32", with_body=True):
@@ -41,11 +49,14 @@ def test_block_maps_match_oracle(gpu, name):
         assert np.array_equal(g.block_map(l).astype(np.uint8), sim.block_map(l)), f"level {l}"
 
 
-@pytest.mark.parametrize("name", ["two_level_b8", "three_level_b8", "two_level_b16"])
-def test_coarse_steps_match_oracle(gpu, name):
-    print(f"[amr steps] {name}", flush=True)
-    g, sim, solid, b = _setup(gpu, name)
+@pytest.mark.parametrize("name,storage", [("two_level_b8", "fp32"), ("three_level_b8", "fp32"),
+                                          ("two_level_b16", "fp32"), ("four_level_b8", "fp32"),
+                                          ("three_level_b8", "fp16"), ("four_level_b8", "fp16")])
+def test_coarse_steps_match_oracle(gpu, name, storage):
+    print(f"[amr steps] {name} {storage}", flush=True)
+    g, sim, solid, b = _setup(gpu, name, storage)
     L = CONFIGS[name]["L"]
+    tol = TOL_STEP[storage] * (1 if storage == "fp32" else 1 << (L - 1))
     for step in range(3):
         g.step(1)
         sim.step(1)
@@ -54,16 +65,15 @@ def test_coarse_steps_match_oracle(gpu, name):
             act = cls == O.CLS_ACTIVE
             if l == L - 1:
                 act &= solid == 0
-            fg = g.get_populations(l)
-            fo = sim.get_f(l)
-            err = np.abs(fg[:, act] - fo[:, act]).max()
+            idx = np.flatnonzero(act)
+            err = np.abs(g.get_cells(idx, l) - sim.get_f(l)[:, idx]).max()
             print(f"  coarse step {step + 1} level {l}: {act.sum()} active cells, max |df| = {err:.3e}",
                   flush=True)
-            assert np.isfinite(err) and err < 4e-6 * (step + 1)
+            assert np.isfinite(err) and err < tol * (step + 1)
     fo = sim.force_log()
     fgs = g.drag_series(len(fo))
     assert fgs.shape == fo.shape
-    assert np.abs(fgs - fo).max() < 2e-5 * np.abs(fo).max()
+    assert np.abs(fgs - fo).max() < (2e-5 if storage == "fp32" else 2e-3) * np.abs(fo).max()
 
 
 def test_two_level_run_cd_matches_oracle(gpu):

@@ -78,6 +78,40 @@ def test_three_level_turbulent_inflow_matches_oracle(gpu):
     assert np.abs(fgs - fo).max() < 2e-5 * np.abs(fo).max()
 
 
+def test_four_level_fp16_turbulent_inflow_matches_oracle(gpu):
+    """The production form of the turbulent-inflow workload at a size the
+    oracle runs: four levels, FP16 deviation storage, I_u = 8 %.  Tolerance:
+    the FP16 storage rounding of 3e-5 per finest sub-step (see the uniform
+    tests), summed over the sub-steps done."""
+    print("[inflow amr4 fp16] 2 coarse steps", flush=True)
+    L, B = 4, 8
+    nx, ny, nz = 512, 256, 256
+    b = O.build_tree(O.cfg1_tree_params(), 0.0, [192.0, 128.0, 128.0])
+    band, wake = [0, 4, 2, 0], [0, 0, 0, 0]
+    g = gpu.Grid(nx, ny, nz, u_in=U, re_h=100.0, block_edge=B, levels=L, storage="fp16", drag_every=1, **TURB)
+    g.set_geometry(b, refine={"band": band, "wake": wake})
+    solid = O.voxelize(b, nx, ny, nz)
+    lk = O.links(b, solid, nx, ny, nz)
+    nu = U * O.tree_height(b) / 100.0
+    sim = O.AmrSim(L, B, nx, ny, nz, U, nu, b, band, wake, solid=solid, link=lk, n_branch=len(b))
+    d0 = 1 << (L - 1)
+    sim.set_inlet_series(_planes(ny // d0, nz // d0, float(d0), 8, float(d0)))
+    for step in range(2):
+        g.step(1)
+        sim.step(1)
+        for l in range(L):
+            act = sim.classes(l) == O.CLS_ACTIVE
+            if l == L - 1:
+                act &= solid == 0
+            idx = np.flatnonzero(act)
+            err = np.abs(g.get_cells(idx, l) - sim.get_f(l)[:, idx]).max()
+            print(f"  coarse step {step + 1} level {l}: max|df| {err:.2e}", flush=True)
+            assert np.isfinite(err) and err < 3e-5 * d0 * (step + 1)
+    fo = sim.force_log()
+    fgs = g.drag_series(len(fo))
+    assert np.abs(fgs - fo).max() < 2e-3 * np.abs(fo).max()
+
+
 @pytest.mark.parametrize("levels", [1, 3])
 def test_graph_replay_keeps_the_inflow_time(gpu, levels):
     print(f"[inflow graph] levels={levels}", flush=True)
