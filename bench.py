@@ -338,7 +338,7 @@ def main():
                          "for the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py runs on one GPU only: there is no multi-GPU path (the sharding design is documented, not built)",
               file=sys.stderr)
         sys.exit(2)
 
