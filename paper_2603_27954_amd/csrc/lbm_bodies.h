@@ -59,10 +59,13 @@ __device__ __forceinline__ void dense_odd_rowwave(const CollideArgs &a, uint32_t
     const int rec = record_of(a, own);
     float g[NQ];
     const S *bk[NQ];
+    uint32_t sink[NQ];  // offset of this row's spare element from bk[k] (wave-uniform)
+    const int64_t ncell = (int64_t)nx * ny * nz + (int64_t)(row & (uint32_t)(DENSE_SINK - 1));
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
         const int64_t roff = ((int64_t)ys[qcy(k) + 1] + (int64_t)ny * zs[qcz(k) + 1] - ((int64_t)y + (int64_t)ny * z)) * nx;
         bk[k] = reinterpret_cast<const S *>(a.pop[k]) + roff;
+        sink[k] = (uint32_t)(ncell - roff);
     }
 #pragma unroll
     for (int k = 0; k < NQ; ++k)
@@ -79,11 +82,13 @@ __device__ __forceinline__ void dense_odd_rowwave(const CollideArgs &a, uint32_t
         }
     }
     collide_rec(g, a, rec);
+    // every lane stores every direction (scalar base, 32-bit lane offset); a
+    // population that leaves through a face goes to the spare elements, which
+    // nothing reads
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
         const bool leaves = (at_in && qcx(k) == -1) || (at_out && qcx(k) == 1);
-        if (!leaves)
-            stp<S>(const_cast<S *>(bk[k]), vx[qcx(k) + 1], g[k]);
+        stp<S>(const_cast<S *>(bk[k]), leaves ? sink[k] : vx[qcx(k) + 1], g[k]);
     }
     if (at_in) {
 #pragma unroll

@@ -26,6 +26,11 @@ constexpr int LINK_PIECE = 2048;
 
 // Arguments of the collide-and-stream kernel of one level.
 constexpr int DENSE_TILE = 256;  // cells per work item of a dense level
+// spare elements after a dense level's cells in every direction array: the
+// odd step's populations that leave through a face land at row index mod
+// DENSE_SINK, so concurrent rows write different elements
+constexpr int DENSE_SINK = 4096;
+constexpr size_t DENSE_ALIGN = (size_t)1 << 19;  // elements
 
 struct CollideArgs {
     void *pop[27];            // per-direction arrays (storage type)
