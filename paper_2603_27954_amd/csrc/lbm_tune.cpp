@@ -95,8 +95,9 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     (void)hipEventCreate(&e1);
     lbm_status st = LBM_OK;
     // times whole coarse steps (both parities) of candidate c: the fastest of
-    // three runs of 8 steps, so that one slow run (clock or power state)
-    // does not decide the choice
+    // five runs of `reps` steps, so that one slow run (clock or power state)
+    // does not decide the choice; `reps` makes each run last at least 25 ms
+    int reps = 8;
     auto time_choice = [&](const Choice &c, float *ms) -> lbm_status {
         g->threads = c.threads;
         g->tile = c.tile;
@@ -107,9 +108,9 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
         if (s2 == LBM_OK)
             s2 = grid_coarse_step(g);
         *ms = 1e30f;
-        for (int rep = 0; rep < 3 && s2 == LBM_OK; ++rep) {
+        for (int rep = 0; rep < 5 && s2 == LBM_OK; ++rep) {
             (void)hipEventRecord(e0, g->stream);
-            for (int r = 0; r < 8 && s2 == LBM_OK; ++r)
+            for (int r = 0; r < reps && s2 == LBM_OK; ++r)
                 s2 = grid_coarse_step(g);
             (void)hipEventRecord(e1, g->stream);
             (void)hipEventSynchronize(e1);
@@ -121,8 +122,15 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     };
     Choice best = old;
     float best_ms = 1e30f;
-    // coordinate search: block tiles (refined levels), then the occupancy caps
-    // of the even and of the odd collide kernels
+    {
+        float ms = 0.0f;
+        st = time_choice(old, &ms);
+        if (st == LBM_OK && ms > 0.0f)
+            reps = std::min(64, std::max(8, (int)(25.0f * 8 / ms))) & ~1;  // even: both parities alike
+    }
+    // search in passes: block tiles (refined levels); the occupancy cap of the
+    // even collide kernel; the odd kernel's cap jointly with the XCD run length
+    // (the best cap depends on the tile order); the even cap again
     const int cells = g->B * g->B * g->B;
     std::vector<Choice> cand;
     if (g->L > 1)
@@ -132,18 +140,15 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     else
         cand.push_back(best);
     for (int pass = 0; pass < 4 && st == LBM_OK; ++pass) {
-        if (pass == 1) {
+        if (pass == 1 || pass == 3) {
             cand.clear();
             for (int occ : {0, 2, 3, 4, 6})
                 cand.push_back({best.threads, best.tile, occ, best.occ_odd, best.xcd});
         } else if (pass == 2) {
             cand.clear();
             for (int occ : {0, 2, 3, 4})
-                cand.push_back({best.threads, best.tile, best.occ_even, occ, best.xcd});
-        } else if (pass == 3) {
-            cand.clear();
-            for (int k : {1, 4, 16, 64, 256})
-                cand.push_back({best.threads, best.tile, best.occ_even, best.occ_odd, k});
+                for (int k : {1, 4, 16, 64, 256})
+                    cand.push_back({best.threads, best.tile, best.occ_even, occ, k});
         }
         for (const Choice &c : cand) {
             float ms = 0.0f;
