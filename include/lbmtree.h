@@ -366,8 +366,15 @@ lbm_status lbm_timing_enable(lbm_grid *g, int32_t enable);
 lbm_status lbm_timing_read(lbm_grid *g, double *collide_ms, int64_t *collide_launches, double *links_ms,
                            int64_t *links_launches);
 
-/* Picks the collide-kernel tile by timing the candidates on this grid; caches
- * the choice in cache_path (may be NULL). */
+/* Picks the collide kernels' launch shapes (block tile and threads, an
+ * occupancy cap per parity, the XCD run length) by timing coarse steps of each
+ * candidate on this grid, then restores the populations, the force
+ * accumulators and the step counters.  Appends the choice to the text file
+ * cache_path (may be NULL), one line per grid key; a later call with a key
+ * already in the file takes the shapes from it without timing.  Allocates a
+ * device copy of every level for the duration of the call (LBM_E_NOMEM when
+ * that fails, the grid unchanged); LBM_E_DEVICE when a copy of the state
+ * fails; LBM_E_STATE before lbm_set_geometry.  Synchronous. */
 lbm_status lbm_autotune(lbm_grid *g, const char *cache_path);
 
 /* Checkpoint of populations, step counters and force accumulators. */

@@ -71,19 +71,31 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     const size_t eb = grid_storage_bytes(g->d.storage);
     // back up the evolving state
     std::vector<void *> backup(g->L, nullptr);
+    auto free_backup = [&]() {
+        for (void *p : backup)
+            if (p) (void)hipFree(p);
+    };
+    hipError_t ce = hipSuccess;  // first failing copy
+    auto keep = [&](hipError_t e) {
+        if (ce == hipSuccess) ce = e;
+    };
     for (int l = 0; l < g->L; ++l) {
         const size_t bytes = g->lv[l].dir_elems * 27 * eb;
         if (hipMalloc(&backup[l], bytes) != hipSuccess) {
-            for (void *p : backup)
-                if (p) (void)hipFree(p);
+            free_backup();
             return grid_fail(g, LBM_E_NOMEM, "autotune backup allocation failed");
         }
-        (void)hipMemcpyAsync(backup[l], g->lv[l].pop, bytes, hipMemcpyDeviceToDevice, g->stream);
+        keep(hipMemcpyAsync(backup[l], g->lv[l].pop, bytes, hipMemcpyDeviceToDevice, g->stream));
     }
     std::vector<double> acc(3 * (size_t)g->nseg + 3);
-    (void)hipMemcpyAsync(acc.data(), g->d_acc_branch, sizeof(double) * 3 * g->nseg, hipMemcpyDeviceToHost, g->stream);
-    (void)hipMemcpyAsync(acc.data() + 3 * g->nseg, g->d_acc_total, sizeof(double) * 3, hipMemcpyDeviceToHost, g->stream);
-    (void)hipStreamSynchronize(g->stream);
+    keep(hipMemcpyAsync(acc.data(), g->d_acc_branch, sizeof(double) * 3 * g->nseg, hipMemcpyDeviceToHost, g->stream));
+    keep(hipMemcpyAsync(acc.data() + 3 * g->nseg, g->d_acc_total, sizeof(double) * 3, hipMemcpyDeviceToHost,
+                        g->stream));
+    keep(hipStreamSynchronize(g->stream));
+    if (ce != hipSuccess) {  // nothing has been run yet: the grid is unchanged
+        free_backup();
+        return grid_fail(g, LBM_E_DEVICE, std::string("autotune state backup: ") + hipGetErrorString(ce));
+    }
     std::vector<int64_t> steps(g->L);
     for (int l = 0; l < g->L; ++l)
         steps[l] = g->lv[l].steps;
@@ -165,14 +177,17 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     (void)hipEventDestroy(e1);
     // restore
     for (int l = 0; l < g->L; ++l) {
-        (void)hipMemcpyAsync(g->lv[l].pop, backup[l], g->lv[l].dir_elems * 27 * eb, hipMemcpyDeviceToDevice, g->stream);
+        keep(hipMemcpyAsync(g->lv[l].pop, backup[l], g->lv[l].dir_elems * 27 * eb, hipMemcpyDeviceToDevice,
+                            g->stream));
         g->lv[l].steps = steps[l];
     }
-    (void)hipMemcpyAsync(g->d_acc_branch, acc.data(), sizeof(double) * 3 * g->nseg, hipMemcpyHostToDevice, g->stream);
-    (void)hipMemcpyAsync(g->d_acc_total, acc.data() + 3 * g->nseg, sizeof(double) * 3, hipMemcpyHostToDevice, g->stream);
-    (void)hipStreamSynchronize(g->stream);
-    for (void *p : backup)
-        (void)hipFree(p);
+    keep(hipMemcpyAsync(g->d_acc_branch, acc.data(), sizeof(double) * 3 * g->nseg, hipMemcpyHostToDevice, g->stream));
+    keep(hipMemcpyAsync(g->d_acc_total, acc.data() + 3 * g->nseg, sizeof(double) * 3, hipMemcpyHostToDevice,
+                        g->stream));
+    keep(hipStreamSynchronize(g->stream));
+    free_backup();
+    if (ce != hipSuccess && st == LBM_OK)
+        st = grid_fail(g, LBM_E_DEVICE, std::string("autotune state restore: ") + hipGetErrorString(ce));
     g->coarse_steps = cs;
     g->finest_steps = fs;
     g->samples = sm;
