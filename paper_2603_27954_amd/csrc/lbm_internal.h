@@ -128,7 +128,8 @@ struct DevLevel {
     void *pop = nullptr;
     int *nbr = nullptr;
     int *bxyz = nullptr;
-    uint2 *work = nullptr;    // collide work list (unit, mask id): dense tiles or blocks
+    uint2 *work = nullptr;    // collide work list (unit, mask id): dense tiles or blocks, in memory order
+    uint2 *work_odd = nullptr;  // the same items for odd steps of a block level, x fastest (null: use work)
     int n_work = 0;
     uint2 *leaf = nullptr;    // leaf-cell work list (mass, fields)
     int n_leaf = 0;
@@ -144,7 +145,7 @@ struct DevLevel {
     std::vector<int> h_nbr;           // 27 per block
     std::vector<int8_t> h_map;        // block map over the lattice (0 none, 1 leaf, 2 refined, 3 ghost)
     std::vector<int> h_lattice_to_block;  // -1 when absent
-    std::vector<uint2> h_work, h_leaf;
+    std::vector<uint2> h_work, h_work_odd, h_leaf;
     std::vector<uint32_t> h_masks;
 };
 

@@ -419,6 +419,16 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
             push(v.h_work, mw, nw);
             push(v.h_leaf, ml, nl);
         }
+        // The odd step reads one element of the next block's row at each x
+        // face.  Running blocks that share an x face close together lets the
+        // L2 serve that line to both; the even step keeps memory order.
+        v.h_work_odd = v.h_work;
+        std::stable_sort(v.h_work_odd.begin(), v.h_work_odd.end(), [&](const uint2 &p, const uint2 &q) {
+            const int *u = &v.h_bxyz[3 * (size_t)p.x], *w = &v.h_bxyz[3 * (size_t)q.x];
+            if (u[2] != w[2]) return u[2] < w[2];
+            if (u[1] != w[1]) return u[1] < w[1];
+            return u[0] < w[0];
+        });
     }
 
     // ---- coarse/fine plans -------------------------------------------------

@@ -170,6 +170,8 @@ static lbm_status level_collide(lbm_grid *g, int l)
     DevLevel &v = g->lv[l];
     const int odd = (int)(v.steps & 1);
     CollideArgs a = collide_args(g, l);
+    if (odd && v.work_odd)
+        a.work = v.work_odd;
     if (l < g->L - 1) {
         AmrPair &pr = g->amr.pairs[l];
         a.mom_idx = pr.d_mom_idx;
@@ -864,6 +866,8 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
         if ((st = upload(g, &v.nbr, v.h_nbr)) != LBM_OK || (st = upload(g, &v.bxyz, v.h_bxyz)) != LBM_OK ||
             (st = upload(g, &v.work, v.h_work)) != LBM_OK || (st = upload(g, &v.leaf, v.h_leaf)) != LBM_OK ||
             (st = upload(g, &v.masks, v.h_masks)) != LBM_OK)
+            return st;
+        if (!v.h_work_odd.empty() && (st = upload(g, &v.work_odd, v.h_work_odd)) != LBM_OK)
             return st;
         v.n_work = (int)v.h_work.size();
         v.n_leaf = (int)v.h_leaf.size();
