@@ -245,9 +245,11 @@ __device__ __forceinline__ void collide_block_item(const CollideArgs &a, int wg,
         return;
     const uint2 w = a.work[item];
     const int blk = (int)w.x;
-    if (threadIdx.x < 27)
-        nb[threadIdx.x] = a.nbr[(size_t)blk * 27 + threadIdx.x];
-    __syncthreads();
+    if (ODD) {  // only the odd step reaches into neighbouring blocks
+        if (threadIdx.x < 27)
+            nb[threadIdx.x] = a.nbr[(size_t)blk * 27 + threadIdx.x];
+        __syncthreads();
+    }
     const int tile = CELLS / a.parts;
     const int c0 = part * tile;
     const uint32_t *mask = w.y == FULL_MASK ? nullptr : a.masks + (size_t)w.y * (CELLS / 32);
@@ -364,10 +366,21 @@ __device__ __forceinline__ void link_piece_sum(const float *lforce, const int *p
 {
     const int s0 = pstart[p], s1 = pstart[p + 1];
     double v[3] = {0.0, 0.0, 0.0};
-    for (int l = s0 + (int)threadIdx.x; l < s1; l += 256) {
-        v[0] += (double)lforce[3 * (size_t)l];
-        v[1] += (double)lforce[3 * (size_t)l + 1];
-        v[2] += (double)lforce[3 * (size_t)l + 2];
+    for (int l0 = s0 + (int)threadIdx.x; l0 < s1; l0 += 8 * 256) {
+        // eight links of this lane in flight at once, added in link order
+        float buf[8][3];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int l = l0 + 256 * i;
+            if (l < s1)
+                for (int a = 0; a < 3; ++a)
+                    buf[i][a] = lforce[3 * (size_t)l + a];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (l0 + 256 * i < s1)
+                for (int a = 0; a < 3; ++a)
+                    v[a] += (double)buf[i][a];
     }
     block_sum3(v, sh);
     if (threadIdx.x == 0)
@@ -389,9 +402,21 @@ __device__ __forceinline__ void branch_totals(const double *piece_sum, const int
     double tot[3] = {0.0, 0.0, 0.0};
     for (int s = threadIdx.x; s < nseg; s += 256) {
         double t[3] = {0.0, 0.0, 0.0};
-        for (int q = segp[s]; q < segp[s + 1]; ++q)
-            for (int a = 0; a < 3; ++a)
-                t[a] += piece_sum[3 * q + a];
+        const int q1 = segp[s + 1];
+        for (int q = segp[s]; q < q1; q += 8) {
+            // eight piece sums in flight at once, added in piece order
+            double buf[8][3];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (q + i < q1)
+                    for (int a = 0; a < 3; ++a)
+                        buf[i][a] = piece_sum[3 * (q + i) + a];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (q + i < q1)
+                    for (int a = 0; a < 3; ++a)
+                        t[a] += buf[i][a];
+        }
         for (int a = 0; a < 3; ++a) {
             sample[3 * s + a] = t[a];
             acc_branch[3 * s + a] += t[a];
