@@ -22,7 +22,7 @@ constexpr int MOM_REC = 12;
 // launch (one per thread of its 256-thread work-groups)
 constexpr int RESTRICT_CELLS = 256;
 // links per piece of the force reduction (one work-group each)
-constexpr int LINK_PIECE = 2048;
+constexpr int LINK_PIECE = 8192;
 
 // Arguments of the collide-and-stream kernel of one level.
 constexpr int DENSE_TILE = 256;  // cells per work item of a dense level
