@@ -398,11 +398,38 @@ class AmrSim:
         lib().or_amr_branch_force(self.h, _ptr(out))
         return out.reshape(-1, 3)[: self.n_branch]
 
+    def prolong_only(self, l):
+        """Ghost cells of level l + 1 rebuilt from level l's present state
+        (the prolongation from time T alone, no stepping)."""
+        lib().or_amr_prolong_only(self.h, l)
+
+    def restrict_only(self, l):
+        """Band cells of level l rebuilt from level l + 1's present state."""
+        lib().or_amr_restrict_only(self.h, l)
+
     def fields(self, l):
         f = self.get_f(l)
         rho = f.sum(0)
         u = (f.T @ CVEC) / rho[:, None]
         return rho, u
+
+
+def amr_maps(L, B, nx, ny, nz, branches, band, wake):
+    """Block maps of every level (0 none, 1 leaf, 2 refined, 3 ghost storage;
+    x fastest over each level's block lattice) from the refinement rule alone,
+    without the dense state of AmrSim.  Raises ValueError when a refined region
+    comes too close to the box faces."""
+    b = np.ascontiguousarray(branches, dtype=np.float64).reshape(-1, 10)
+    bd = (C.c_int * 4)(*[int(v) for v in (list(band) + [0] * 4)[:4]])
+    wk = (C.c_int * 4)(*[int(v) for v in (list(wake) + [0] * 4)[:4]])
+    maps = []
+    for l in range(L):
+        h = 1 << (L - 1 - l)
+        maps.append(np.zeros((nx // h // B) * (ny // h // B) * (nz // h // B), np.uint8))
+    ptrs = (C.c_void_p * 4)(*([m.ctypes.data for m in maps] + [None] * (4 - L)))
+    if lib().or_amr_maps(L, B, nx, ny, nz, _ptr(b), len(b), bd, wk, ptrs) != 0:
+        raise ValueError("invalid refinement: a refined region comes too close to the box faces")
+    return maps
 
 
 def cell_transfer(f, omega1, dt):

@@ -28,3 +28,10 @@ def bind(L):
         L.or_amr_set_inlet.argtypes = [C.c_void_p, _dp, C.c_int64]
         L.or_cell_transfer.argtypes = [_dp, C.c_double, C.c_double, _dp]
         L.or_cell_rebuild.argtypes = [_dp, C.c_double, C.c_double, _dp]
+    if hasattr(L, "or_amr_prolong_only"):
+        L.or_amr_prolong_only.argtypes = [C.c_void_p, C.c_int]
+        L.or_amr_restrict_only.argtypes = [C.c_void_p, C.c_int]
+    if hasattr(L, "or_amr_maps"):
+        L.or_amr_maps.restype = C.c_int
+        L.or_amr_maps.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dp, C.c_int, _ip, _ip,
+                                  C.POINTER(C.c_void_p)]

@@ -762,3 +762,45 @@ void or_amr_branch_force(const or_amr *a, double *out)
     if (a->branch_force)
         memcpy(out, a->branch_force, sizeof(double) * 3 * (size_t)a->n_branch);
 }
+
+/* Block maps of every level without the state (the refinement rule of
+ * or_amr_create alone), for boxes too large to hold as dense FP64 levels.
+ * maps[l] receives level l's map (nbx_l * nby_l * nbz_l values, 0 none,
+ * 1 leaf, 2 refined, 3 ghost storage).  Returns 0, or -1 when a refined
+ * region comes too close to the box faces. */
+int or_amr_maps(int L, int B, int nx, int ny, int nz, const double *br, int n, const int *band, const int *wake,
+                uint8_t *const *maps)
+{
+    or_amr a;
+    memset(&a, 0, sizeof a);
+    a.L = L;
+    a.B = B;
+    for (int l = 0; l < L; l++) {
+        int h = 1 << (L - 1 - l);
+        a.lnx[l] = nx / h;
+        a.lny[l] = ny / h;
+        a.lnz[l] = nz / h;
+        a.nbx[l] = a.lnx[l] / B;
+        a.nby[l] = a.lny[l] / B;
+        a.nbz[l] = a.lnz[l] / B;
+    }
+    int rc = build_maps(&a, br, n, band, wake);
+    for (int l = 0; l < L; l++) {
+        if (rc == 0 && maps[l])
+            memcpy(maps[l], a.bmap[l], (size_t)a.nbx[l] * a.nby[l] * a.nbz[l]);
+        free(a.bmap[l]);
+    }
+    return rc;
+}
+
+/* The coupling steps alone, for pinning them on prescribed fields: the
+ * prolongation of level l's present populations (read as pre-collision
+ * state at time T) into the ghost cells of level l + 1, and the restriction
+ * of level l + 1's present populations into the band cells of level l. */
+void or_amr_prolong_only(or_amr *a, int l)
+{
+    level_transfer(a, l, a->m0[l]);
+    prolong(a, l, a->m0[l], NULL);
+}
+
+void or_amr_restrict_only(or_amr *a, int l) { restrict_band(a, l); }

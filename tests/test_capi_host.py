@@ -129,6 +129,8 @@ def test_fp32_collision_matches_oracle(lt):
     dict(L=2, B=8, box=(96, 96, 96), com=(40.0, 48.0, 48.0), band=[0, 8], wake=[0, 0]),
     dict(L=3, B=8, box=(256, 128, 128), com=(96.0, 64.0, 64.0), band=[0, 2, 0], wake=[0, 0, 0]),
     dict(L=2, B=16, box=(128, 128, 128), com=(48.0, 64.0, 64.0), band=[0, 4], wake=[0, 0]),
+    dict(L=3, B=8, box=(256, 128, 128), com=(96.0, 64.0, 64.0), band=[0, 2, 0], wake=[0, 64, 0]),
+    dict(L=3, B=8, box=(256, 128, 128), com=(96.0, 64.0, 64.0), band=[0, 2, 0], wake=[0, 48, 32]),
 ])
 def test_planned_block_maps_match_oracle(lt, case):
     """The library's host-built block grid (lbm_plan_levels, the same builder
@@ -145,6 +147,37 @@ def test_planned_block_maps_match_oracle(lt, case):
     solid = O.voxelize(b, nx, ny, nz)
     assert plan["solid_cells"] == int(solid.sum())
     assert plan["links"] == len(O.links(b, solid, nx, ny, nz)["cell"])
+
+
+# The octree workloads' own geometries: the three-level grid (order-4 seeded
+# tree, seed 3, H = 256, finest box 1024x512x512, bands 32/16 and a one-H
+# wake) and the four-level grid (order-5 tree, seed 5, H = 384, finest box
+# 2048x1024x1024, bands 48/24/12, wakes 768/384)
+OCTREES = {
+    "three_level_1024x512x512": dict(order=4, seed=3, H=256.0, com=(272.0, 245.0, 282.0), box=(1024, 512, 512),
+                                     band=[0, 32, 16], wake=[0, 256, 0]),
+    "four_level_2048x1024x1024": dict(order=5, seed=5, H=384.0, com=(544.0, 495.5, 540.5),
+                                      box=(2048, 1024, 1024), band=[0, 48, 24, 12], wake=[0, 768, 384, 0]),
+}
+
+
+@pytest.mark.parametrize("name", list(OCTREES))
+def test_planned_block_maps_with_wake_match_oracle_at_full_size(lt, name):
+    """Block maps of the wake-refined octree workloads, bit for bit against the
+    oracle's refinement rule (maps only: the oracle's dense state would not fit
+    at these sizes)."""
+    c = OCTREES[name]
+    L = len(c["band"])
+    b = O.build_tree(O.seeded3_tree_params(c["order"], c["seed"]), c["H"], list(c["com"]))
+    want = O.amr_maps(L, 16, *c["box"], b, c["band"], c["wake"])
+    nx, ny, nz = c["box"]
+    plan = lt.plan_levels(b, refine={"band": c["band"], "wake": c["wake"]}, maps=True, nx=nx, ny=ny, nz=nz,
+                          u_in=0.05, re_h=2e4, block_edge=16, levels=L)
+    for l in range(L):
+        assert np.array_equal(plan["maps"][l].astype(np.uint8), want[l]), f"level {l}"
+    # the wake refines blocks that the surface bands alone leave coarse
+    bands_only = O.amr_maps(L, 16, *c["box"], b, c["band"], [0] * L)
+    assert (want[0] == 2).sum() > (bands_only[0] == 2).sum()
 
 
 def test_plan_rejects_refinement_at_the_faces(lt):

@@ -16,6 +16,10 @@ CONFIGS = {
     "three_level_b8": dict(L=3, B=8, box=(256, 128, 128), com=(96.0, 64.0, 64.0), band=[0, 2, 0],
                            wake=[0, 0, 0]),
     "two_level_b16": dict(L=2, B=16, box=(128, 128, 128), com=(48.0, 64.0, 64.0), band=[0, 4], wake=[0, 0]),
+    # wake-box refinement on both refined levels (the octree workloads refine
+    # their wakes the same way)
+    "three_level_b8_wake": dict(L=3, B=8, box=(256, 128, 128), com=(96.0, 64.0, 64.0), band=[0, 2, 0],
+                                wake=[0, 48, 32]),
     # four levels (the smallest box whose refined blocks keep one coarse block
     # from the faces): coarse 64x32x32, finest 512x256x256
     "four_level_b8": dict(L=4, B=8, box=(512, 256, 256), com=(192.0, 128.0, 128.0), band=[0, 4, 2, 0],
@@ -50,6 +54,7 @@ def test_block_maps_match_oracle(gpu, name):
 
 
 @pytest.mark.parametrize("name,storage", [("two_level_b8", "fp32"), ("three_level_b8", "fp32"),
+                                          ("three_level_b8_wake", "fp32"), ("three_level_b8_wake", "fp16"),
                                           ("two_level_b16", "fp32"), ("four_level_b8", "fp32"),
                                           ("three_level_b8", "fp16"), ("four_level_b8", "fp16")])
 def test_coarse_steps_match_oracle(gpu, name, storage):

@@ -198,3 +198,35 @@ def test_cfg1_mirror_symmetry():
     uy = u[:, 1].reshape(nz, ny, nx)
     assert np.abs(uy + uy[:, ::-1, :]).max() < 1e-13
     assert sim.last_force[0] > 0
+
+
+def test_one_step_streams_collided_states_and_applies_the_box_faces():
+    """One step from a random state is the pull of each cell's own collision
+    (paper Sec. 2.2): f_i(x, t+1) = f*_i(x - c_i, t), periodic in y and z.  At
+    the inlet the pulled value is the equilibrium ghost f_eq(1, U); at the
+    outlet it is the zero-gradient ghost, a copy of the collided plane
+    x = nx - 1 at the ghost's (y, z) (Sec. 2.3)."""
+    nx, ny, nz, U = 7, 5, 4, 0.05
+    rng = np.random.default_rng(17)
+    sim = O.UniformSim(nx, ny, nz, 1.7, u_in=U)
+    for c in range(nx * ny * nz):
+        f = O.equilibrium(1 + 0.01 * rng.standard_normal(), [U, 0, 0] + 0.02 * rng.standard_normal(3))
+        sim.f[:, c] = f * (1 + 0.02 * rng.standard_normal(27))
+    post = np.stack([O.collide(sim.f[:, c], 1.7) for c in range(nx * ny * nz)], axis=1)
+    post = post.reshape(27, nz, ny, nx)
+    feq = O.equilibrium(1.0, [U, 0.0, 0.0])
+    sim.step(1)
+    new = sim.f.reshape(27, nz, ny, nx)
+    for i in range(27):
+        cx, cy, cz = O.CVEC[i]
+        for z in range(nz):
+            for y in range(ny):
+                for x in range(nx):
+                    sx, sy, sz = x - cx, (y - cy) % ny, (z - cz) % nz
+                    if sx < 0:
+                        want = feq[i]
+                    elif sx >= nx:
+                        want = post[i, sz, sy, nx - 1]
+                    else:
+                        want = post[i, sz, sy, sx]
+                    assert abs(new[i, z, y, x] - want) < 1e-15, (i, x, y, z)

@@ -114,7 +114,9 @@ def test_crisis_of_the_paper_trees_starts_near_3e6_and_softens_with_n():
     re = 10.0 ** np.linspace(4, 9, 201)
     slopes = []
     for n in (4, 6, 8):
-        b = O.tree_generate(O.paper_tree_params(n))
+        # the paper's n rewrites draw n generations (trunk and n - 1 child
+        # levels), the reading that reproduces Table 3
+        b = O.tree_generate(O.paper_tree_params(n - 1))
         c = A.tree_cd_est(b, re, O.tree_height(b), 1.0)
         ref = c[np.searchsorted(re, 1e5)]
         onset = re[np.argmax((re > 1e5) & (c < 0.9 * ref))]
@@ -122,3 +124,125 @@ def test_crisis_of_the_paper_trees_starts_near_3e6_and_softens_with_n():
         s = np.diff(np.log(c)) / np.diff(np.log(re))
         slopes.append(-s.min())
     assert slopes[0] > slopes[1] > slopes[2]
+
+
+def _capsule(p0, p1, d):
+    """One branch record (rows of 10) from axis ends and diameter."""
+    return [p0[0], p0[1], p0[2], p1[0], p1[1], p1[2], d, 0.0, -1.0, 0.0]
+
+
+# Pixel counting misses at most the pixels the outline crosses: |error| below
+# the perimeter times the pixel diagonal.
+H_PIX = 1.0 / 1024
+
+
+def _stadium(length, d):
+    return length * d + math.pi * d * d / 4.0, 2.0 * length + math.pi * d
+
+
+def test_projected_area_of_a_cross_flow_capsule_is_a_stadium():
+    """A capsule whose axis lies in the (y, z) plane projects along x to the 2D
+    stadium of area L D + pi D^2 / 4, at any orientation in that plane."""
+    L, D = 0.5, 0.2
+    want, per = _stadium(L, D)
+    for ang in (0.0, 30.0, 90.0, 137.0):
+        a = math.radians(ang)
+        b = np.array([_capsule([0.3, 0.0, 0.0], [0.3, L * math.cos(a), L * math.sin(a)], D)])
+        got = A.projected_area(b, H_PIX)
+        assert abs(got - want) < per * H_PIX * math.sqrt(2.0)
+        assert abs(got - want) < 2e-3 * want
+
+
+def test_projected_area_of_a_streamwise_capsule_is_a_disc():
+    """A capsule along the flow projects to the disc of its diameter; inclined
+    by alpha to the flow, its projected axis shortens to L sin(alpha)."""
+    L, D = 0.5, 0.2
+    b = np.array([_capsule([0.0, 0.0, 0.0], [L, 0.0, 0.0], D)])
+    disc = math.pi * D * D / 4.0
+    assert abs(A.projected_area(b, H_PIX) - disc) < math.pi * D * H_PIX * math.sqrt(2.0)
+    a = math.radians(40.0)
+    b = np.array([_capsule([0.0, 0.0, 0.0], [L * math.cos(a), 0.0, L * math.sin(a)], D)])
+    want, per = _stadium(L * math.sin(a), D)
+    assert abs(A.projected_area(b, H_PIX) - want) < per * H_PIX * math.sqrt(2.0)
+
+
+def test_projected_area_of_overlapping_capsules_is_their_union():
+    """Two collinear capsules that overlap cover one longer stadium; two that
+    cross at right angles through their midpoints cover both stadia less the
+    D x D square they share (their round ends lie apart)."""
+    L, D = 0.5, 0.1
+    b = np.array([_capsule([0.0, 0.0, 0.0], [0.0, L, 0.0], D), _capsule([0.0, 0.3, 0.0], [0.0, 0.3 + L, 0.0], D)])
+    want, per = _stadium(0.3 + L, D)
+    assert abs(A.projected_area(b, H_PIX) - want) < per * H_PIX * math.sqrt(2.0)
+    b = np.array([_capsule([0.0, -L / 2, 0.0], [0.0, L / 2, 0.0], D),
+                  _capsule([0.0, 0.0, -L / 2], [0.0, 0.0, L / 2], D)])
+    one, per = _stadium(L, D)
+    want = 2.0 * one - D * D
+    assert abs(A.projected_area(b, H_PIX) - want) < 2.0 * per * H_PIX * math.sqrt(2.0)
+
+
+def _probe_network(kind):
+    """Parameters whose output is known in closed form: 'const' gives y = 0.75
+    for every input; 'lre' gives y = 0.5 + x0 / 4 with x0 the first (log10 Re_D)
+    feature, which passes both ReLU layers unchanged while Re_D > 1."""
+    w = {"W1": np.zeros((64, 5)), "b1": np.zeros(64), "W2": np.zeros((64, 64)), "b2": np.zeros(64),
+         "w3": np.zeros(64), "b3": np.array([0.75])}
+    if kind == "lre":
+        w["W1"][0, 0] = 1.0
+        w["W2"][0, 0] = 1.0
+        w["w3"][0] = 0.25
+        w["b3"][0] = 0.5
+    return M.pack(w)
+
+
+def _sweep_inputs():
+    b = O.build_tree(O.seeded3_tree_params(2, 11), 1.0, [0.0, 0.0, 0.0])
+    L, D, alpha, zmid = A.branch_geometry(b)
+    fixed = np.column_stack([np.degrees(alpha), b[:, 7], zmid - b[0, 2]])
+    return np.log10(D), L * D, fixed
+
+
+def test_sweep_with_a_constant_network_is_its_value_times_the_summed_areas():
+    """Inside the training range of Re_D the estimate is sum_b y_b L_b D_b / A_x
+    (Eq. (4) with the network's coefficient): a constant y gives y sum L D / A."""
+    lgd, w, fixed = _sweep_inputs()
+    scale = (np.zeros(5), np.ones(5))
+    area = 0.37
+    re = np.array([2e3, 1e4])
+    # every branch's Re_D = Re_H D / H inside [lo, hi] at both Re_H
+    lo, hi = 10.0 ** (lgd.min() + math.log10(2e3) - 0.1), 10.0 ** (lgd.max() + 4.0 + 0.1)
+    c = M.tree_cd_sweep(_probe_network("const"), scale, (0.0, 1.0), fixed, lgd, w, re, 0.0, lo, hi, area,
+                        A.cylinder_cd)
+    assert np.allclose(c, 0.75 * w.sum() / area, rtol=1e-12)
+    # the output scale of the targets applies: y_mean + y_std * y
+    c2 = M.tree_cd_sweep(_probe_network("const"), scale, (0.1, 2.0), fixed, lgd, w, re, 0.0, lo, hi, area,
+                         A.cylinder_cd)
+    assert np.allclose(c2, (0.1 + 2.0 * 0.75) * w.sum() / area, rtol=1e-12)
+
+
+def test_sweep_outside_the_envelope_carries_the_cylinder_ratio():
+    """A branch beyond the training range is evaluated at the clamped Re_D and
+    scaled by C_d(Re_D) / C_d(Re_D,clamped): with y = 0.5 + log10(Re_D) / 4 the
+    estimate is known per branch in closed form; it is continuous across both
+    edges of the range and, far above it, follows the cylinder curve's crisis."""
+    lgd, w, fixed = _sweep_inputs()
+    scale = (np.zeros(5), np.ones(5))
+    lo, hi = 30.0, 3000.0
+    p = _probe_network("lre")
+    for inten in (0.0, 0.08):
+        re = 10.0 ** np.linspace(2.0, 8.0, 25)
+        got = M.tree_cd_sweep(p, scale, (0.0, 1.0), fixed, lgd, w, re, inten, lo, hi, 1.0, A.cylinder_cd)
+        for k, r in enumerate(re):
+            lre = math.log10(r) + lgd
+            lc = np.clip(lre, math.log10(lo), math.log10(hi))
+            ratio = A.cylinder_cd(10.0 ** lre, inten) / A.cylinder_cd(10.0 ** lc, inten)
+            # the inference form rounds the scaled features to BF16 before layer 1
+            want = np.sum((0.5 + M.bf16_round(lc) / 4.0) * ratio * w)
+            assert abs(got[k] - want) < 1e-12 * abs(want)
+        # continuity across the edges: Re_H just below and above the point where
+        # the trunk's Re_D meets each edge
+        for edge in (lo, hi):
+            r0 = edge / 10.0 ** lgd[0]
+            a, b = M.tree_cd_sweep(p, scale, (0.0, 1.0), fixed, lgd, w, [r0 * (1 - 1e-9), r0 * (1 + 1e-9)], inten,
+                                   lo, hi, 1.0, A.cylinder_cd)
+            assert abs(a - b) < 1e-6 * abs(a)
