@@ -377,7 +377,11 @@ lbm_status lbm_timing_read(lbm_grid *g, double *collide_ms, int64_t *collide_lau
  * fails; LBM_E_STATE before lbm_set_geometry.  Synchronous. */
 lbm_status lbm_autotune(lbm_grid *g, const char *cache_path);
 
-/* Checkpoint of populations, step counters and force accumulators. */
+/* Checkpoint of populations, step counters, force accumulators and the
+ * force-sample ring, taken after an even number of steps on every level
+ * (LBM_E_STATE otherwise; synchronous).  lbm_load restores it into a grid set
+ * up with the same description and geometry (LBM_E_INVALID when the file does
+ * not match): the run then continues bit for bit as if it had not stopped. */
 lbm_status lbm_save(lbm_grid *g, const char *path);
 lbm_status lbm_load(lbm_grid *g, const char *path);
 

@@ -15,7 +15,7 @@ using namespace lbm;
 
 namespace {
 
-const uint64_t MAGIC = 0x31544B43544D424CULL;  // checkpoint tag
+const uint64_t MAGIC = 0x32544B43544D424CULL;  // checkpoint tag (format 2: with the force ring)
 
 struct CkptHeader {
     uint64_t magic;
@@ -69,6 +69,12 @@ lbm_status lbm_save(lbm_grid *g, const char *path)
         ok = hipMemcpy(acc.data(), g->d_acc_branch, sizeof(double) * 3 * g->nseg, hipMemcpyDeviceToHost) == hipSuccess &&
              hipMemcpy(acc.data() + 3 * g->nseg, g->d_acc_total, sizeof(double) * 3, hipMemcpyDeviceToHost) == hipSuccess &&
              wr(f, acc.data(), sizeof(double) * acc.size());
+    // the force-sample ring, so that lbm_drag_series after a load returns the
+    // samples taken before the checkpoint
+    std::vector<double> ring(3 * (size_t)RING);
+    if (ok)
+        ok = hipMemcpy(ring.data(), g->d_ring, sizeof(double) * ring.size(), hipMemcpyDeviceToHost) == hipSuccess &&
+             wr(f, ring.data(), sizeof(double) * ring.size());
     ok = (fclose(f) == 0) && ok;
     return ok ? LBM_OK : grid_fail(g, LBM_E_DEVICE, "checkpoint write failed");
 }
@@ -103,6 +109,9 @@ lbm_status lbm_load(lbm_grid *g, const char *path)
     ok = ok && rd(f, acc.data(), sizeof(double) * acc.size()) &&
          hipMemcpy(g->d_acc_branch, acc.data(), sizeof(double) * 3 * g->nseg, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(g->d_acc_total, acc.data() + 3 * g->nseg, sizeof(double) * 3, hipMemcpyHostToDevice) == hipSuccess;
+    std::vector<double> ring(3 * (size_t)RING);
+    ok = ok && rd(f, ring.data(), sizeof(double) * ring.size()) &&
+         hipMemcpy(g->d_ring, ring.data(), sizeof(double) * ring.size(), hipMemcpyHostToDevice) == hipSuccess;
     fclose(f);
     if (!ok)
         return grid_fail(g, LBM_E_DEVICE, "checkpoint read failed");

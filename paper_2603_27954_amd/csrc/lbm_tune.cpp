@@ -91,6 +91,9 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     keep(hipMemcpyAsync(acc.data(), g->d_acc_branch, sizeof(double) * 3 * g->nseg, hipMemcpyDeviceToHost, g->stream));
     keep(hipMemcpyAsync(acc.data() + 3 * g->nseg, g->d_acc_total, sizeof(double) * 3, hipMemcpyDeviceToHost,
                         g->stream));
+    // the candidates' runs write force samples into the ring: keep its contents
+    std::vector<double> ring(3 * (size_t)RING);
+    keep(hipMemcpyAsync(ring.data(), g->d_ring, sizeof(double) * ring.size(), hipMemcpyDeviceToHost, g->stream));
     keep(hipStreamSynchronize(g->stream));
     if (ce != hipSuccess) {  // nothing has been run yet: the grid is unchanged
         free_backup();
@@ -184,6 +187,7 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     keep(hipMemcpyAsync(g->d_acc_branch, acc.data(), sizeof(double) * 3 * g->nseg, hipMemcpyHostToDevice, g->stream));
     keep(hipMemcpyAsync(g->d_acc_total, acc.data() + 3 * g->nseg, sizeof(double) * 3, hipMemcpyHostToDevice,
                         g->stream));
+    keep(hipMemcpyAsync(g->d_ring, ring.data(), sizeof(double) * ring.size(), hipMemcpyHostToDevice, g->stream));
     keep(hipStreamSynchronize(g->stream));
     free_backup();
     if (ce != hipSuccess && st == LBM_OK)
