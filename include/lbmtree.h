@@ -254,6 +254,20 @@ lbm_status lbm_mlp_set_scaling(lbm_mlp *m, const float *x_mean, const float *x_s
 /* gradient (host, 4609) and loss (host, may be NULL) of the mean-square loss
  * over n samples x (n x 5) with raw targets t (n); deterministic */
 lbm_status lbm_mlp_grad(lbm_mlp *m, const float *x, const float *t, int64_t n, float *grad, float *loss);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * gradient of lbm_mlp_grad with the same kernels, whose per-chunk partial
+ * sums live in a static device workspace of the library instead of a buffer
+ * the handle allocates.  x, t: device arrays (n x 5, n); grad (4609 floats)
+ * and loss (1 float, may be NULL): DEVICE outputs.  n <= 32768 samples, else
+ * LBM_E_INVALID.  Allocates nothing and does not synchronise: the work is
+ * enqueued on the handle's stream and the outputs are valid once that stream
+ * has reached this point.  The workspace (18.9 MB per device, resolved by
+ * lbm_mlp_create and held until the process ends) is shared by every handle on
+ * the device and keeps the last call's contents: two calls on one device that
+ * overlap in time (different streams or threads) race on it and must be
+ * ordered by the caller. */
+lbm_status lbm_mlp_grad_noalloc(lbm_mlp *m, const float *x, const float *t, int64_t n, float *grad, float *loss);
 /* one Adam step with a host gradient (4609) */
 lbm_status lbm_mlp_adam_step(lbm_mlp *m, const float *grad, float lr);
 /* epochs over n samples in shuffled mini-batches (Fisher-Yates from

@@ -113,6 +113,7 @@ def lib():
         "lbm_mlp_set_params": [_P, C.POINTER(C.c_float)],
         "lbm_mlp_set_scaling": [_P, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_float, C.c_float],
         "lbm_mlp_grad": [_P, _P, _P, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)],
+        "lbm_mlp_grad_noalloc": [_P, _P, _P, C.c_int64, _P, _P],
         "lbm_mlp_adam_step": [_P, C.POINTER(C.c_float), C.c_float],
         "lbm_mlp_train": [_P, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64,
                           C.POINTER(C.c_float)],
@@ -363,6 +364,13 @@ class Mlp:
         loss = C.c_float(0.0)
         _check(lib().lbm_mlp_grad(self.h, self._dev(x), self._dev(t), x.shape[0], _fptr(g), C.byref(loss)))
         return g, loss.value
+
+    def grad_noalloc(self, x, t, grad, loss=None):
+        """lbm_mlp_grad_noalloc: gradient (4609) and loss (1) into the device
+        tensors grad and loss, enqueued on the handle's stream (no sync)."""
+        _check(lib().lbm_mlp_grad_noalloc(self.h, self._dev(x), self._dev(t), x.shape[0], self._dev(grad),
+                                          self._dev(loss) if loss is not None else None))
+        return grad
 
     def adam_step(self, grad, lr):
         g = np.ascontiguousarray(grad, dtype=np.float32)

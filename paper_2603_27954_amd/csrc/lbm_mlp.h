@@ -30,6 +30,14 @@ hipError_t launch_mlp_grad(const MlpDev &d, const float *x, const float *t, cons
                            int count, int n_norm, hipStream_t s);
 // grad = sum of the partial sums of nchunks chunks, in chunk order
 hipError_t launch_mlp_reduce(const MlpDev &d, int nchunks, hipStream_t s);
+// Static gradient workspace for callers that cannot allocate: per device, one
+// reduced row and the partial sums of up to MLP_STATIC_CHUNKS chunks
+// (MLP_PSTRIDE floats each) in a file-scope device array.
+constexpr int MLP_STATIC_CHUNKS = 1024;  // 32768 samples
+// Resolves the array's address on the current device (once per device) and
+// returns it in *ptr; call with the device current.
+hipError_t mlp_static_scratch(int device, float **ptr);
+
 // one Adam step on grad; bc1 = 1 - beta1^t, bc2 = 1 - beta2^t; refreshes wr, w1b, w2b
 hipError_t launch_mlp_adam(const MlpDev &d, float lr, float beta1, float beta2, float eps, float bc1, float bc2,
                            hipStream_t s);

@@ -18,6 +18,7 @@
 #include "lbm_mlp.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace lbm {
 
@@ -648,6 +649,31 @@ hipError_t launch_frontal_area(const float *rec, const int64_t *tree_start, int 
         return hipSuccess;
     hipLaunchKernelGGL(k_frontal_area, dim3(n_trees), dim3(256), 0, s, rec, tree_start, h, area);
     return hipGetLastError();
+}
+
+// Gradient workspace of lbm_mlp_grad_noalloc: the reduced row, then the
+// partial sums of MLP_STATIC_CHUNKS chunks (18.9 MB per device, held until the
+// process ends).  Host code never passes the symbol itself to a kernel: the
+// address hipGetSymbolAddress returns for each device is what the kernels take.
+static __device__ __align__(256) float scratch[(size_t)(MLP_STATIC_CHUNKS + 1) * MLP_PSTRIDE];
+
+hipError_t mlp_static_scratch(int device, float **ptr)
+{
+    constexpr int MAX_DEV = 64;
+    static std::mutex mu;
+    static float *addr[MAX_DEV] = {};
+    if (device < 0 || device >= MAX_DEV)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        addr[device] = static_cast<float *>(p);
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace lbm

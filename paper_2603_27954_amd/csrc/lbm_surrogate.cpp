@@ -26,6 +26,7 @@ struct lbm_mlp {
     int32_t *idx = nullptr;   // training permutation
     int64_t idx_cap = 0;
     int64_t adam_t = 0;
+    float *scratch = nullptr;  // this device's static gradient workspace (not owned)
     std::vector<void *> allocs;
 
     ~lbm_mlp()
@@ -113,6 +114,13 @@ lbm_status lbm_mlp_create(uint64_t seed, int32_t device, void *stream, lbm_mlp *
         (st = ensure_chunks(m, 64)) != LBM_OK) {
         delete m;
         return st;
+    }
+    // the static workspace of lbm_mlp_grad_noalloc on this device, resolved
+    // here (device current) so that the entry point itself calls nothing but
+    // launches and copies
+    if (mlp_static_scratch(device, &m->scratch) != hipSuccess) {
+        delete m;
+        return mfail(LBM_E_DEVICE, "hipGetSymbolAddress of the static gradient workspace failed");
     }
     // He-uniform weights for the ReLU layers, Glorot-uniform output weights,
     // zero biases; draws from SplitMix64(seed) in parameter order
@@ -208,6 +216,30 @@ lbm_status lbm_mlp_grad(lbm_mlp *m, const float *x, const float *t, int64_t n, f
     std::memcpy(grad, g.data(), sizeof(float) * MLP_NPARAM);
     if (loss)
         *loss = g[MLP_NPARAM];
+    return LBM_OK;
+}
+
+lbm_status lbm_mlp_grad_noalloc(lbm_mlp *m, const float *x, const float *t, int64_t n, float *grad, float *loss)
+{
+    if (!m || !x || !t || !grad || n <= 0)
+        return mfail(LBM_E_INVALID, "bad arguments");
+    if (n > (int64_t)MLP_STATIC_CHUNKS * MLP_CHUNK)
+        return mfail(LBM_E_INVALID, "lbm_mlp_grad_noalloc: at most " +
+                                        std::to_string((int64_t)MLP_STATIC_CHUNKS * MLP_CHUNK) + " samples, got " +
+                                        std::to_string(n));
+    if (!m->scratch)
+        return mfail(LBM_E_STATE, "the static gradient workspace was not resolved for this device");
+    const int chunks = (int)((n + MLP_CHUNK - 1) / MLP_CHUNK);
+    // the same kernels as lbm_mlp_grad, on the static workspace: the reduced
+    // row first, the chunk partials after it
+    MlpDev d = m->d;
+    d.grad = m->scratch;
+    d.partial = m->scratch + MLP_PSTRIDE;
+    MHIP(launch_mlp_grad(d, x, t, nullptr, 0, (int)n, (int)n, m->stream));
+    MHIP(launch_mlp_reduce(d, chunks, m->stream));
+    MHIP(hipMemcpyAsync(grad, d.grad, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToDevice, m->stream));
+    if (loss)
+        MHIP(hipMemcpyAsync(loss, d.grad + MLP_NPARAM, sizeof(float), hipMemcpyDeviceToDevice, m->stream));
     return LBM_OK;
 }
 
