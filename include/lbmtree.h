@@ -58,8 +58,8 @@ typedef enum {
 /* flags of lbm_grid_desc.flags */
 #define LBM_F_NO_GALILEAN 1u /* drop the Galilean-correction terms of the second-order relaxation */
 #define LBM_F_GRAPH 2u       /* replay each coarse step from a captured HIP graph */
-#define LBM_F_PERSISTENT 4u  /* run each coarse step as one persistent launch; currently disabled:
-                                lbm_create_grid rejects it with LBM_E_INVALID */
+#define LBM_F_PERSISTENT 4u  /* run each coarse step as one persistent launch over its phase list;
+                                currently disabled: lbm_create_grid rejects it with LBM_E_INVALID */
 #define LBM_F_AUTOTUNE 8u    /* time the tile candidates at set_geometry and keep the fastest */
 
 /* One cylinder of the tree (Sec. 2.1: the tree is an assembly of cylinders).
@@ -146,6 +146,8 @@ typedef struct {
     int32_t persist_graph;    /* 1: the persistent launch replays from a captured graph */
     int64_t collided_cells[4];/* cells collided per level sub-step (leaf + band + ghost, solid excluded) */
     int32_t xcd_group;        /* consecutive collide tiles per XCD run (1 = plain dispatch order) */
+    int32_t wall_clock_khz;   /* the device's constant real-time clock (hipDeviceAttributeWallClockRate) */
+    uint64_t persist_wait_ticks; /* time limit of one wait of the persistent launch, in ticks of that clock */
 } lbm_info;
 
 /* ---- lifecycle ------------------------------------------------------------ */
@@ -406,6 +408,55 @@ lbm_status lbm_load(lbm_grid *g, const char *path);
 lbm_status lbm_geometry_build(const lbm_branch *b, int32_t n_b, int32_t nx, int32_t ny, int32_t nz,
                               uint8_t *solid, int64_t cap, int64_t *cell, int8_t *dir, double *q,
                               int32_t *branch, int64_t *n_links, double *area_x);
+
+/* ---- persistent coarse step: phase lists and the protocol model ------------
+ * The persistent form (LBM_F_PERSISTENT) runs one coarse step as one launch
+ * over a recorded list of phases (collide of one level sub-step, bounce-back,
+ * force sums, coarse/fine transfer, in the order of the coarse-first
+ * recursion of Sec. 2.2).  Work-groups claim chunks of a phase's items from a
+ * counter, count each finished chunk, and start a phase once the previous
+ * phase is complete; the last work-group to leave clears the counters. */
+typedef struct {
+    int32_t kind;   /* 0 collide, 1 bounce-back links, 2 link-piece sums, 3 branch totals,
+                       4 transfer records at T+1, 5 prolongation, 6 restriction */
+    int32_t step;   /* coarse step of the recording (0-based) */
+    int32_t items;  /* work items (one work-group each) */
+    int32_t chunk;  /* items per claim for the given work-group count */
+    int32_t chunks; /* claims of the phase */
+} lbm_phase_info;
+
+/* Host only: the phase lists of coarse_steps consecutive coarse steps of the
+ * grid d would run in the persistent form (planned as lbm_set_geometry plans
+ * it, without a device), chunked for a launch of `groups` work-groups.  Up to
+ * cap entries go to out; *n receives the full count.  Errors as
+ * lbm_plan_levels; turbulent inflow is not available in this form
+ * (LBM_E_INVALID). */
+lbm_status lbm_plan_phases(const lbm_grid_desc *d, const lbm_branch *b, int32_t n_b, const lbm_refine_desc *refine,
+                           int32_t groups, int32_t coarse_steps, lbm_phase_info *out, int32_t cap, int32_t *n);
+
+typedef struct {
+    int64_t chunks_run;        /* chunk executions */
+    int64_t chunks_missed;     /* chunks never run */
+    int64_t chunks_repeated;   /* chunks run more than once */
+    int64_t order_violations;  /* chunks started before the previous phase was complete */
+    int64_t waits_given_up;    /* waits that gave up (abort flag or time limit) */
+    int32_t abandoned;         /* the abort flag is set at the end */
+    int32_t counters_zero;     /* every counter is zero at the end */
+    double seconds;            /* wall time of the launch */
+} lbm_persist_model_result;
+
+/* Host only: one launch of the persistent kernel's work-distribution protocol
+ * (the same code the kernel runs), with `groups` work-groups run by `threads`
+ * host threads (each work-group to its end before a thread takes the next:
+ * groups > threads models a launch larger than the device holds at once).
+ * chunks: n_phases claim counts (lbm_phase_info.chunks).  ctr (2 n_phases + 1
+ * words) and *abort_flag are the launch's counters and flag, read at the start
+ * (zero for a clean launch) and written back at the end.  A wait gives up
+ * after wait_s seconds.  stuck_phase >= 0 makes every chunk of that phase take
+ * 3 wait_s (a hung work item); -1 for none. */
+lbm_status lbm_persist_model(const int32_t *chunks, int32_t n_phases, int32_t groups, int32_t threads,
+                             uint32_t *ctr, uint32_t *abort_flag, double wait_s, int32_t stuck_phase,
+                             lbm_persist_model_result *out);
 
 /* ---- host probe (tests) ------------------------------------------------------ */
 

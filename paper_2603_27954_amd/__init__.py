@@ -62,6 +62,17 @@ class Plan(C.Structure):
                 ("pop_bytes", C.c_int64)]
 
 
+class PhaseInfo(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("step", C.c_int32), ("items", C.c_int32), ("chunk", C.c_int32),
+                ("chunks", C.c_int32)]
+
+
+class PersistModelResult(C.Structure):
+    _fields_ = [("chunks_run", C.c_int64), ("chunks_missed", C.c_int64), ("chunks_repeated", C.c_int64),
+                ("order_violations", C.c_int64), ("waits_given_up", C.c_int64), ("abandoned", C.c_int32),
+                ("counters_zero", C.c_int32), ("seconds", C.c_double)]
+
+
 class DragResult(C.Structure):
     _fields_ = [("force", C.c_double * 3), ("cd", C.c_double), ("area_x", C.c_double),
                 ("height", C.c_double), ("mass", C.c_double), ("samples", C.c_int64), ("step", C.c_int64)]
@@ -75,7 +86,7 @@ class Info(C.Structure):
                 ("nu_finest", C.c_double), ("device_bytes", C.c_size_t), ("tile_cells", C.c_int32),
                 ("threads", C.c_int32), ("occ_even", C.c_int32), ("occ_odd", C.c_int32),
                 ("persist_wgs", C.c_int32), ("persist_graph", C.c_int32), ("collided_cells", C.c_int64 * 4),
-                ("xcd_group", C.c_int32)]
+                ("xcd_group", C.c_int32), ("wall_clock_khz", C.c_int32), ("persist_wait_ticks", C.c_uint64)]
 
 
 _lib = None
@@ -127,6 +138,10 @@ def lib():
         "lbm_plan_levels": [C.POINTER(GridDesc), C.POINTER(Branch), C.c_int32, C.POINTER(RefineDesc),
                             C.POINTER(Plan), C.POINTER(C.POINTER(C.c_int8))],
         "lbm_mass": [_P, _dp],
+        "lbm_plan_phases": [C.POINTER(GridDesc), C.POINTER(Branch), C.c_int32, C.POINTER(RefineDesc), C.c_int32,
+                            C.c_int32, C.POINTER(PhaseInfo), C.c_int32, C.POINTER(C.c_int32)],
+        "lbm_persist_model": [C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_uint32),
+                              C.POINTER(C.c_uint32), C.c_double, C.c_int32, C.POINTER(PersistModelResult)],
         "lbm_autotune": [_P, C.c_char_p],
         "lbm_save": [_P, C.c_char_p],
         "lbm_load": [_P, C.c_char_p],
@@ -446,6 +461,41 @@ def plan_levels(branches, refine=None, maps=False, **desc):
     return res
 
 
+def plan_phases(branches, groups, coarse_steps=1, refine=None, **desc):
+    """Host-only phase lists of the persistent coarse step (lbm_plan_phases):
+    list of dicts kind, step, items, chunk, chunks."""
+    if isinstance(branches, np.ndarray):
+        branches = branches_from_numpy(branches)
+    d = _make_desc(**desc)
+    r = _refine_desc(refine)
+    n = C.c_int32(0)
+    _check(lib().lbm_plan_phases(C.byref(d), branches, len(branches), C.byref(r) if r else None, groups,
+                                 coarse_steps, None, 0, C.byref(n)))
+    out = (PhaseInfo * max(n.value, 1))()
+    _check(lib().lbm_plan_phases(C.byref(d), branches, len(branches), C.byref(r) if r else None, groups,
+                                 coarse_steps, out, n.value, C.byref(n)))
+    return [{"kind": p.kind, "step": p.step, "items": p.items, "chunk": p.chunk, "chunks": p.chunks}
+            for p in out[:n.value]]
+
+
+def persist_model(chunks, groups, threads, ctr=None, abort=0, wait_s=0.5, stuck_phase=-1):
+    """One launch of the persistent protocol on host threads
+    (lbm_persist_model).  ctr: the 2n + 1 counters at the start (None: zero),
+    updated in place when given as a uint32 array.  Returns (result dict,
+    counters, abort flag)."""
+    ch = np.ascontiguousarray(chunks, dtype=np.int32)
+    n = len(ch)
+    c = np.zeros(2 * n + 1, np.uint32) if ctr is None else ctr
+    assert c.dtype == np.uint32 and c.flags["C_CONTIGUOUS"] and len(c) == 2 * n + 1
+    ab = C.c_uint32(abort)
+    r = PersistModelResult()
+    _check(lib().lbm_persist_model(ch.ctypes.data_as(C.POINTER(C.c_int32)), n, groups, threads,
+                                   c.ctypes.data_as(C.POINTER(C.c_uint32)), C.byref(ab), float(wait_s),
+                                   stuck_phase, C.byref(r)))
+    res = {k: getattr(r, k) for k, _ in PersistModelResult._fields_}
+    return res, c, ab.value
+
+
 class Grid:
     """Owns one lbm_grid handle."""
 
@@ -513,7 +563,8 @@ class Grid:
                 "nu_finest": i.nu_finest, "device_bytes": i.device_bytes, "tile_cells": i.tile_cells,
                 "threads": i.threads, "occ_even": i.occ_even, "occ_odd": i.occ_odd,
                 "persist_wgs": i.persist_wgs, "persist_graph": i.persist_graph,
-                "collided_cells": list(i.collided_cells), "xcd_group": i.xcd_group}
+                "collided_cells": list(i.collided_cells), "xcd_group": i.xcd_group,
+                "wall_clock_khz": i.wall_clock_khz, "persist_wait_ticks": i.persist_wait_ticks}
 
     def get_populations(self, level=0):
         nx, ny, nz = self.level_shape(level)

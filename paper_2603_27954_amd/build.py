@@ -8,7 +8,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmtree.so")
 SOURCES = ["lbm_kernels.hip", "lbm_amr_kernels.hip", "lbm_persist.hip", "lbm_runtime.cpp", "lbm_levels.cpp",
            "lbm_geometry.cpp", "lbm_extra.cpp", "lbm_tune.cpp", "lbm_inflow.cpp", "lbm_inflow.hip",
-           "lbm_mlp.hip", "lbm_surrogate.cpp"]
+           "lbm_mlp.hip", "lbm_surrogate.cpp", "lbm_persist_model.cpp"]
 ARCH = "gfx950"
 
 

@@ -78,6 +78,8 @@ struct lbm_grid {
     unsigned *d_abort = nullptr;   // set by a persistent launch whose bounded wait expired
     int persist_grid = 0;       // work-groups of the persistent launch (0 = all resident)
     int persist_max = 0, cus = 0;
+    unsigned long long persist_wait_ticks = 0;  // time limit of one wait in the persistent launch
+    int wall_khz = 0;                           // the device's constant real-time clock
     bool persist_failed = false;   // a wait expired: the state is undefined
     // per-kernel timing (event pairs, kind 0 collide, 1 links)
     bool timing = false;

@@ -23,6 +23,9 @@ constexpr int MOM_REC = 12;
 constexpr int RESTRICT_CELLS = 256;
 // links per piece of the force reduction (one work-group each)
 constexpr int LINK_PIECE = 8192;
+// seconds after which one wait of the persistent launch gives up (a phase of
+// the largest grids takes milliseconds)
+constexpr double PERSIST_WAIT_S = 1.0;
 
 // Arguments of the collide-and-stream kernel of one level.
 constexpr int DENSE_TILE = 256;  // cells per work item of a dense level
@@ -112,10 +115,11 @@ struct Phase {
 
 // launcher of the persistent coarse step (lbm_persist.hip).  ctr: 2 n_phases
 // + 1 counters, zero before the first launch (each launch leaves them zero);
-// abort_flag: set by the launch when a bounded wait expired.  Any grid size
-// is correct; persistent_max_grid gives the number of resident work-groups.
+// abort_flag: set by the launch when a wait gave up after wait_ticks of the
+// device's constant real-time counter.  Any grid size is correct;
+// persistent_max_grid gives the number of resident work-groups.
 hipError_t launch_persistent(int B, int storage, const Phase *phases, int n_phases, unsigned *ctr,
-                             unsigned *abort_flag, int grid, hipStream_t s);
+                             unsigned *abort_flag, unsigned long long wait_ticks, int grid, hipStream_t s);
 hipError_t persistent_max_grid(int B, int storage, int device, int *grid, int *cus);
 
 struct DevLevel {

@@ -2,58 +2,31 @@
 // sums and coarse/fine transfer) as a single persistent launch.
 //
 // The host records the step as a list of phases (see Phase).  The work-groups
-// walk the list together.  In each phase they claim chunks of the phase's work
-// items from an atomic counter and count each finished chunk.  Before a phase
-// starts, a work-group waits until every chunk of the previous phase is
-// counted, because the next phase reads what that one wrote.  The bodies are
-// the ones the per-phase kernels run.
+// walk the list with the claim / count / leave protocol of persist_walk
+// (lbm_persist_protocol.h): chunks of a phase's items are claimed from an
+// atomic counter, each finished chunk is counted, and a phase starts once the
+// previous phase's chunks are all counted.  The bodies are the ones the
+// per-phase kernels run.
 //
-// Deadlock freedom does not rest on all work-groups being resident.  A
-// work-group only ever waits for chunks that running work-groups have already
-// claimed, and a claimed chunk completes without waiting on anything.  A
-// work-group that starts late finds the work done and leaves.  Each wave
-// drains its own stores to the L2, then one agent-scope release writes the
-// per-XCD L2 back before the work-group counts the chunk.  The waiter
-// acquires once (which invalidates stale lines) before reading.  Every wait is still bounded: a
-// wait past the bound raises the abort flag, every work-group then leaves the
-// launch, and the host reports the failure.  The last work-group to leave
-// resets the counters for the next launch.
+// Memory ordering across the XCDs (each has its own L2): a work-group drains
+// its stores, then one agent-scope release writes its L2 back before the chunk
+// is counted.  A waiting work-group polls the count with relaxed agent-scope
+// loads and acquires once after the wait: an acquire per poll would invalidate
+// the XCD's whole L2 on every iteration of every waiting work-group and starve
+// the work-groups still computing.
+//
+// Every wait is bounded in time, not in polls: thread 0 reads the constant
+// real-time counter and gives up once wait_ticks have passed, raising the
+// abort flag.  A raised flag ends every later wait at its first poll, so the
+// launch is abandoned: each work-group leaves at its next phase boundary and
+// the host reports the failure.  Each wait therefore ends within wait_ticks of
+// the counter's clock plus one poll, whatever a poll costs.
 #include "lbm_bodies.h"
+#include "lbm_persist_protocol.h"
 
 namespace lbm {
 
 namespace {
-
-constexpr unsigned SPIN_LIMIT = 1u << 22;
-
-// waits until *done reaches need (thread 0 spins, the work-group follows);
-// returns false when the launch is being abandoned.  The spin polls with
-// relaxed device-scope loads, which bypass the stale caches without
-// invalidating them: an acquire per poll would invalidate the whole XCD L2 on
-// every iteration of every waiting work-group and starve the ones still
-// working.  One acquire fence follows the wait.
-__device__ __forceinline__ bool wait_done(unsigned *done, unsigned need, unsigned *abort_flag, int *ok_sh)
-{
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        unsigned spins = 0;
-        while (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-                ++spins > SPIN_LIMIT) {
-                __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(8);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        *ok_sh = ok;
-    }
-    __syncthreads();
-    const bool ok = *ok_sh != 0;
-    __syncthreads();
-    return ok;
-}
 
 template <int B, typename S>
 __device__ __forceinline__ void run_item(const Phase &p, int it, int *nb, double *sh, float (*rrec)[RESTRICT_CELLS])
@@ -115,59 +88,124 @@ __device__ __forceinline__ void run_item(const Phase &p, int it, int *nb, double
     }
 }
 
+// Device side of the protocol for one work-group: thread 0 talks to the
+// counters and word_sh hands its results to the whole work-group.
+template <int B, typename S>
+struct DevOps {
+    const Phase *__restrict__ phases;
+    unsigned *abort_flag;
+    unsigned long long wait_ticks;
+    int *nb;
+    double *sh;
+    float (*rrec)[RESTRICT_CELLS];
+    unsigned *word_sh;
+
+    __device__ int chunks(int p) const { return phases[p].chunks; }
+    __device__ unsigned groups() const { return gridDim.x; }
+
+    __device__ unsigned broadcast(unsigned v)
+    {
+        if (threadIdx.x == 0)
+            *word_sh = v;
+        __syncthreads();
+        const unsigned r = *word_sh;
+        __syncthreads();
+        return r;
+    }
+
+    __device__ bool wait(unsigned *done, unsigned need)
+    {
+        unsigned ok = 1u;
+        if (threadIdx.x == 0) {
+            const unsigned long long t0 = (unsigned long long)wall_clock64();
+            for (;;) {
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                    ok = 0u;
+                    break;
+                }
+                if (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need)
+                    break;
+                if ((unsigned long long)wall_clock64() - t0 > wait_ticks) {
+                    __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0u;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        return broadcast(ok) != 0u;
+    }
+
+    __device__ unsigned claim(unsigned *claimed)
+    {
+        unsigned c = 0u;
+        if (threadIdx.x == 0)
+            c = __hip_atomic_fetch_add(claimed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return broadcast(c);
+    }
+
+    __device__ void run(int p, int c)
+    {
+        const Phase &ph = phases[p];
+        const int i0 = c * ph.chunk, i1 = min(i0 + ph.chunk, ph.items);
+        for (int it = i0; it < i1; ++it)
+            run_item<B, S>(ph, it, nb, sh, rrec);
+    }
+
+    __device__ void complete(unsigned *done)
+    {
+        // every wave's stores reach the L2, then one agent-scope release
+        // writes the L2 back before the chunk is counted
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+
+    __device__ unsigned leave(unsigned *left)
+    {
+        __syncthreads();
+        unsigned v = 0u;
+        if (threadIdx.x == 0)
+            v = __hip_atomic_fetch_add(left, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        return broadcast(v);
+    }
+
+    __device__ void reset(unsigned *ctr, int n)
+    {
+        if (threadIdx.x == 0) {
+            for (int i = 0; i < n; ++i)
+                __hip_atomic_store(&ctr[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        }
+    }
+};
+
 // The phase list is read-only for the whole launch; __restrict__ lets the
 // compiler keep its (uniform) fields in scalar registers.  ctr holds, per
 // phase, the claimed and the finished chunk counts, then the count of
 // work-groups that left.
 template <int B, typename S>
 __global__ void __launch_bounds__(256) k_persist(const Phase *__restrict__ phases, int n_phases, unsigned *ctr,
-                                                 unsigned *abort_flag)
+                                                 unsigned *abort_flag, unsigned long long wait_ticks)
 {
     __shared__ int nb[27];
     __shared__ double sh[12];
     __shared__ float rrec[11][RESTRICT_CELLS];
-    __shared__ int claim_sh, ok_sh;
-    unsigned *claimed = ctr, *done = ctr + n_phases, *left = ctr + 2 * n_phases;
-    for (int ph = 0; ph < n_phases; ++ph) {
-        const Phase &p = phases[ph];
-        if (ph > 0 && !wait_done(&done[ph - 1], (unsigned)phases[ph - 1].chunks, abort_flag, &ok_sh))
-            break;
-        for (;;) {
-            if (threadIdx.x == 0)
-                claim_sh = (int)__hip_atomic_fetch_add(&claimed[ph], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __syncthreads();
-            const int c = claim_sh;
-            __syncthreads();
-            if (c >= p.chunks)
-                break;
-            const int i0 = c * p.chunk, i1 = min(i0 + p.chunk, p.items);
-            for (int it = i0; it < i1; ++it)
-                run_item<B, S>(p, it, nb, sh, rrec);
-            // every wave's stores reach the L2, then one agent-scope release
-            // writes the L2 back before the chunk is counted
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __hip_atomic_fetch_add(&done[ph], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned out = __hip_atomic_fetch_add(left, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (out == gridDim.x - 1u) {
-            for (int i = 0; i < 2 * n_phases + 1; ++i)
-                __hip_atomic_store(&ctr[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        }
-    }
+    __shared__ unsigned word_sh;
+    DevOps<B, S> o{phases, abort_flag, wait_ticks, nb, sh, rrec, &word_sh};
+    persist_walk(o, n_phases, ctr);
 }
 
 template <int B, typename S>
-hipError_t launch_t(const Phase *phases, int n_phases, unsigned *ctr, unsigned *abort_flag, int grid, hipStream_t s)
+hipError_t launch_t(const Phase *phases, int n_phases, unsigned *ctr, unsigned *abort_flag,
+                    unsigned long long wait_ticks, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_persist<B, S>), dim3(grid), dim3(256), 0, s, phases, n_phases, ctr, abort_flag);
+    hipLaunchKernelGGL((k_persist<B, S>), dim3(grid), dim3(256), 0, s, phases, n_phases, ctr, abort_flag,
+                       wait_ticks);
     return hipGetLastError();
 }
 
@@ -180,18 +218,19 @@ hipError_t max_grid_t(int *per_cu)
 }  // namespace
 
 hipError_t launch_persistent(int B, int storage, const Phase *phases, int n_phases, unsigned *ctr,
-                             unsigned *abort_flag, int grid, hipStream_t s)
+                             unsigned *abort_flag, unsigned long long wait_ticks, int grid, hipStream_t s)
 {
     if (n_phases == 0)
         return hipSuccess;
+    const unsigned long long w = wait_ticks;
     if (B == 16) {
-        if (storage == 0) return launch_t<16, float>(phases, n_phases, ctr, abort_flag, grid, s);
-        if (storage == 1) return launch_t<16, __half>(phases, n_phases, ctr, abort_flag, grid, s);
-        return launch_t<16, __hip_bfloat16>(phases, n_phases, ctr, abort_flag, grid, s);
+        if (storage == 0) return launch_t<16, float>(phases, n_phases, ctr, abort_flag, w, grid, s);
+        if (storage == 1) return launch_t<16, __half>(phases, n_phases, ctr, abort_flag, w, grid, s);
+        return launch_t<16, __hip_bfloat16>(phases, n_phases, ctr, abort_flag, w, grid, s);
     }
-    if (storage == 0) return launch_t<8, float>(phases, n_phases, ctr, abort_flag, grid, s);
-    if (storage == 1) return launch_t<8, __half>(phases, n_phases, ctr, abort_flag, grid, s);
-    return launch_t<8, __hip_bfloat16>(phases, n_phases, ctr, abort_flag, grid, s);
+    if (storage == 0) return launch_t<8, float>(phases, n_phases, ctr, abort_flag, w, grid, s);
+    if (storage == 1) return launch_t<8, __half>(phases, n_phases, ctr, abort_flag, w, grid, s);
+    return launch_t<8, __hip_bfloat16>(phases, n_phases, ctr, abort_flag, w, grid, s);
 }
 
 hipError_t persistent_max_grid(int B, int storage, int device, int *grid, int *cus)

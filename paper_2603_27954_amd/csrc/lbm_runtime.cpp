@@ -20,6 +20,7 @@
 #include "lbm_levels.h"
 #include "lbm_grid.h"
 #include "lbm_inflow.h"
+#include "lbm_persist_protocol.h"
 
 using namespace lbm;
 
@@ -503,8 +504,8 @@ static lbm_status persistent_step(lbm_grid *g)
         if (sg.exec)
             HIPX(g, hipGraphLaunch(sg.exec, g->stream));
         else
-            HIPX(g, launch_persistent(g->B, g->d.storage, sg.d_phases, sg.n_phases, sg.d_ctr, g->d_abort, grid,
-                                      g->stream));
+            HIPX(g, launch_persistent(g->B, g->d.storage, sg.d_phases, sg.n_phases, sg.d_ctr, g->d_abort,
+                                      g->persist_wait_ticks, grid, g->stream));
         apply_deltas(g, sg);
         return LBM_OK;
     }
@@ -531,10 +532,8 @@ static lbm_status persistent_step(lbm_grid *g)
         restore();
         return st;
     }
-    // about two claims per work-group in large phases, one item per claim in
-    // small ones
     for (Phase &p : ph) {
-        p.chunk = std::max(1, p.items / (2 * grid));
+        p.chunk = persist_chunk(p.items, grid);
         p.chunks = (p.items + p.chunk - 1) / p.chunk;
     }
     sg.n_phases = (int)ph.size();
@@ -562,7 +561,7 @@ static lbm_status persistent_step(lbm_grid *g)
         bool ok = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             const hipError_t el = launch_persistent(g->B, g->d.storage, sg.d_phases, sg.n_phases, sg.d_ctr,
-                                                    g->d_abort, grid, g->stream);
+                                                    g->d_abort, g->persist_wait_ticks, grid, g->stream);
             const hipError_t ee = hipStreamEndCapture(g->stream, &graph);
             ok = el == hipSuccess && ee == hipSuccess && graph &&
                  hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0) == hipSuccess;
@@ -585,7 +584,7 @@ static lbm_status persistent_step(lbm_grid *g)
     g->graphs.push_back(sg);
     const hipError_t el = sg.exec ? hipGraphLaunch(sg.exec, g->stream)
                                   : launch_persistent(g->B, g->d.storage, sg.d_phases, sg.n_phases, sg.d_ctr,
-                                                      g->d_abort, grid, g->stream);
+                                                      g->d_abort, g->persist_wait_ticks, grid, g->stream);
     if (el != hipSuccess) {
         restore();
         return fail(g, LBM_E_DEVICE, std::string("persistent launch: ") + hipGetErrorString(el));
@@ -679,8 +678,8 @@ static lbm_status check_desc(const lbm_grid_desc *d, std::string *msg)
     if (d->drag_every < 0)
         return (*msg = "drag_every must be >= 1", LBM_E_INVALID);
     if (d->flags & LBM_F_PERSISTENT)
-        return (*msg = "LBM_F_PERSISTENT is disabled: the persistent coarse-step launch has not passed its GPU "
-                       "tests; use LBM_F_GRAPH",
+        return (*msg = "LBM_F_PERSISTENT is disabled: the persistent coarse-step launch did not finish on the GPU "
+                       "(its waits are bounded, so a cause outside them is still open); use LBM_F_GRAPH",
                 LBM_E_INVALID);
     if (d->turb_intensity < 0.0 || d->turb_intensity > 0.5)
         return (*msg = "turb_intensity must be in [0, 0.5]", LBM_E_INVALID);
@@ -994,6 +993,16 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
             g->persist_max = 0;
             g->cus = 0;
         }
+        // one wait of the persistent launch gives up after PERSIST_WAIT_S
+        // seconds of the device's constant real-time clock (kHz)
+        int wall_khz = 0;
+        if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, g->d.device) != hipSuccess ||
+            wall_khz <= 0) {
+            (void)hipGetLastError();
+            g->persist_max = 0;  // no time bound, no persistent launch
+        }
+        g->persist_wait_ticks = (unsigned long long)(PERSIST_WAIT_S * 1000.0 * wall_khz);
+        g->wall_khz = wall_khz;
     }
     HIPX(g, hipStreamSynchronize(g->stream));
     g->state = 1;
@@ -1162,6 +1171,8 @@ lbm_status lbm_get_info(const lbm_grid *g, lbm_info *out)
     out->occ_odd = g->occ_odd;
     out->persist_wgs = persist_grid_size(g);
     out->xcd_group = g->xcd_group;
+    out->wall_clock_khz = g->wall_khz;
+    out->persist_wait_ticks = g->persist_wait_ticks;
     bool pg = false;
     for (const lbm_grid::StepGraph &sg : g->graphs)
         pg = pg || (sg.d_phases && sg.exec);
@@ -1453,6 +1464,73 @@ lbm_status lbm_plan_levels(const lbm_grid_desc *d, const lbm_branch *b, int32_t 
         if (maps && maps[l])
             std::memcpy(maps[l], v.h_map.data(), v.h_map.size());
     }
+    return LBM_OK;
+}
+
+lbm_status lbm_plan_phases(const lbm_grid_desc *d, const lbm_branch *b, int32_t n_b, const lbm_refine_desc *refine,
+                           int32_t groups, int32_t coarse_steps, lbm_phase_info *out, int32_t cap, int32_t *n)
+{
+    if (!d || !n || groups <= 0 || coarse_steps <= 0 || (!out && cap > 0))
+        return fail(nullptr, LBM_E_INVALID, "bad arguments");
+    std::string msg;
+    lbm_grid_desc dd = *d;
+    dd.flags &= ~LBM_F_PERSISTENT;
+    if (check_desc(&dd, &msg) != LBM_OK || check_branches(dd, b, n_b, &msg) != LBM_OK)
+        return fail(nullptr, LBM_E_INVALID, msg);
+    if (dd.levels > 1 && !refine)
+        return fail(nullptr, LBM_E_INVALID, "refinement bands required when levels > 1");
+    if (dd.turb_intensity > 0.0)
+        return fail(nullptr, LBM_E_INVALID, "turbulent inflow is not available in the persistent form");
+    // the host state lbm_create_grid and lbm_set_geometry build, without
+    // device memory: the recorded phases carry null device pointers
+    lbm_grid g;
+    g.d = dd;
+    if (g.d.drag_every == 0)
+        g.d.drag_every = 1;
+    g.B = dd.block_edge;
+    g.L = dd.levels;
+    g.tile = g.B * g.B;
+    g.branches.assign(b, b + n_b);
+    g.H = tree_height(b, n_b);
+    g.nu_f = dd.nu > 0.0 ? dd.nu : dd.u_in * g.H / dd.re_h;
+    voxelize(b, n_b, dd.nx, dd.ny, dd.nz, g.solid);
+    build_links(b, n_b, dd.nx, dd.ny, dd.nz, g.solid, g.links);
+    lbm_status st = build_levels(dd, g.B, g.L, b, n_b, refine, g.solid, g.lv, g.amr, &msg);
+    if (st != LBM_OK)
+        return fail(nullptr, st, msg);
+    for (int l = 0; l < g.L; ++l) {
+        nu_to_level_omega(g.nu_f, g.L, l, &g.lv[l].om1);
+        g.lv[l].n_work = (int)g.lv[l].h_work.size();
+        g.lv[l].n_leaf = (int)g.lv[l].h_leaf.size();
+    }
+    g.n_links = (int)g.links.size();
+    g.nseg = n_b + 1;
+    std::vector<int> per_seg(g.nseg, 0);
+    for (const HostLink &Lk : g.links)
+        per_seg[Lk.branch < 0 ? n_b : Lk.branch]++;
+    g.npieces = 0;
+    for (int c : per_seg)
+        g.npieces += (c + LINK_PIECE - 1) / LINK_PIECE;
+    std::vector<Phase> ph;
+    std::vector<int> step_of;
+    g.rec = &ph;
+    for (int s2 = 0; s2 < coarse_steps; ++s2) {
+        if ((st = coarse_step(&g)) != LBM_OK) {
+            g.rec = nullptr;
+            return st;
+        }
+        step_of.resize(ph.size(), s2);
+    }
+    g.rec = nullptr;
+    for (size_t i = 0; i < ph.size() && (int32_t)i < cap; ++i) {
+        const Phase &p = ph[i];
+        out[i].kind = p.kind;
+        out[i].step = step_of[i];
+        out[i].items = p.items;
+        out[i].chunk = persist_chunk(p.items, groups);
+        out[i].chunks = (p.items + out[i].chunk - 1) / out[i].chunk;
+    }
+    *n = (int32_t)ph.size();
     return LBM_OK;
 }
 

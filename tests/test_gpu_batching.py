@@ -41,7 +41,9 @@ def _flags(gpu, mode):
 
 
 PERSISTENT_OFF = ("the persistent coarse-step launch is disabled in the library (lbm_create_grid rejects "
-                  "LBM_F_PERSISTENT): its first GPU runs exceeded their time limit; see the design notes")
+                  "LBM_F_PERSISTENT): its first launch on the uniform grid did not finish on the GPU, also with "
+                  "time-bounded waits; its work-distribution protocol passes on host threads "
+                  "(test_persist_protocol.py); see the design notes")
 
 
 @pytest.mark.parametrize("case", list(CASES))
@@ -70,4 +72,5 @@ def test_batched_step_is_bitwise_eager(gpu, mode, case, drag_every, storage):
     assert np.array_equal(se, sg)
     assert de["step"] == dg["step"] == 7
     info = gg.info()
-    print(f"  persistent work-groups {info['persist_wgs']}, persistent graph {info['persist_graph']}", flush=True)
+    print(f"  persistent work-groups {info['persist_wgs']}, persistent graph {info['persist_graph']}, "
+          f"wall clock {info['wall_clock_khz']} kHz, wait limit {info['persist_wait_ticks']} ticks", flush=True)
