@@ -135,9 +135,10 @@ def amr_leg(lt, torch, steps, warmup):
     res = {}
     # both modes use the tiles tuned once
     cache = TUNE_CACHE or os.path.join(tempfile.mkdtemp(), "tune.txt")
-    for mode, flags in (("eager", 0), ("graph", lt.LBM_F_GRAPH)):
+    for mode, flags, storage in (("eager", 0, "fp32"), ("graph", lt.LBM_F_GRAPH, "fp32"),
+                                 ("graph_fp16", lt.LBM_F_GRAPH, "fp16")):
         g = lt.Grid(AMR["nx"], AMR["ny"], AMR["nz"], u_in=U_IN, re_h=AMR["re_h"], block_edge=16, levels=3,
-                    storage="fp32", drag_every=1, flags=flags, stream=stream.cuda_stream)
+                    storage=storage, drag_every=1, flags=flags, stream=stream.cuda_stream)
         t0 = time.time()
         g.set_geometry(arr, refine={"band": AMR["band"], "wake": AMR["wake"]})
         setup = time.time() - t0
@@ -156,8 +157,9 @@ def amr_leg(lt, torch, steps, warmup):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         d = g.drag()
+        bpc = 216.0 if storage == "fp32" else 108.0
         r = {"mlups": upd * steps / (ms * 1e-3) / 1e6, "ms_per_coarse_step": ms / steps,
-             "step_hbm_frac": 216.0 * work * steps / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), "cd": d["cd"]}
+             "step_hbm_frac": bpc * work * steps / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), "cd": d["cd"]}
         if mode == "eager":
             g.timing(True)
             g.step(steps)
@@ -175,7 +177,134 @@ def amr_leg(lt, torch, steps, warmup):
                            "effective_finest_cells": AMR["nx"] * AMR["ny"] * AMR["nz"]}
         res[mode] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
         g.close()
+    res["fp16_vs_fp32_mlups"] = round(res["graph_fp16"]["mlups"] / res["graph"]["mlups"], 3)
     return res
+
+
+# Four-level workload: 16^3-cell blocks, finest box 2048 x 1024 x 1024,
+# coarse level 256 x 128 x 128; order-5 seeded three-child tree (seed 5, 364
+# branches) with H = 384 finest cells; finest blocks within 12 finest cells of
+# a branch surface, the next levels within 24 / 48 cells and wake boxes of 2H
+# and 1H on levels 1 and 2; Re_H = 1.2e5; FP16 deviation storage; turbulent
+# inflow I_u = 8 % with integral length H/2 from 200 random Fourier modes.
+AMR4 = dict(nx=2048, ny=1024, nz=1024, H=384.0, re_h=1.2e5, com=(544.0, 495.5, 540.5),
+            band=[0, 48, 24, 12], wake=[0, 768, 384, 0], intensity=0.08, modes=200, seed=41)
+
+
+def amr4_leg(lt, torch, steps, warmup):
+    """Coarse steps of the four-level FP16 grid with turbulent inflow, replayed
+    from graphs with tuned tiles: MLUPS, the mean and rms fluctuation of C_D
+    over the timed coarse steps, and the per-branch mean forces."""
+    import tempfile
+    stream = STREAM
+    p = lt.tree_params(3, 5, 1.0, 0.3, [0.7] * 3, [0.7] * 3, [0.0, 120.0, 240.0], [35.0] * 3, [90.0] * 3,
+                       jitter=5.0, seed=5)
+    arr = lt.tree_generate(p)
+    lt.tree_place(arr, AMR4["H"], list(AMR4["com"]))
+    g = lt.Grid(AMR4["nx"], AMR4["ny"], AMR4["nz"], u_in=U_IN, re_h=AMR4["re_h"], block_edge=16, levels=4,
+                storage="fp16", drag_every=1, flags=lt.LBM_F_GRAPH, stream=stream.cuda_stream,
+                turb_intensity=AMR4["intensity"], turb_length=AMR4["H"] / 2, turb_seed=AMR4["seed"],
+                turb_modes=AMR4["modes"])
+    t0 = time.time()
+    g.set_geometry(arr, refine={"band": AMR4["band"], "wake": AMR4["wake"]})
+    setup = time.time() - t0
+    if TUNE:
+        g.autotune(TUNE_CACHE or os.path.join(tempfile.mkdtemp(), "tune.txt"))
+    info = g.info()
+    leaf = info["updated_cells"][:4]
+    upd = sum(leaf[l] << l for l in range(4))
+    work = sum(info["collided_cells"][l] << l for l in range(4))
+    g.step(warmup)
+    g.drag()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    d = g.drag(per_branch=True)
+    # C_D of every coarse step of the timed run: the mean of its 8 finest samples
+    series = g.drag_series(8 * steps)[:, 0]
+    cd = series.reshape(steps, 8).mean(1) / (0.5 * U_IN ** 2 * info["area_x"])
+    pb = d["per_branch"][:, 0]
+    gen = lt.branches_to_numpy(arr)[:, 7].astype(int)
+    g.close()
+    return {"workload": "4-level octree, 16^3 blocks, finest 2048x1024x1024 (coarse 256x128x128), order-5 "
+                        "seeded tree H=384, Re_H=1.2e5, FP16 deviations, turbulent inflow I_u=8% (L=H/2, "
+                        "200 modes), bands 12/24/48 + wakes 2H/1H",
+            "coarse_steps": steps, "mlups": round(upd * steps / (ms * 1e-3) / 1e6, 1),
+            "ms_per_coarse_step": round(ms / steps, 4),
+            "step_hbm_frac": round(108.0 * work * steps / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "cd_mean": round(float(cd.mean()), 5), "cd_rms_fluctuation": round(float(cd.std()), 5),
+            "per_branch_mean_fx": {"sum": float(pb.sum()), "by_generation": [float(pb[gen == k].sum())
+                                                                            for k in range(6)],
+                                   "max_branch": int(np.argmax(np.abs(pb))), "max_fx": float(pb[np.argmax(np.abs(pb))])},
+            "grid": {"blocks": info["blocks"][:4], "leaf_fluid_cells": leaf,
+                     "updates_per_coarse_step": upd, "links": info["links"], "branches": info["branches"],
+                     "device_gb": round(info["device_bytes"] / 1e9, 2), "setup_s": round(setup, 1),
+                     "tuned": {"tile_cells": info["tile_cells"], "occ_even": info["occ_even"],
+                               "occ_odd": info["occ_odd"], "xcd_group": info["xcd_group"]},
+                     "effective_finest_cells": AMR4["nx"] * AMR4["ny"] * AMR4["nz"]}}
+
+
+# The paper's own tree in the paper's setup (Table 2, Sec. 2.3): the binary
+# family with n = 4 rewrites (trunk and three child levels, 15 branches), in a
+# 32H x 16H x 16H box with the tree's centre of mass at (8H, 8H, 8H), on 8^3-cell
+# leaf blocks.  Four levels at H = 128 finest cells: coarse H/16 (512 x 256 x
+# 256), finest H/128 (box 4096 x 2048 x 2048); finest blocks within 8 finest
+# cells of the surface, the middle levels within 16 / 32 cells, and a wake box
+# 4H long on level 1 (H/32), two levels coarser than the surface as in the
+# paper (H/256 wake against H/1024 surface).  Re_H = 2500, the lowest of the
+# paper's runs.
+PAPER = dict(n=4, H=128.0, re_h=2500.0, band=[0, 32, 16, 8], wake=[0, 512, 0, 0])
+
+
+def paper_tree_leg(lt, torch, steps, warmup):
+    """The n = 4 tree of Table 2 in the paper's domain at H = 128: device memory,
+    cell counts per level, MLUPS and C_D (graph replay, FP32, tuned tiles)."""
+    import tempfile
+    stream = STREAM
+    H = PAPER["H"]
+    nx, ny, nz = int(32 * H), int(16 * H), int(16 * H)
+    wq = 0.5 ** 0.5
+    p = lt.tree_params(2, PAPER["n"] - 1, 100.0, 30.0, [0.8, 0.8], [wq, wq], [0.0, 0.0], [30.0, -30.0],
+                       [137.0, 137.0])
+    arr = lt.tree_generate(p)
+    lt.tree_place(arr, H, [8 * H, 8 * H, 8 * H])
+    g = lt.Grid(nx, ny, nz, u_in=U_IN, re_h=PAPER["re_h"], block_edge=8, levels=4, storage="fp32", drag_every=1,
+                flags=lt.LBM_F_GRAPH, stream=stream.cuda_stream)
+    t0 = time.time()
+    g.set_geometry(arr, refine={"band": PAPER["band"], "wake": PAPER["wake"]})
+    setup = time.time() - t0
+    if TUNE:
+        g.autotune(TUNE_CACHE or os.path.join(tempfile.mkdtemp(), "tune.txt"))
+    info = g.info()
+    leaf = info["updated_cells"][:4]
+    upd = sum(leaf[l] << l for l in range(4))
+    work = sum(info["collided_cells"][l] << l for l in range(4))
+    g.step(warmup)
+    g.drag()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    d = g.drag()
+    g.close()
+    b = lt.branches_to_numpy(arr)
+    return {"workload": f"paper binary tree n=4 (Table 2), domain 32Hx16Hx16H = {nx}x{ny}x{nz} finest cells, "
+                        f"COM (8H,8H,8H), 8^3 blocks, 4 levels H/16..H/128, wake H/32, Re_H=2500, FP32",
+            "coarse_steps": steps, "mlups": round(upd * steps / (ms * 1e-3) / 1e6, 1),
+            "ms_per_coarse_step": round(ms / steps, 4),
+            "step_hbm_frac": round(216.0 * work * steps / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "cd": round(d["cd"], 5), "d0_over_h": round(b[0, 6] / info["height"], 4),
+            "grid": {"blocks": info["blocks"][:4], "leaf_fluid_cells": leaf, "updates_per_coarse_step": upd,
+                     "total_leaf_cells": int(sum(info["active_cells"][:4])), "links": info["links"],
+                     "device_gb": round(info["device_bytes"] / 1e9, 2), "setup_s": round(setup, 1),
+                     "finest_dx_over_h": round(1.0 / H, 5)}}
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -328,6 +457,10 @@ def main():
     ap.add_argument("--no-amr", action="store_true", help="skip the three-level AMR leg")
     ap.add_argument("--amr-steps", type=int, default=40)
     ap.add_argument("--amr-only", action="store_true", help="run only the three-level AMR leg (profiling)")
+    ap.add_argument("--amr4-steps", type=int, default=16, help="timed coarse steps of the four-level leg")
+    ap.add_argument("--paper-steps", type=int, default=16, help="timed coarse steps of the paper-tree leg")
+    ap.add_argument("--legs", default=None,
+                    help="comma list of legs to run alone and print (amr3, amr4, paper): profiling")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the drag-surrogate leg")
     ap.add_argument("--surrogate-trees", type=int, default=1_000_000)
     ap.add_argument("--surrogate-only", action="store_true", help="run only the drag-surrogate leg (profiling)")
@@ -363,6 +496,12 @@ def main():
     TUNE_CACHE = args.tune_cache
     if args.amr_only:
         print(json.dumps({"amr_3level": amr_leg(lt, torch, args.amr_steps, 4)}), flush=True)
+        return
+    if args.legs:
+        legs = {"amr3": lambda: amr_leg(lt, torch, args.amr_steps, 4),
+                "amr4": lambda: amr4_leg(lt, torch, args.amr4_steps, 2),
+                "paper": lambda: paper_tree_leg(lt, torch, args.paper_steps, 2)}
+        print(json.dumps({k: legs[k]() for k in args.legs.split(",")}), flush=True)
         return
     if args.sweep_only:
         print(json.dumps({"sweep": sweep_only_leg(lt, torch, args.surrogate_trees)}), flush=True)
@@ -436,6 +575,9 @@ def main():
                          "seeded tree H=256, Re_H=2e4, FP32, bands 16/32 + 1H wake")
         a["coarse_steps"] = args.amr_steps
         out["amr_3level"] = a
+    if not args.no_amr:
+        out["amr_4level_fp16_turbulent"] = amr4_leg(lt, torch, args.amr4_steps, 2)
+        out["paper_tree_n4"] = paper_tree_leg(lt, torch, args.paper_steps, 2)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(lt, torch, args.surrogate_trees)
     print(json.dumps(out), flush=True)

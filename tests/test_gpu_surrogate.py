@@ -191,3 +191,55 @@ def test_many_tree_sweeps_match_oracle(gpu, intensity):
                                  env[0], env[1], ag[i], A.cylinder_cd)
         err = np.abs(cd_s[i] - want_s) / np.abs(want_s)
         assert err.max() < 5e-3, f"tree {i} surrogate: {err.max():.2e}"
+
+
+def _paper_params(gpu, n):
+    """The binary family of Table 2 with n rewrites (n generations: trunk and
+    n - 1 child levels, the reading that reproduces Table 3)."""
+    wq = 0.5 ** 0.5
+    return gpu.tree_params(2, n - 1, 100.0, 30.0, [0.8, 0.8], [wq, wq], [0.0, 0.0], [30.0, -30.0], [137.0, 137.0])
+
+
+def test_paper_tree_crisis_curves_match_oracle(gpu):
+    """The drag-crisis curves of the paper's trees n = 4, 6, 8 (Sec. 4.1 and
+    4.2, with the synthetic cylinder curve of the analytic model): frontal area
+    and C_D-est(Re_H) from 1e3 to 1e9 at I_u = 0 and 8 % on the GPU against the
+    oracle; the crisis sets in near Re_H = 3e6 under uniform inflow and an order
+    of magnitude earlier at I_u = 8 %, and the drop softens as n grows."""
+    import torch
+
+    import oracle as O
+    from oracle import analytic_oracle as A
+    re_h = 10.0 ** np.linspace(3, 9, 31)  # at most 32 Re_H per sweep
+    onsets, steepest, slopes = {}, {}, {}
+    for n in (4, 6, 8):
+        rec, start = gpu.tree_batch(_paper_params(gpu, n), 0, [n - 1])
+        assert start[-1] == 2 ** n - 1
+        rd, sd = torch.from_numpy(rec).cuda(), torch.from_numpy(start).cuda()
+        area = torch.empty(1, dtype=torch.float32, device="cuda")
+        h = 1.0 / 256
+        gpu.frontal_area(rd, sd, h, area)
+        b = O.build_tree(O.paper_tree_params(n - 1), 1.0, [0.0, 0.0, 0.0])
+        ao = A.projected_area(b, h)
+        ag = float(area.cpu()[0])
+        assert abs(ag - ao) <= 2e-3 * ao
+        for iu in (0.0, 0.08):
+            cd = torch.empty((1, len(re_h)), dtype=torch.float32, device="cuda")
+            gpu.analytic_sweep(rd, sd, area, cd, re_h, iu)
+            got = cd.cpu().numpy()[0].astype(np.float64)
+            want = A.tree_cd_est(b, re_h, 1.0, ag, iu)
+            assert np.allclose(got, want, rtol=2e-4)
+            ref = got[np.searchsorted(re_h, 1e5)]
+            onsets[(n, iu)] = re_h[np.argmax((re_h > 1e5) & (got < 0.9 * ref))]
+            s = np.diff(np.log(got)) / np.diff(np.log(re_h))
+            steepest[(n, iu)] = np.sqrt(re_h[np.argmin(s)] * re_h[np.argmin(s) + 1])
+            slopes[(n, iu)] = -s.min()
+    print("  uniform inflow: C_D 10 % below its Re_H = 1e5 value at "
+          + ", ".join(f"n={n}: {onsets[(n, 0.0)]:.3g}" for n in (4, 6, 8))
+          + "; steepest drop at I_u = 0 / 8 %: "
+          + ", ".join(f"n={n}: {steepest[(n, 0.0)]:.3g} / {steepest[(n, 0.08)]:.3g}" for n in (4, 6, 8)),
+          flush=True)
+    for n in (4, 6, 8):
+        assert 1e6 < onsets[(n, 0.0)] < 1e7
+        assert steepest[(n, 0.08)] < steepest[(n, 0.0)] / 5
+    assert slopes[(4, 0.0)] > slopes[(6, 0.0)] > slopes[(8, 0.0)]
