@@ -311,27 +311,46 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 MLP_FLOP = 8960  # 2 x (5 x 64 + 64 x 64 + 64) per inference
 
 
-def surrogate_leg(lt, torch, n_trees, chunk=1 << 17):
+# Training sweeps of the surrogate.  "small": orders 1-3 at Re_H 100-800 (224
+# runs, about a minute: the default bench leg).  "large": orders 1-4 at Re_H
+# 100 to 2e4 (the seeded workloads' Reynolds numbers, 2500 and 2e4 included),
+# about 1e5 per-branch samples from 3220 runs.  Both: I_u 0 and 8 %, trees of
+# height 32 in a 128 x 64 x 64 box, held-out seeds disjoint from training.
+SURROGATE_SWEEPS = {
+    "small": dict(re_h=(100.0, 200.0, 400.0, 800.0),
+                  train={1: range(1000, 1016), 2: range(1100, 1108), 3: range(1200, 1204)},
+                  held={1: range(1057, 1060), 2: range(1127, 1130), 3: range(1212, 1215)}),
+    "large": dict(re_h=(100.0, 300.0, 1000.0, 2500.0, 5000.0, 1.0e4, 2.0e4),
+                  train={1: range(2000, 2100), 2: range(3000, 3060), 3: range(4000, 4040), 4: range(5000, 5030)},
+                  held={1: range(9000, 9003), 2: range(9100, 9103), 3: range(9200, 9203), 4: range(9300, 9303)}),
+}
+
+
+def surrogate_leg(lt, torch, n_trees, chunk=1 << 17, scale="small"):
     """Learned per-branch drag surrogate: trained on per-branch forces from LBM
-    runs of seeded trees (orders 1-3, Re_H 100-800, I_u 0 and 8 %), checked on
-    held-out seeds, then swept over n_trees seeded trees (orders 1-6 in turn) at
-    25 Re_H from 1e3 to 1e9 on the matrix cores, with the analytic model
-    (Eqs. (2), (4)) on the same trees."""
+    runs of seeded trees (SURROGATE_SWEEPS[scale]: orders, Re_H, I_u 0 and
+    8 %), checked on held-out seeds (mean and maximum tree-C_D error), then
+    swept over n_trees seeded trees (orders 1-6 in turn) at 25 Re_H from 1e3 to
+    1e9 on the matrix cores, with the analytic model (Eqs. (2), (4)) on the
+    same trees."""
     from paper_2603_27954_amd import surrogate as S
     stream = STREAM
     t0 = time.time()
+    sw = SURROGATE_SWEEPS[scale]
 
     def runs(seeds_by_order):
         out = []
         for order, seeds in seeds_by_order.items():
-            for re_h in (100.0, 200.0, 400.0, 800.0):
+            for re_h in sw["re_h"]:
                 for iu in (0.0, 0.08):
                     for seed in seeds:
-                        out.append(S.lbm_samples(order, seed, re_h, iu, stream=stream.cuda_stream))
+                        r = S.lbm_samples(order, seed, re_h, iu, stream=stream.cuda_stream)
+                        r.update(order=order, re_h=re_h, iu=iu, seed=seed)
+                        out.append(r)
         return out
 
-    train = runs({1: range(1000, 1016), 2: range(1100, 1108), 3: range(1200, 1204)})
-    held = runs({1: range(1057, 1060), 2: range(1127, 1130), 3: range(1212, 1215)})
+    train = runs(sw["train"])
+    held = runs(sw["held"])
     lbm_s = time.time() - t0
     X = np.concatenate([r["feat"] for r in train])
     Y = np.concatenate([r["y"] for r in train])
@@ -341,7 +360,24 @@ def surrogate_leg(lt, torch, n_trees, chunk=1 << 17):
     losses = m.train(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), epochs=40, batch=256, lr=2e-3,
                      seed=17)
     train_s = time.time() - t1
-    err = [abs(S.tree_cd(m, r["feat"], r["ld"], r["area_x"]) - r["cd"]) / r["cd"] for r in held]
+    err = np.array([abs(S.tree_cd(m, r["feat"], r["ld"], r["area_x"]) - r["cd"]) / r["cd"] for r in held])
+    # the analytic model of Eqs. (2), (4) on the same held-out runs (the
+    # method without the learned part), on the GPU: the run's tree as a unit-
+    # height branch batch, its voxel frontal area over H^2
+    params = lt.tree_params(3, 1, 1.0, 0.3, [0.7] * 3, [0.7] * 3, [0.0, 120.0, 240.0], [35.0] * 3, [90.0] * 3,
+                            jitter=5.0, seed=0)
+    err_a = []
+    for r in held:
+        rec, start = lt.tree_batch(params, r["seed"], [r["order"]])
+        rd, sd = torch.from_numpy(rec).cuda(), torch.from_numpy(start).cuda()
+        area = torch.tensor([r["area_x"] / 32.0 ** 2], dtype=torch.float32, device="cuda")
+        cda = torch.empty((1, 1), dtype=torch.float32, device="cuda")
+        lt.analytic_sweep(rd, sd, area, cda, [r["re_h"]], r["iu"], stream.cuda_stream)
+        torch.cuda.synchronize()
+        err_a.append(abs(float(cda.cpu()[0, 0]) - r["cd"]) / r["cd"])
+    err_a = np.array(err_a)
+    by_re = {f"{re:g}": round(float(np.mean([e for e, r in zip(err, held) if r["re_h"] == re])), 4)
+             for re in sw["re_h"]}
     re_d = 10.0 ** X[:, 0]
     env = (float(re_d.min()), float(re_d.max()))
     sweep = sweep_trees(lt, torch, m, env, n_trees, chunk)
@@ -351,7 +387,11 @@ def surrogate_leg(lt, torch, n_trees, chunk=1 << 17):
                      "epochs": 40, "train_seconds": round(train_s, 2), "final_loss": float(losses[-1]),
                      "re_d_envelope": [round(env[0], 2), round(env[1], 1)]},
         "held_out": {"runs": len(held), "cd_rel_err_mean": round(float(np.mean(err)), 4),
-                     "cd_rel_err_max": round(float(np.max(err)), 4)},
+                     "cd_rel_err_max": round(float(np.max(err)), 4),
+                     "cd_rel_err_p90": round(float(np.quantile(err, 0.9)), 4),
+                     "analytic_cd_rel_err_mean": round(float(np.mean(err_a)), 4),
+                     "mean_err_by_re_h": by_re},
+        "scale": scale,
         "sweep": sweep,
     }
 
@@ -423,6 +463,31 @@ def sweep_only_leg(lt, torch, n_trees):
     return out
 
 
+GOLDEN_SERIES = os.path.join(ROOT, "tests", "golden", "cd_series_uniform512x256x256.txt")
+
+
+def cd_series_error(lt, torch, arr):
+    """C_D of every step of the first 1000 against the FP64 oracle's series of
+    the same workload (stored by tests/golden/make_cd_series.py): the largest
+    difference over the mean |C_D| and the relative error of the mean C_D over
+    steps 501-1000, FP32 and FP16 storage.  None when the series is absent."""
+    if not os.path.exists(GOLDEN_SERIES):
+        return None
+    ref = np.loadtxt(GOLDEN_SERIES, comments="#")[:, 1]
+    out = {"oracle_mean_cd_501_1000": round(float(ref[500:].mean()), 6)}
+    for storage in ("fp32", "fp16"):
+        g = lt.Grid(NX, NY, NZ, u_in=U_IN, re_h=RE_H, storage=storage, drag_every=1, stream=STREAM.cuda_stream)
+        g.set_geometry(arr)
+        g.step(len(ref))
+        f = g.drag_series(len(ref))
+        ax = g.info()["area_x"]
+        g.close()
+        cd = f[:, 0] / (0.5 * U_IN ** 2 * ax)
+        out[storage] = {"max_dev_over_mean_abs_cd": float(np.abs(cd - ref).max() / np.abs(ref).mean()),
+                        "mean_cd_501_1000_rel": float(abs(cd[500:].mean() - ref[500:].mean()) / abs(ref[500:].mean()))}
+    return out
+
+
 def cpu_leg(lt, arr, nsteps):
     import oracle as O
     b = lt.branches_to_numpy(arr)
@@ -463,6 +528,8 @@ def main():
                     help="comma list of legs to run alone and print (amr3, amr4, paper): profiling")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the drag-surrogate leg")
     ap.add_argument("--surrogate-trees", type=int, default=1_000_000)
+    ap.add_argument("--surrogate-scale", choices=list(SURROGATE_SWEEPS), default="small",
+                    help="training sweep of the surrogate (large: about 1e5 samples, several minutes)")
     ap.add_argument("--surrogate-only", action="store_true", help="run only the drag-surrogate leg (profiling)")
     ap.add_argument("--sweep-only", action="store_true",
                     help="run only the many-tree sweep with an untrained network (profiling its kernels)")
@@ -507,7 +574,8 @@ def main():
         print(json.dumps({"sweep": sweep_only_leg(lt, torch, args.surrogate_trees)}), flush=True)
         return
     if args.surrogate_only:
-        print(json.dumps({"surrogate": surrogate_leg(lt, torch, args.surrogate_trees)}), flush=True)
+        print(json.dumps({"surrogate": surrogate_leg(lt, torch, args.surrogate_trees, scale=args.surrogate_scale)}),
+              flush=True)
         return
     arr = build_tree(lt)
     r32 = r16 = None
@@ -569,6 +637,9 @@ def main():
         out["cd_error"] = {"steps": args.cpu_steps, "cd_oracle": c["cd"],
                            "fp32_rel": abs(cd32 - c["cd"]) / abs(c["cd"]),
                            "fp16_rel": abs(cd16 - c["cd"]) / abs(c["cd"])}
+        series = cd_series_error(lt, torch, arr)
+        if series is not None:
+            out["cd_error"]["series_1000_steps"] = series
     if not args.no_amr:
         a = amr_leg(lt, torch, args.amr_steps, 4)
         a["workload"] = ("3-level octree, 16^3 blocks, finest 1024x512x512 (coarse 256x128x128), order-4 "
@@ -579,7 +650,7 @@ def main():
         out["amr_4level_fp16_turbulent"] = amr4_leg(lt, torch, args.amr4_steps, 2)
         out["paper_tree_n4"] = paper_tree_leg(lt, torch, args.paper_steps, 2)
     if not args.no_surrogate:
-        out["surrogate"] = surrogate_leg(lt, torch, args.surrogate_trees)
+        out["surrogate"] = surrogate_leg(lt, torch, args.surrogate_trees, scale=args.surrogate_scale)
     print(json.dumps(out), flush=True)
 
 

@@ -25,7 +25,8 @@
  *     whole box (nx_l = nx >> (levels-1-l), likewise y, z); SoA for populations
  *     (f[i*N + cell]);
  *   - all host pointers are owned by the caller, read or written only during
- *     the call; device memory is allocated and owned by the library;
+ *     the call; device memory is allocated and owned by the library, except
+ *     the populations when the caller binds its own (lbm_bind_memory);
  *   - one grid handle is used by one host thread at a time.
  */
 #ifndef LBMTREE_H
@@ -61,6 +62,9 @@ typedef enum {
 #define LBM_F_PERSISTENT 4u  /* run each coarse step as one persistent launch over its phase list;
                                 currently disabled: lbm_create_grid rejects it with LBM_E_INVALID */
 #define LBM_F_AUTOTUNE 8u    /* time the tile candidates at set_geometry and keep the fastest */
+#define LBM_F_FRICTION 16u   /* with every force sample, also integrate the wall shear stress over the
+                                tree surface (friction force, Sec. 3 Eq. (8)); lbm_drag then reports
+                                C_F and C_P = C_D - C_F (Eq. (9)) */
 
 /* One cylinder of the tree (Sec. 2.1: the tree is an assembly of cylinders).
  * The solid is the union of the cylinders and of a sphere of the same
@@ -127,6 +131,8 @@ typedef struct {
     double mass;       /* sum of rho * cell volume (finest units) over all active cells */
     int64_t samples;   /* force samples averaged */
     int64_t step;      /* coarse steps done */
+    double friction[3]; /* FP64 mean friction force over the same samples (LBM_F_FRICTION; else 0) */
+    double cf, cp;      /* C_F = friction[0] / (0.5 u_in^2 area_x) (Eq. (8)), C_P = C_D - C_F (Eq. (9)) */
 } lbm_drag_result;
 
 typedef struct {
@@ -152,32 +158,70 @@ typedef struct {
 
 /* ---- lifecycle ------------------------------------------------------------ */
 
-/* Validates d on the host (sizes, Mach, levels, storage) and creates a grid
- * bound to d->device.  No device memory is allocated yet. */
+/* The problem statement of Sec. 2.3: the inflow speed u_in (uniform at x = 0,
+ * or with the turbulence of Sec. 4.2), Re_H = u_in H / nu, the box and the
+ * refinement levels of the octree of Sec. 2.2.  Validates d on the host
+ * (sizes, Mach, levels, storage) and creates a grid bound to d->device.  No
+ * device memory is allocated yet. */
 lbm_status lbm_create_grid(const lbm_grid_desc *d, lbm_grid **out);
 
-/* Voxelises the branches (copied), builds boundary links with their wall
- * distances q, the block grid and its refinement (refine may be NULL when
- * levels == 1), uploads everything and initialises f = f_eq(1, u_in) in fluid.
+/* The tree geometry (Sec. 2.1, an assembly of cylinders) and the grid around
+ * it (Sec. 2.2: finest blocks near the surface, a moderately refined wake,
+ * coarse blocks elsewhere).  Voxelises the branches (copied), builds boundary
+ * links with their wall distances q for the interpolated bounce-back, the
+ * block grid and its refinement (refine may be NULL when levels == 1), uploads
+ * everything and initialises f = f_eq(1, u_in) in fluid (Sec. 2.3).
  * Fails with LBM_E_INVALID when a branch or refined region comes within one
  * block of the box faces.  device_bytes_out (may be NULL) receives the device
- * memory held. */
+ * memory the library allocated (memory bound with lbm_bind_memory excluded). */
 lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b,
                             const lbm_refine_desc *refine, size_t *device_bytes_out);
 
-/* Advances n coarse steps (2^(levels-1) finest sub-steps each), asynchronously
- * on the grid's stream. */
+/* Places the populations of every level in caller-owned device memory (for
+ * example a torch tensor) instead of memory the library allocates, so that a
+ * framework above the library keeps the largest buffer.  Call between
+ * lbm_create_grid and lbm_set_geometry (LBM_E_STATE otherwise).  device_ptr:
+ * device memory of the grid's device, 256-byte aligned (LBM_E_INVALID
+ * otherwise); bytes: its size, at least lbm_plan_levels' pop_bytes for the
+ * same description (checked by lbm_set_geometry, LBM_E_INVALID when short).
+ * The caller keeps the memory alive until lbm_destroy_grid; the library never
+ * frees it and owns its contents (populations as deviations, per level 27
+ * direction arrays) while the grid lives.  The rest of the grid (tables,
+ * links, sums) stays library-allocated. */
+lbm_status lbm_bind_memory(lbm_grid *g, void *device_ptr, size_t bytes);
+
+/* The time marching of Sec. 2.2: cumulant collision and streaming on every
+ * level, sub-cycled (a level-l sub-step is 2^(levels-1-l) finest steps), with
+ * the coarse/fine coupling, the interpolated bounce-back at the tree surface
+ * and the momentum-exchange force sampled every drag_every finest steps.
+ * Advances n coarse steps (2^(levels-1) finest sub-steps each),
+ * asynchronously on the grid's stream. */
 lbm_status lbm_step(lbm_grid *g, int32_t n_coarse_steps);
 
-/* Synchronises, returns the mean force over the samples taken since the
+/* The drag of Sec. 2.2 (momentum exchange over the tree surface) and Eq. (7)
+ * (C_D = F_x / (rho U^2 A_x / 2), A_x the frontal area).  Synchronises,
+ * returns the mean force over the samples taken since the
  * previous lbm_drag (then restarts the mean), C_D, mass; per_branch (3*n_b
  * doubles, may be NULL) receives the mean force per branch id.  Returns
  * LBM_E_UNSTABLE when the run has produced NaN or a density outside
  * [0.5, 1.5]. */
 lbm_status lbm_drag(lbm_grid *g, lbm_drag_result *out, double *per_branch);
 
-/* Copies out up to cap force samples (3 doubles each, FP64, oldest first) of
- * the ring of the last 65536 samples; *n receives the count copied. */
+/* lbm_drag, and per_branch_friction (3*n_b doubles, may be NULL) receives the
+ * mean friction force per branch id (Sec. 3: the wall shear stress integrated
+ * over the branch's surface).  Friction is sampled only with LBM_F_FRICTION
+ * (LBM_E_STATE otherwise when per_branch_friction is given).  The shear stress
+ * of a surface cell is the deviatoric stress -(1 - omega1/2) dev(N) of its
+ * pre-collision non-equilibrium second-order central moments N; each axis face
+ * between a fluid cell x_f and a solid neighbour x_f + e_k carries the stress
+ * extrapolated along e_k from x_f and x_f - e_k to the wall point x_f + q e_k,
+ * its traction on the branch's analytic outward normal n with the normal part
+ * removed, and the weight |n_k|. */
+lbm_status lbm_drag_split(lbm_grid *g, lbm_drag_result *out, double *per_branch, double *per_branch_friction);
+
+/* The drag history of Sec. 2.2 / Eq. (7) sample by sample: copies out up to
+ * cap force samples (3 doubles each, FP64, oldest first) of the ring of the
+ * last 65536 samples; *n receives the count copied. */
 lbm_status lbm_drag_series(lbm_grid *g, double *out, int64_t cap, int64_t *n);
 
 void lbm_destroy_grid(lbm_grid *g);
@@ -186,11 +230,13 @@ lbm_status lbm_get_info(const lbm_grid *g, lbm_info *out);
 
 /* ---- geometry helpers (host only) ------------------------------------------ */
 
-/* Writes up to cap branches of the tree of p (trunk base at the origin,
- * heading +z, left +y); *n receives the full count. */
+/* The L-system of Eq. (1) read by the turtle of Table 1 (Sec. 2.1): writes up
+ * to cap branches of the tree of p (trunk base at the origin, heading +z, left
+ * +y); *n receives the full count. */
 lbm_status lbm_tree_generate(const lbm_tree_params *p, lbm_branch *out, int32_t cap, int32_t *n);
 
-/* Scales about the trunk base to height target_h (when > 0) and translates so
+/* The placement of Sec. 2.3 (tree height H, centre of mass at a given point):
+ * scales about the trunk base to height target_h (when > 0) and translates so
  * the cylinder-volume centre of mass is at com.  *height_out (may be NULL)
  * receives the final height. */
 lbm_status lbm_tree_place(lbm_branch *b, int32_t n, double target_h, const double com[3],
@@ -361,7 +407,8 @@ typedef struct {
     int64_t work_blocks[4];       /* blocks (dense: 256-cell tiles) holding cells to collide */
     int64_t work_tiles[4];        /* of those, B^2-cell z-slices holding cells to collide */
     int64_t links, solid_cells;
-    int64_t pop_bytes;            /* population storage of every level in d->storage */
+    int64_t pop_bytes;            /* population storage of every level in d->storage: the size
+                                     lbm_bind_memory needs */
 } lbm_plan;
 
 /* maps may be NULL; otherwise maps[l] (may be NULL) receives level l's block

@@ -74,15 +74,19 @@ def branch_normal(br, x):
     return min(cands, key=lambda c: c[0])[1]
 
 
-def friction_force(f, omega1, solid, link, shape, normal, n_branch=1):
+def friction_force(f, omega1, solid, link, shape, normal, n_branch=1, usable=None):
     """Friction force on the body (3,) and per branch (n_branch, 3).
 
     f: pre-collision populations (27, N) of the box shape = (nx, ny, nz),
     cell = x + nx (y + ny z); solid: (N,) mask; link: dict of arrays cell,
     dir, q, branch (the boundary links); normal(x_w, branch) -> outward unit
-    normal at the wall point (cell centres at integer + 1/2)."""
+    normal at the wall point (cell centres at integer + 1/2); usable: (N,)
+    mask of the cells whose stress may serve as x_f - e_k (default: the fluid
+    cells; on a refined grid, the fluid cells of the finest level's leaf
+    blocks)."""
     nx, ny, nz = shape
     solid = np.asarray(solid).astype(bool)
+    usable = ~solid if usable is None else np.asarray(usable).astype(bool)
     sel = np.isin(link["dir"], list(AXES))
     cells = link["cell"][sel].astype(np.int64)
     dirs = link["dir"][sel].astype(np.int64)
@@ -98,13 +102,15 @@ def friction_force(f, omega1, solid, link, shape, normal, n_branch=1):
     inside = np.all((back >= 0) & (back < np.array([nx, ny, nz])), axis=1)
     bcell = back[:, 0] + nx * (back[:, 1] + ny * back[:, 2])
     bcell = np.where(inside, bcell, cells)
-    up = inside & ~solid[bcell]
+    up = inside & usable[bcell]
     s0 = cell_stress(f[:, cells], omega1)
     s1 = cell_stress(f[:, bcell], omega1)
     sw = np.where(up[:, None, None], s0 + qs[:, None, None] * (s0 - s1), s0)
     total = np.zeros(3)
     per = np.zeros((max(n_branch, 1), 3))
     for k in range(len(cells)):
+        if brs[k] < 0:  # a wall point no branch claims has no normal
+            continue
         xw = np.array([x[k] + 0.5, y[k] + 0.5, z[k] + 0.5])
         xw[ax[k]] += sg[k] * qs[k]
         n = normal(xw, brs[k])
@@ -112,13 +118,13 @@ def friction_force(f, omega1, solid, link, shape, normal, n_branch=1):
         tau = t - (n @ t) * n
         df = abs(n[ax[k]]) * tau
         total += df
-        if 0 <= brs[k] < n_branch:
+        if brs[k] < n_branch:
             per[brs[k]] += df
     return total, per
 
 
-def tree_friction_force(f, omega1, solid, link, shape, branches):
+def tree_friction_force(f, omega1, solid, link, shape, branches, usable=None):
     """friction_force with the analytic normals of the tree's branches
     (rows of 10: p0, p1, diameter, generation, parent, id)."""
     b = np.asarray(branches, dtype=np.float64)
-    return friction_force(f, omega1, solid, link, shape, lambda xw, k: branch_normal(b[k], xw), len(b))
+    return friction_force(f, omega1, solid, link, shape, lambda xw, k: branch_normal(b[k], xw), len(b), usable)

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "liblbmtree.so")
 
 LBM_OK, LBM_E_INVALID, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_STATE = 0, -1, -2, -3, -4, -5
 LBM_FP32, LBM_FP16_DEV, LBM_BF16_DEV = 0, 1, 2
-LBM_F_NO_GALILEAN, LBM_F_GRAPH, LBM_F_PERSISTENT, LBM_F_AUTOTUNE = 1, 2, 4, 8
+LBM_F_NO_GALILEAN, LBM_F_GRAPH, LBM_F_PERSISTENT, LBM_F_AUTOTUNE, LBM_F_FRICTION = 1, 2, 4, 8, 16
 STORAGE = {"fp32": LBM_FP32, "fp16": LBM_FP16_DEV, "bf16": LBM_BF16_DEV}
 
 _STATUS_NAMES = {0: "LBM_OK", -1: "LBM_E_INVALID", -2: "LBM_E_NOMEM", -3: "LBM_E_DEVICE",
@@ -75,7 +75,8 @@ class PersistModelResult(C.Structure):
 
 class DragResult(C.Structure):
     _fields_ = [("force", C.c_double * 3), ("cd", C.c_double), ("area_x", C.c_double),
-                ("height", C.c_double), ("mass", C.c_double), ("samples", C.c_int64), ("step", C.c_int64)]
+                ("height", C.c_double), ("mass", C.c_double), ("samples", C.c_int64), ("step", C.c_int64),
+                ("friction", C.c_double * 3), ("cf", C.c_double), ("cp", C.c_double)]
 
 
 class Info(C.Structure):
@@ -138,6 +139,8 @@ def lib():
         "lbm_plan_levels": [C.POINTER(GridDesc), C.POINTER(Branch), C.c_int32, C.POINTER(RefineDesc),
                             C.POINTER(Plan), C.POINTER(C.POINTER(C.c_int8))],
         "lbm_mass": [_P, _dp],
+        "lbm_drag_split": [_P, C.POINTER(DragResult), _dp, _dp],
+        "lbm_bind_memory": [_P, _P, C.c_size_t],
         "lbm_plan_phases": [C.POINTER(GridDesc), C.POINTER(Branch), C.c_int32, C.POINTER(RefineDesc), C.c_int32,
                             C.c_int32, C.POINTER(PhaseInfo), C.c_int32, C.POINTER(C.c_int32)],
         "lbm_persist_model": [C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_uint32),
@@ -524,6 +527,14 @@ class Grid:
         s = self.desc.levels - 1 - level
         return self.desc.nx >> s, self.desc.ny >> s, self.desc.nz >> s
 
+    def bind_memory(self, tensor):
+        """Populations in the caller's device tensor (lbm_bind_memory); the
+        tensor must outlive the grid."""
+        assert tensor.is_cuda and tensor.is_contiguous()
+        self._bound = tensor
+        _check(lib().lbm_bind_memory(self.h, C.c_void_p(tensor.data_ptr()), tensor.numel() * tensor.element_size()),
+               self.h)
+
     def set_geometry(self, branches, refine: Optional[dict] = None):
         if isinstance(branches, np.ndarray):
             branches = branches_from_numpy(branches)
@@ -537,14 +548,19 @@ class Grid:
     def step(self, n=1):
         _check(lib().lbm_step(self.h, n), self.h)
 
-    def drag(self, per_branch=False):
+    def drag(self, per_branch=False, per_branch_friction=False):
         r = DragResult()
         pb = np.zeros(3 * max(self.n_branch, 1)) if per_branch else None
-        _check(lib().lbm_drag(self.h, C.byref(r), _dptr(pb) if pb is not None else None), self.h)
+        pf = np.zeros(3 * max(self.n_branch, 1)) if per_branch_friction else None
+        _check(lib().lbm_drag_split(self.h, C.byref(r), _dptr(pb) if pb is not None else None,
+                                    _dptr(pf) if pf is not None else None), self.h)
         out = {"force": np.array(r.force), "cd": r.cd, "area_x": r.area_x, "height": r.height,
-               "mass": r.mass, "samples": r.samples, "step": r.step}
+               "mass": r.mass, "samples": r.samples, "step": r.step, "friction": np.array(r.friction),
+               "cf": r.cf, "cp": r.cp}
         if per_branch:
             out["per_branch"] = pb.reshape(-1, 3)[: self.n_branch]
+        if per_branch_friction:
+            out["per_branch_friction"] = pf.reshape(-1, 3)[: self.n_branch]
         return out
 
     def drag_series(self, cap=65536):

@@ -393,7 +393,8 @@ __device__ __forceinline__ void link_piece_sum(const float *lforce, const int *p
 // acc_branch; then the total over the branches (thread t adds branches t,
 // t + 256, ... in order, then block_sum3) is added to acc_total and appended
 // to the sample ring at the device-held position ring_pos, which a replayed
-// graph advances itself.  Called by the whole work-group (256 threads) after
+// graph advances itself (sample and ring null: the accumulators only).
+// Called by the whole work-group (256 threads) after
 // an acquire of the piece sums.
 __device__ __forceinline__ void branch_totals(const double *piece_sum, const int *segp, int nseg, double *sample,
                                               double *acc_branch, double *acc_total, double *ring,
@@ -418,19 +419,22 @@ __device__ __forceinline__ void branch_totals(const double *piece_sum, const int
                         t[a] += buf[i][a];
         }
         for (int a = 0; a < 3; ++a) {
-            sample[3 * s + a] = t[a];
+            if (sample)
+                sample[3 * s + a] = t[a];
             acc_branch[3 * s + a] += t[a];
             tot[a] += t[a];
         }
     }
     block_sum3(tot, sh);
     if (threadIdx.x == 0) {
-        const unsigned long long slot = *ring_pos % RING;
-        for (int a = 0; a < 3; ++a) {
+        for (int a = 0; a < 3; ++a)
             acc_total[a] += tot[a];
-            ring[3 * slot + a] = tot[a];
+        if (ring) {
+            const unsigned long long slot = *ring_pos % RING;
+            for (int a = 0; a < 3; ++a)
+                ring[3 * slot + a] = tot[a];
+            *ring_pos += 1ull;
         }
-        *ring_pos += 1ull;
     }
 }
 

@@ -15,7 +15,7 @@ using namespace lbm;
 
 namespace {
 
-const uint64_t MAGIC = 0x32544B43544D424CULL;  // checkpoint tag (format 2: with the force ring)
+const uint64_t MAGIC = 0x33544B43544D424CULL;  // checkpoint tag (format 3: force ring, friction sums)
 
 struct CkptHeader {
     uint64_t magic;
@@ -75,6 +75,15 @@ lbm_status lbm_save(lbm_grid *g, const char *path)
     if (ok)
         ok = hipMemcpy(ring.data(), g->d_ring, sizeof(double) * ring.size(), hipMemcpyDeviceToHost) == hipSuccess &&
              wr(f, ring.data(), sizeof(double) * ring.size());
+    // the friction accumulators (zero when friction is not sampled)
+    std::vector<double> facc(3 * (size_t)g->nseg + 3, 0.0);
+    if (ok && g->d_facc_total)
+        ok = hipMemcpy(facc.data(), g->d_facc_branch, sizeof(double) * 3 * g->nseg, hipMemcpyDeviceToHost) ==
+                 hipSuccess &&
+             hipMemcpy(facc.data() + 3 * g->nseg, g->d_facc_total, sizeof(double) * 3, hipMemcpyDeviceToHost) ==
+                 hipSuccess;
+    if (ok)
+        ok = wr(f, facc.data(), sizeof(double) * facc.size());
     ok = (fclose(f) == 0) && ok;
     return ok ? LBM_OK : grid_fail(g, LBM_E_DEVICE, "checkpoint write failed");
 }
@@ -112,6 +121,13 @@ lbm_status lbm_load(lbm_grid *g, const char *path)
     std::vector<double> ring(3 * (size_t)RING);
     ok = ok && rd(f, ring.data(), sizeof(double) * ring.size()) &&
          hipMemcpy(g->d_ring, ring.data(), sizeof(double) * ring.size(), hipMemcpyHostToDevice) == hipSuccess;
+    std::vector<double> facc(3 * (size_t)g->nseg + 3, 0.0);
+    ok = ok && rd(f, facc.data(), sizeof(double) * facc.size());
+    if (ok && g->d_facc_total)
+        ok = hipMemcpy(g->d_facc_branch, facc.data(), sizeof(double) * 3 * g->nseg, hipMemcpyHostToDevice) ==
+                 hipSuccess &&
+             hipMemcpy(g->d_facc_total, facc.data() + 3 * g->nseg, sizeof(double) * 3, hipMemcpyHostToDevice) ==
+                 hipSuccess;
     fclose(f);
     if (!ok)
         return grid_fail(g, LBM_E_DEVICE, "checkpoint read failed");

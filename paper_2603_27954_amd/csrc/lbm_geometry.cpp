@@ -375,6 +375,38 @@ int64_t build_links(const lbm_branch *b, int n, int nx, int ny, int nz, const st
     return (int64_t)links.size();
 }
 
+void branch_wall_normal(const lbm_branch &b, const double x[3], double n[3])
+{
+    const Shape s = make_shape(b);
+    const V3 p{x[0], x[1], x[2]};
+    const V3 rel = p - s.p0;
+    const double along = dot(rel, s.axis);  // distance along the axis from p0
+    double best = 1e300;
+    V3 nb{0.0, 0.0, 1.0};
+    // side of the cylinder
+    const V3 radial = rel - along * s.axis;
+    const double rr = std::sqrt(dot(radial, radial));
+    if (along >= 0.0 && along <= s.len && rr > 0.0) {
+        best = std::fabs(rr - s.r);
+        nb = (1.0 / rr) * radial;
+    }
+    // sphere at the end
+    const V3 sp = p - s.p1;
+    const double rs = std::sqrt(dot(sp, sp));
+    if (rs > 0.0 && std::fabs(rs - s.r) < best) {
+        best = std::fabs(rs - s.r);
+        nb = (1.0 / rs) * sp;
+    }
+    // base disc at p0
+    if (rr <= s.r && std::fabs(along) < best) {
+        best = std::fabs(along);
+        nb = -1.0 * s.axis;
+    }
+    n[0] = nb.x;
+    n[1] = nb.y;
+    n[2] = nb.z;
+}
+
 int64_t frontal_area(const std::vector<uint8_t> &solid, int nx, int ny, int nz)
 {
     int64_t a = 0;

@@ -24,5 +24,9 @@ void voxelize(const lbm_branch *b, int n, int nx, int ny, int nz, std::vector<ui
 int64_t build_links(const lbm_branch *b, int n, int nx, int ny, int nz, const std::vector<uint8_t> &solid,
                     std::vector<HostLink> &links);
 int64_t frontal_area(const std::vector<uint8_t> &solid, int nx, int ny, int nz);
+// Outward unit normal of one branch's solid (cylinder p0 -> p1 of diameter D
+// and a sphere of diameter D at p1) at a point x of its surface: the normal
+// of the nearest of the cylinder side, the end sphere and the base disc.
+void branch_wall_normal(const lbm_branch &b, const double x[3], double n[3]);
 
 }  // namespace lbm

@@ -43,6 +43,16 @@ struct lbm_grid {
     unsigned *d_counter = nullptr;
     double *d_mass = nullptr;
     std::vector<int32_t> link_perm;  // device order -> (cell, dir) order
+    // wall friction (LBM_F_FRICTION): axis faces between fluid and solid cells,
+    // sorted by branch and cut into pieces for the FP64 reduction
+    int n_fric = 0, fric_npieces = 0;
+    uint32_t *d_fa0 = nullptr, *d_fa1 = nullptr;
+    float *d_fq = nullptr;
+    float4 *d_fnw = nullptr;
+    float *d_fforce = nullptr;
+    int *d_fpstart = nullptr, *d_fsegp = nullptr;
+    double *d_fpiece_sum = nullptr, *d_facc_branch = nullptr, *d_facc_total = nullptr;
+    unsigned *d_fcounter = nullptr;
     int64_t samples = 0, ring_count = 0;
     int64_t coarse_steps = 0, finest_steps = 0;
     int threads = 256, tile = 0;
@@ -50,6 +60,8 @@ struct lbm_grid {
     int xcd_group = 1;              // tiles per XCD run of the collide kernels
     size_t device_bytes = 0;
     std::vector<void *> allocs;
+    void *bound = nullptr;          // caller-owned memory holding the populations (lbm_bind_memory)
+    size_t bound_bytes = 0;
     unsigned long long *d_ring_pos = nullptr;  // device copy of ring_count (slot of the next sample)
     // synthetic turbulent inflow (coarsest level's inlet)
     bool turb = false;

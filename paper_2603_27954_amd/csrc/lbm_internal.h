@@ -75,6 +75,19 @@ struct LinkArgs {
     float *lforce;            // 3 per link when sampling, else null
 };
 
+// Arguments of the wall-friction kernel (finest level): one surface element
+// per axis face between a fluid cell and a solid neighbour.
+struct FricArgs {
+    const uint32_t *a0;       // element address of the fluid cell x_f
+    const uint32_t *a1;       // element address of x_f - e_k (FRIC_NO_UP: none)
+    const float *q;           // wall distance along e_k
+    const float4 *nw;         // outward body normal at the wall point (x, y, z) and the weight |n_k|
+    int n;
+    float om1;                // shear rate of the finest level
+    float *force;             // 3 per element: the element's friction force
+};
+constexpr uint32_t FRIC_NO_UP = 0xFFFFFFFFu;
+
 // One phase of a coarse step run as a single persistent launch: the work
 // items of what would otherwise be one kernel launch, followed by a grid-wide
 // barrier.  The host records the phases in the order the per-phase launches
@@ -170,6 +183,9 @@ hipError_t launch_fill_sink_and_all(int storage, void *pop, size_t dir_elems, hi
 hipError_t launch_branch_reduce(const float *lforce, const int *pstart, int npieces, const int *segp, int nseg,
                                 double *piece_sum, double *sample, double *acc_branch, double *acc_total,
                                 double *ring, unsigned long long *ring_pos, unsigned *counter, hipStream_t s);
+// friction force of every surface element from the level's pre-collision
+// state for its next step (odd: that step's parity)
+hipError_t launch_friction(int B, int storage, int odd, const CollideArgs &a, const FricArgs &f, hipStream_t s);
 // element addresses (dense: x + nx (y + ny z); blocks: block * B^3 + local)
 hipError_t launch_gather(int B, int storage, int odd, const CollideArgs &a, const uint32_t *cells,
                          int n, double *out_f, size_t out_stride, hipStream_t s);

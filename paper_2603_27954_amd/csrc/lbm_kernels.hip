@@ -157,6 +157,84 @@ hipError_t launch_branch_reduce(const float *lforce, const int *pstart, int npie
 }
 
 // ---------------------------------------------------------------------------
+// wall friction (paper Sec. 3, Eq. (8)): shear stress integrated over the
+// tree surface, one axis face between a fluid cell and a solid neighbour per
+// thread
+// ---------------------------------------------------------------------------
+
+// deviatoric viscous stress -(1 - omega1/2) dev(N) of a cell's non-equilibrium
+// second-order central moments N (xx, yy, zz, xy, xz, yz)
+__device__ __forceinline__ void cell_stress(const Moments &m, float om1, float (&s)[6])
+{
+    const float c = -(1.0f - 0.5f * om1);
+    const float t3 = (m.nxx + m.nyy + m.nzz) * (1.0f / 3.0f);
+    s[0] = c * (m.nxx - t3);
+    s[1] = c * (m.nyy - t3);
+    s[2] = c * (m.nzz - t3);
+    s[3] = c * m.nxy;
+    s[4] = c * m.nxz;
+    s[5] = c * m.nyz;
+}
+
+// The stress at the wall point x_f + q e_k (linear along the axis from x_f
+// and x_f - e_k, or that of x_f alone when x_f - e_k is not fluid), its
+// traction on the body's outward normal n with the normal part removed (the
+// wall shear stress), times the face's share |n_k| of the surface.
+template <int B, typename S, bool ODD>
+__global__ void __launch_bounds__(256) k_friction(const CollideArgs a, const FricArgs f)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= f.n)
+        return;
+    float g[NQ], s[6];
+    load_pre<B, S, ODD>(a, f.a0[t], g);
+    cell_stress(forward_moments(g), f.om1, s);
+    const uint32_t a1 = f.a1[t];
+    if (a1 != FRIC_NO_UP) {
+        float s1[6];
+        load_pre<B, S, ODD>(a, a1, g);
+        cell_stress(forward_moments(g), f.om1, s1);
+        const float q = f.q[t];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            s[k] = fmaf(q, s[k] - s1[k], s[k]);
+    }
+    const float4 nw = f.nw[t];
+    const float tx = s[0] * nw.x + s[3] * nw.y + s[4] * nw.z;
+    const float ty = s[3] * nw.x + s[1] * nw.y + s[5] * nw.z;
+    const float tz = s[4] * nw.x + s[5] * nw.y + s[2] * nw.z;
+    const float tn = tx * nw.x + ty * nw.y + tz * nw.z;
+    f.force[3 * (size_t)t + 0] = nw.w * (tx - tn * nw.x);
+    f.force[3 * (size_t)t + 1] = nw.w * (ty - tn * nw.y);
+    f.force[3 * (size_t)t + 2] = nw.w * (tz - tn * nw.z);
+}
+
+template <int B, typename S>
+static hipError_t launch_friction_t(int odd, const CollideArgs &a, const FricArgs &f, hipStream_t s)
+{
+    const dim3 grid((f.n + 255) / 256), blk(256);
+    if (odd)
+        hipLaunchKernelGGL((k_friction<B, S, true>), grid, blk, 0, s, a, f);
+    else
+        hipLaunchKernelGGL((k_friction<B, S, false>), grid, blk, 0, s, a, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_friction(int B, int storage, int odd, const CollideArgs &a, const FricArgs &f, hipStream_t s)
+{
+    if (f.n == 0)
+        return hipSuccess;
+    if (B == 16) {
+        if (storage == 0) return launch_friction_t<16, float>(odd, a, f, s);
+        if (storage == 1) return launch_friction_t<16, __half>(odd, a, f, s);
+        return launch_friction_t<16, __hip_bfloat16>(odd, a, f, s);
+    }
+    if (storage == 0) return launch_friction_t<8, float>(odd, a, f, s);
+    if (storage == 1) return launch_friction_t<8, __half>(odd, a, f, s);
+    return launch_friction_t<8, __hip_bfloat16>(odd, a, f, s);
+}
+
+// ---------------------------------------------------------------------------
 // state transfer: pre-collision populations of listed cells (FP64, full f)
 // ---------------------------------------------------------------------------
 

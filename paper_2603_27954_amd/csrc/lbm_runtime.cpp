@@ -71,6 +71,28 @@ static lbm_status upload(lbm_grid *g, T **p, const std::vector<T> &h)
 
 static size_t storage_bytes(int storage) { return storage == LBM_FP32 ? 4 : 2; }
 
+// Elements per direction array of a level.  A dense level's arrays end in
+// DENSE_SINK spare elements, where the odd step stores the populations that
+// leave through the box faces.  The distance between the direction arrays
+// changes how the 27 streams of a step spread over the HBM channels; measured
+// on the uniform 512x256x256 grid, FP32 runs fastest with a power-of-two
+// distance and FP16/BF16 with a multiple of DENSE_ALIGN elements.
+static size_t level_dir_elems(const DevLevel &v, int B, int storage)
+{
+    if (!v.dense)
+        return (size_t)(v.nb + 1) * B * B * B;
+    const size_t need = (size_t)v.nx * v.ny * v.nz + DENSE_SINK;
+    size_t p2 = 1;
+    while (p2 < need)
+        p2 <<= 1;
+    if (storage == 0 && p2 <= (size_t)UINT32_MAX / 2)
+        return p2;
+    return (need + DENSE_ALIGN - 1) / DENSE_ALIGN * DENSE_ALIGN;
+}
+
+// bytes one level's populations take in bound memory (256-byte aligned)
+static size_t bound_share(size_t bytes) { return (bytes + 255) / 256 * 256; }
+
 static int nu_to_level_omega(double nu_f, int L, int l, double *om)
 {
     const double nu = nu_f / double(1 << (L - 1 - l));
@@ -256,8 +278,112 @@ static lbm_status finest_links(lbm_grid *g, int odd_done)
             }
             g->ring_count++;
         }
+        if (g->n_fric > 0) {
+            // wall friction from the state the links just completed: the
+            // pre-collision populations of the finest level's next step
+            if (g->rec)
+                return fail(g, LBM_E_INVALID, "wall friction is not available in the persistent form");
+            const int L1 = g->L - 1;
+            FricArgs f{};
+            f.a0 = g->d_fa0;
+            f.a1 = g->d_fa1;
+            f.q = g->d_fq;
+            f.nw = g->d_fnw;
+            f.n = g->n_fric;
+            f.om1 = (float)g->lv[L1].om1;
+            f.force = g->d_fforce;
+            HIPX(g, launch_friction(g->B, g->d.storage, (int)(g->lv[L1].steps & 1), collide_args(g, L1), f,
+                                    g->stream));
+            HIPX(g, launch_branch_reduce(g->d_fforce, g->d_fpstart, g->fric_npieces, g->d_fsegp, g->nseg,
+                                         g->d_fpiece_sum, nullptr, g->d_facc_branch, g->d_facc_total, nullptr,
+                                         nullptr, g->d_fcounter, g->stream));
+        }
         g->samples++;
     }
+    return LBM_OK;
+}
+
+// Surface elements of the wall friction: every axis face between a fluid cell
+// x_f and a solid neighbour x_f + e_k (the links in the six axis directions),
+// with the wall point x_f + q e_k, the branch's outward normal there and the
+// face's weight |n_k|, and x_f - e_k when it is a fluid cell of a leaf block of
+// the finest level (else the stress of x_f alone is used).  Sorted by branch
+// and cut into pieces of at most LINK_PIECE for the FP64 reduction.
+static lbm_status build_friction(lbm_grid *g)
+{
+    const lbm_grid_desc &d = g->d;
+    const DevLevel &fv = g->lv[g->L - 1];
+    const int n_b = (int)g->branches.size();
+    struct Face {
+        uint32_t a0, a1;
+        float q;
+        float4 nw;
+        int branch;
+    };
+    std::vector<Face> faces;
+    auto leaf_fluid = [&](int x, int y, int z) -> int64_t {
+        if (x < 0 || x >= d.nx || y < 0 || y >= d.ny || z < 0 || z >= d.nz)
+            return -1;
+        if (g->solid[(size_t)x + (size_t)d.nx * ((size_t)y + (size_t)d.ny * z)])
+            return -1;
+        if (!fv.dense && fv.h_map[(size_t)(x / g->B) + (size_t)fv.nbx * ((size_t)(y / g->B) +
+                                                                         (size_t)fv.nby * (z / g->B))] != 1)
+            return -1;
+        return level_cell_address(fv, g->B, x, y, z);
+    };
+    for (const HostLink &Lk : g->links) {
+        const int i = Lk.dir, cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+        if (std::abs(cx) + std::abs(cy) + std::abs(cz) != 1 || Lk.branch < 0)
+            continue;
+        const int x = (int)(Lk.cell % d.nx), y = (int)((Lk.cell / d.nx) % d.ny),
+                  z = (int)(Lk.cell / ((int64_t)d.nx * d.ny));
+        const int64_t a0 = level_cell_address(fv, g->B, x, y, z);
+        if (a0 < 0)
+            return fail(g, LBM_E_INVALID, "friction surface cell outside the finest level");
+        const int64_t a1 = leaf_fluid(x - cx, y - cy, z - cz);
+        const double xw[3] = {x + 0.5 + Lk.q * cx, y + 0.5 + Lk.q * cy, z + 0.5 + Lk.q * cz};
+        double n[3];
+        branch_wall_normal(g->branches[(size_t)Lk.branch], xw, n);
+        const double w = std::fabs(cx != 0 ? n[0] : cy != 0 ? n[1] : n[2]);
+        faces.push_back({(uint32_t)a0, a1 < 0 ? FRIC_NO_UP : (uint32_t)a1, (float)Lk.q,
+                         make_float4((float)n[0], (float)n[1], (float)n[2], (float)w), Lk.branch});
+    }
+    std::stable_sort(faces.begin(), faces.end(), [](const Face &a, const Face &b) { return a.branch < b.branch; });
+    const int nf = (int)faces.size();
+    std::vector<uint32_t> a0(nf), a1(nf);
+    std::vector<float> q(nf);
+    std::vector<float4> nw(nf);
+    std::vector<int> seg(g->nseg + 1, 0);
+    for (int t = 0; t < nf; ++t) {
+        a0[t] = faces[t].a0;
+        a1[t] = faces[t].a1;
+        q[t] = faces[t].q;
+        nw[t] = faces[t].nw;
+        seg[faces[t].branch + 1]++;
+    }
+    for (int s2 = 0; s2 < g->nseg; ++s2)
+        seg[s2 + 1] += seg[s2];
+    std::vector<int> pstart(1, 0), segp(g->nseg + 1, 0);
+    for (int s2 = 0; s2 < g->nseg; ++s2) {
+        for (int l = seg[s2]; l < seg[s2 + 1]; l += LINK_PIECE)
+            pstart.push_back(std::min(l + LINK_PIECE, seg[s2 + 1]));
+        segp[s2 + 1] = (int)pstart.size() - 1;
+    }
+    (void)n_b;
+    g->n_fric = nf;
+    g->fric_npieces = (int)pstart.size() - 1;
+    lbm_status st;
+    if ((st = upload(g, &g->d_fa0, a0)) != LBM_OK || (st = upload(g, &g->d_fa1, a1)) != LBM_OK ||
+        (st = upload(g, &g->d_fq, q)) != LBM_OK || (st = upload(g, &g->d_fnw, nw)) != LBM_OK ||
+        (st = upload(g, &g->d_fpstart, pstart)) != LBM_OK || (st = upload(g, &g->d_fsegp, segp)) != LBM_OK ||
+        (st = dalloc(g, &g->d_fforce, (size_t)3 * std::max(nf, 1))) != LBM_OK ||
+        (st = dalloc(g, &g->d_fpiece_sum, (size_t)3 * std::max(g->fric_npieces, 1))) != LBM_OK ||
+        (st = dalloc(g, &g->d_facc_branch, (size_t)3 * g->nseg)) != LBM_OK ||
+        (st = dalloc(g, &g->d_facc_total, 3)) != LBM_OK || (st = dalloc(g, &g->d_fcounter, 1)) != LBM_OK)
+        return st;
+    HIPX(g, hipMemsetAsync(g->d_facc_branch, 0, sizeof(double) * 3 * g->nseg, g->stream));
+    HIPX(g, hipMemsetAsync(g->d_facc_total, 0, sizeof(double) * 3, g->stream));
+    HIPX(g, hipMemsetAsync(g->d_fcounter, 0, sizeof(unsigned), g->stream));
     return LBM_OK;
 }
 
@@ -833,32 +959,27 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
 
     // device buffers of the levels
     const size_t eb = storage_bytes(d.storage);
+    size_t need_bound = 0;
+    for (int l = 0; l < g->L; ++l) {
+        g->lv[l].dir_elems = level_dir_elems(g->lv[l], g->B, d.storage);
+        need_bound += bound_share(g->lv[l].dir_elems * 27 * eb);
+    }
+    if (g->bound && need_bound > g->bound_bytes)
+        return fail(g, LBM_E_INVALID, "bound memory too small: the populations need " + std::to_string(need_bound) +
+                                          " bytes (lbm_plan_levels pop_bytes)");
+    size_t bound_off = 0;
     for (int l = 0; l < g->L; ++l) {
         DevLevel &v = g->lv[l];
-        const size_t cells = (size_t)g->B * g->B * g->B;
-        // a dense level's arrays end in DENSE_SINK spare elements, where the
-        // odd step stores the populations that leave through the box faces.
-        // The distance between the direction arrays changes how the 27 streams
-        // of a step spread over the HBM channels; measured on the uniform
-        // 512x256x256 grid, FP32 runs fastest with a power-of-two distance and
-        // FP16/BF16 with a multiple of DENSE_ALIGN elements.
-        if (v.dense) {
-            const size_t need = (size_t)v.nx * v.ny * v.nz + DENSE_SINK;
-            size_t p2 = 1;
-            while (p2 < need)
-                p2 <<= 1;
-            if (d.storage == 0 && p2 <= (size_t)UINT32_MAX / 2)
-                v.dir_elems = p2;
-            else
-                v.dir_elems = (need + DENSE_ALIGN - 1) / DENSE_ALIGN * DENSE_ALIGN;
-        } else {
-            v.dir_elems = (size_t)(v.nb + 1) * cells;
-        }
         if (v.dir_elems > (size_t)UINT32_MAX / 2)
             return fail(g, LBM_E_INVALID, "level too large for 32-bit cell addressing");
         char *pop = nullptr;
-        if ((st = dalloc(g, &pop, v.dir_elems * 27 * eb)) != LBM_OK)
+        if (g->bound) {
+            // populations of every level carved from the caller's buffer
+            pop = (char *)g->bound + bound_off;
+            bound_off += bound_share(v.dir_elems * 27 * eb);
+        } else if ((st = dalloc(g, &pop, v.dir_elems * 27 * eb)) != LBM_OK) {
             return st;
+        }
         v.pop = pop;
         if (v.dense && v.h_nbr.empty())
             v.h_nbr.assign(27, 0);
@@ -967,6 +1088,10 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
         HIPX(g, hipMemsetAsync(g->d_counter, 0, sizeof(unsigned), g->stream));
         HIPX(g, hipMemsetAsync(g->d_ring_pos, 0, sizeof(unsigned long long), g->stream));
     }
+    if (g->d.flags & LBM_F_FRICTION) {
+        if ((st = build_friction(g)) != LBM_OK)
+            return st;
+    }
     if (g->d.turb_intensity > 0.0) {
         InflowModes m;
         const double d0 = (double)(1 << (g->L - 1));
@@ -1008,6 +1133,25 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
     g->state = 1;
     if (device_bytes_out)
         *device_bytes_out = g->device_bytes;
+    return LBM_OK;
+}
+
+lbm_status lbm_bind_memory(lbm_grid *g, void *device_ptr, size_t bytes)
+{
+    if (!g || !device_ptr || bytes == 0)
+        return fail(g, LBM_E_INVALID, "null argument");
+    if (g->state != 0)
+        return fail(g, LBM_E_STATE, "bind memory before lbm_set_geometry");
+    if ((uintptr_t)device_ptr % 256 != 0)
+        return fail(g, LBM_E_INVALID, "bound memory must be 256-byte aligned");
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, device_ptr) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+        attr.device != g->d.device) {
+        (void)hipGetLastError();
+        return fail(g, LBM_E_INVALID, "bound memory must be device memory of the grid's device");
+    }
+    g->bound = device_ptr;
+    g->bound_bytes = bytes;
     return LBM_OK;
 }
 
@@ -1059,10 +1203,17 @@ lbm_status lbm_mass(lbm_grid *g, double *mass)
 
 lbm_status lbm_drag(lbm_grid *g, lbm_drag_result *out, double *per_branch)
 {
+    return lbm_drag_split(g, out, per_branch, nullptr);
+}
+
+lbm_status lbm_drag_split(lbm_grid *g, lbm_drag_result *out, double *per_branch, double *per_branch_friction)
+{
     if (!g || !out)
         return fail(g, LBM_E_INVALID, "null argument");
     if (g->state != 1)
         return fail(g, LBM_E_STATE, "set_geometry first");
+    if (per_branch_friction && !(g->d.flags & LBM_F_FRICTION))
+        return fail(g, LBM_E_STATE, "friction is sampled only with LBM_F_FRICTION");
     if (lbm_status ps = check_persistent(g); ps != LBM_OK)
         return ps;
     std::memset(out, 0, sizeof *out);
@@ -1074,18 +1225,38 @@ lbm_status lbm_drag(lbm_grid *g, lbm_drag_result *out, double *per_branch)
     HIPX(g, hipStreamSynchronize(g->stream));
     HIPX(g, hipMemsetAsync(g->d_acc_branch, 0, sizeof(double) * acc.size(), g->stream));
     HIPX(g, hipMemsetAsync(g->d_acc_total, 0, sizeof tot, g->stream));
+    std::vector<double> facc;
+    double ftot[3] = {0, 0, 0};
+    if (g->d_facc_total) {
+        facc.assign(3 * (size_t)g->nseg, 0.0);
+        HIPX(g, hipMemcpyAsync(facc.data(), g->d_facc_branch, sizeof(double) * facc.size(), hipMemcpyDeviceToHost,
+                               g->stream));
+        HIPX(g, hipMemcpyAsync(ftot, g->d_facc_total, sizeof ftot, hipMemcpyDeviceToHost, g->stream));
+        HIPX(g, hipStreamSynchronize(g->stream));
+        HIPX(g, hipMemsetAsync(g->d_facc_branch, 0, sizeof(double) * facc.size(), g->stream));
+        HIPX(g, hipMemsetAsync(g->d_facc_total, 0, sizeof ftot, g->stream));
+    }
     const double ns = (double)std::max<int64_t>(g->samples, 1);
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a) {
         out->force[a] = tot[a] / ns;
+        out->friction[a] = ftot[a] / ns;
+    }
     if (per_branch)
         for (int i = 0; i < nb; ++i)
             for (int a = 0; a < 3; ++a)
                 per_branch[3 * i + a] = acc[3 * i + a] / ns;
+    if (per_branch_friction)
+        for (int i = 0; i < nb; ++i)
+            for (int a = 0; a < 3; ++a)
+                per_branch_friction[3 * i + a] = facc[3 * i + a] / ns;
     out->samples = g->samples;
     g->samples = 0;
     out->area_x = g->area_x;
     out->height = g->H;
-    out->cd = g->area_x > 0 && g->d.u_in > 0 ? out->force[0] / (0.5 * g->d.u_in * g->d.u_in * g->area_x) : 0.0;
+    const double qa = 0.5 * g->d.u_in * g->d.u_in * g->area_x;
+    out->cd = qa > 0.0 ? out->force[0] / qa : 0.0;
+    out->cf = qa > 0.0 ? out->friction[0] / qa : 0.0;
+    out->cp = out->cd - out->cf;
     out->step = g->coarse_steps;
     return lbm_mass(g, &out->mass);
 }
@@ -1456,8 +1627,7 @@ lbm_status lbm_plan_levels(const lbm_grid_desc *d, const lbm_branch *b, int32_t 
                 out->work_tiles[l] += any;
             }
         }
-        const size_t elems = v.dense ? (size_t)v.nx * v.ny * v.nz : (size_t)(v.nb + 1) * B * B * B;
-        out->pop_bytes += (int64_t)(elems * 27 * eb);
+        out->pop_bytes += (int64_t)bound_share(level_dir_elems(v, B, d->storage) * 27 * eb);
         out->lattice[l][0] = v.nbx;
         out->lattice[l][1] = v.nby;
         out->lattice[l][2] = v.nbz;

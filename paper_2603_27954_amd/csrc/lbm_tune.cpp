@@ -94,6 +94,13 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     // the candidates' runs write force samples into the ring: keep its contents
     std::vector<double> ring(3 * (size_t)RING);
     keep(hipMemcpyAsync(ring.data(), g->d_ring, sizeof(double) * ring.size(), hipMemcpyDeviceToHost, g->stream));
+    std::vector<double> facc(3 * (size_t)g->nseg + 3);
+    if (g->d_facc_total) {
+        keep(hipMemcpyAsync(facc.data(), g->d_facc_branch, sizeof(double) * 3 * g->nseg, hipMemcpyDeviceToHost,
+                            g->stream));
+        keep(hipMemcpyAsync(facc.data() + 3 * g->nseg, g->d_facc_total, sizeof(double) * 3, hipMemcpyDeviceToHost,
+                            g->stream));
+    }
     keep(hipStreamSynchronize(g->stream));
     if (ce != hipSuccess) {  // nothing has been run yet: the grid is unchanged
         free_backup();
@@ -188,6 +195,12 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     keep(hipMemcpyAsync(g->d_acc_total, acc.data() + 3 * g->nseg, sizeof(double) * 3, hipMemcpyHostToDevice,
                         g->stream));
     keep(hipMemcpyAsync(g->d_ring, ring.data(), sizeof(double) * ring.size(), hipMemcpyHostToDevice, g->stream));
+    if (g->d_facc_total) {
+        keep(hipMemcpyAsync(g->d_facc_branch, facc.data(), sizeof(double) * 3 * g->nseg, hipMemcpyHostToDevice,
+                            g->stream));
+        keep(hipMemcpyAsync(g->d_facc_total, facc.data() + 3 * g->nseg, sizeof(double) * 3, hipMemcpyHostToDevice,
+                            g->stream));
+    }
     keep(hipStreamSynchronize(g->stream));
     free_backup();
     if (ce != hipSuccess && st == LBM_OK)

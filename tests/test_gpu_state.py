@@ -103,3 +103,45 @@ def test_unstable_state_is_reported(gpu, poison):
         g.drag()
     assert e.value.status == gpu.LBM_E_UNSTABLE
     g.close()
+
+
+@pytest.mark.parametrize("name", ["uniform_fp32", "two_level_fp32", "uniform_fp16"])
+def test_bound_memory_holds_the_populations(gpu, name):
+    """Populations in a caller-owned torch tensor (lbm_bind_memory): the run is
+    bit for bit the run in library memory, the tensor is where the state lives,
+    and a tensor shorter than lbm_plan_levels' pop_bytes is refused."""
+    import torch
+    print(f"[bind memory] {name}", flush=True)
+    c = CASES[name]
+    tree = O.build_tree(O.cfg1_tree_params(), 0.0, list(c["com"]))
+    nx, ny, nz = c["box"]
+    plan = gpu.plan_levels(tree, refine=c["refine"], nx=nx, ny=ny, nz=nz, u_in=U, re_h=100.0, block_edge=c["B"],
+                           levels=c["L"], storage=c["storage"])
+    buf = torch.zeros(plan["pop_bytes"], dtype=torch.uint8, device="cuda")
+    a = gpu.Grid(*c["box"], u_in=U, re_h=100.0, block_edge=c["B"], levels=c["L"], storage=c["storage"],
+                 drag_every=1)
+    a.bind_memory(buf)
+    a.set_geometry(tree, refine=c["refine"])
+    ref = _grid(gpu, c, tree)
+    assert a.info()["device_bytes"] < ref.info()["device_bytes"]
+    a.step(4)
+    ref.step(4)
+    torch.cuda.synchronize()
+    before = buf.clone()
+    a.step(1)
+    ref.step(1)
+    torch.cuda.synchronize()
+    assert not torch.equal(before, buf)  # the step wrote the tensor
+    for l in range(c["L"]):
+        fa, fr = a.get_populations(l), ref.get_populations(l)
+        assert np.array_equal(fa, fr, equal_nan=True), f"level {l}"
+    assert np.array_equal(a.drag()["force"], ref.drag()["force"])
+    a.close()
+    ref.close()
+    short = torch.zeros(plan["pop_bytes"] - 256, dtype=torch.uint8, device="cuda")
+    b = gpu.Grid(*c["box"], u_in=U, re_h=100.0, block_edge=c["B"], levels=c["L"], storage=c["storage"])
+    b.bind_memory(short)
+    with pytest.raises(gpu.LbmError) as e:
+        b.set_geometry(tree, refine=c["refine"])
+    assert e.value.status == gpu.LBM_E_INVALID
+    b.close()
