@@ -51,7 +51,7 @@ class _Params(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("periodic_x", C.c_int),
                 ("omega1", C.c_double), ("omega2", C.c_double), ("omega_high", C.c_double),
                 ("galilean", C.c_int), ("u_in", C.c_double), ("force", C.c_double * 3),
-                ("inlet_u", _dp)]
+                ("inlet_u", _dp), ("lateral_inflow", C.c_int)]
 
 
 def lib():
@@ -249,7 +249,8 @@ class UniformSim:
     """Two-array FP64 stepping of the whole box (collide, then pull-stream)."""
 
     def __init__(self, nx, ny, nz, omega1, u_in=0.0, solid=None, link=None, n_branch=0,
-                 omega2=1.0, omega_high=1.0, galilean=True, periodic_x=False, force=(0.0, 0.0, 0.0)):
+                 omega2=1.0, omega_high=1.0, galilean=True, periodic_x=False, force=(0.0, 0.0, 0.0),
+                 lateral_inflow=False):
         self.nx, self.ny, self.nz = nx, ny, nz
         self.N = nx * ny * nz
         self.p = _Params()
@@ -261,6 +262,7 @@ class UniformSim:
         for a in range(3):
             self.p.force[a] = force[a]
         self.p.inlet_u = None
+        self.p.lateral_inflow = int(lateral_inflow)
         self.force = np.array(force, dtype=np.float64)
         self.solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
         if link is None:

@@ -284,6 +284,8 @@ typedef struct {
     double u_in;           /* inlet speed along +x */
     double force[3];       /* body force per cell (tests only) */
     const double *inlet_u; /* optional: velocity fluctuation of the inlet ghost plane, 3*ny*nz, or NULL */
+    int lateral_inflow;    /* 1: the y and z faces are inflow faces (ghosts hold f_eq(1, u_in e_x),
+                              Sec. 2.3); 0: periodic in y and z */
 } or_params;
 
 static inline int64_t cidx(const or_params *p, int x, int y, int z)
@@ -381,7 +383,15 @@ int or_step(const or_params *p, const double *f_in, double *f_out, const uint8_t
                     double val;
                     if (p->periodic_x)
                         sx = wrap(sx, nx);
-                    if (sx < 0) {
+                    const int lat = p->lateral_inflow && (y - cyof(i) < 0 || y - cyof(i) >= ny ||
+                                                          z - czof(i) < 0 || z - czof(i) >= nz);
+                    if (lat) {
+                        /* a lateral or vertical inflow face: the ghost holds the
+                         * equilibrium of the undisturbed inflow */
+                        double ug[3] = {p->u_in, 0.0, 0.0}, feq[Q];
+                        or_equilibrium(1.0, ug, feq);
+                        val = feq[i];
+                    } else if (sx < 0) {
                         double ug[3] = {p->u_in, 0.0, 0.0}, feq[Q];
                         if (p->inlet_u) {
                             const double *du = p->inlet_u + 3 * ((int64_t)sy + (int64_t)ny * sz);

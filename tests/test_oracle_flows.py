@@ -200,15 +200,17 @@ def test_cfg1_mirror_symmetry():
     assert sim.last_force[0] > 0
 
 
-def test_one_step_streams_collided_states_and_applies_the_box_faces():
+@pytest.mark.parametrize("lateral", [False, True])
+def test_one_step_streams_collided_states_and_applies_the_box_faces(lateral):
     """One step from a random state is the pull of each cell's own collision
-    (paper Sec. 2.2): f_i(x, t+1) = f*_i(x - c_i, t), periodic in y and z.  At
-    the inlet the pulled value is the equilibrium ghost f_eq(1, U); at the
-    outlet it is the zero-gradient ghost, a copy of the collided plane
-    x = nx - 1 at the ghost's (y, z) (Sec. 2.3)."""
+    (paper Sec. 2.2): f_i(x, t+1) = f*_i(x - c_i, t), periodic in y and z or,
+    with inflow-type lateral faces, f_eq(1, U) wherever x - c_i leaves the box
+    in y or z.  At the inlet the pulled value is the equilibrium ghost
+    f_eq(1, U); at the outlet it is the zero-gradient ghost, a copy of the
+    collided plane x = nx - 1 at the ghost's (y, z) (Sec. 2.3)."""
     nx, ny, nz, U = 7, 5, 4, 0.05
     rng = np.random.default_rng(17)
-    sim = O.UniformSim(nx, ny, nz, 1.7, u_in=U)
+    sim = O.UniformSim(nx, ny, nz, 1.7, u_in=U, lateral_inflow=lateral)
     for c in range(nx * ny * nz):
         f = O.equilibrium(1 + 0.01 * rng.standard_normal(), [U, 0, 0] + 0.02 * rng.standard_normal(3))
         sim.f[:, c] = f * (1 + 0.02 * rng.standard_normal(27))
@@ -223,10 +225,23 @@ def test_one_step_streams_collided_states_and_applies_the_box_faces():
             for y in range(ny):
                 for x in range(nx):
                     sx, sy, sz = x - cx, (y - cy) % ny, (z - cz) % nz
-                    if sx < 0:
+                    outside_yz = not (0 <= y - cy < ny and 0 <= z - cz < nz)
+                    if lateral and outside_yz:
+                        want = feq[i]
+                    elif sx < 0:
                         want = feq[i]
                     elif sx >= nx:
                         want = post[i, sz, sy, nx - 1]
                     else:
                         want = post[i, sz, sy, sx]
                     assert abs(new[i, z, y, x] - want) < 1e-15, (i, x, y, z)
+
+
+def test_uniform_inflow_stays_uniform_with_lateral_inflow_faces():
+    """With inflow faces on every side but the outlet, the undisturbed inflow
+    f_eq(1, U) is a fixed point of the step (no body)."""
+    nx, ny, nz, U = 12, 8, 6, 0.05
+    sim = O.UniformSim(nx, ny, nz, 1.9, u_in=U, lateral_inflow=True)
+    sim.step(5)
+    feq = O.equilibrium(1.0, [U, 0.0, 0.0])
+    assert np.abs(sim.f - feq[:, None]).max() < 1e-15
