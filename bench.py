@@ -31,6 +31,8 @@ HBM_PEAK_GBS = 8000.0
 STREAM = None
 TUNE = True
 TUNE_CACHE = None  # file of tuned launch shapes shared by runs (None: tune afresh)
+SURROGATE_DUMP = None  # .npz path for the surrogate's training samples and held-out runs (None: not kept)
+SURROGATE_TRAIN = dict(epochs=40, batch=256, lr=2e-3)
 NX, NY, NZ, H = 512, 256, 256, 128.0
 RE_H, U_IN = 2500.0, 0.05
 
@@ -39,11 +41,16 @@ KERNEL_SOURCES = ("paper_2603_27954_amd/csrc/lbm_kernels.hip", "paper_2603_27954
                   "paper_2603_27954_amd/csrc/lbm_access.h", "paper_2603_27954_amd/csrc/lbm_device.h")
 
 
-def measured_traffic():
-    """HBM bytes per FP32 collide launch from the committed rocprofv3 counter
-    summary, or None when the kernel sources changed since it was taken."""
+TRAFFIC_FILES = {"fp32": "profiles/k_collide_dense_uniform512x256x256_hbm_counters.txt",
+                 "fp16": "profiles/k_collide_dense_fp16_uniform512x256x256_hbm_counters.txt"}
+
+
+def measured_traffic(storage="fp32"):
+    """HBM bytes per collide launch from the committed rocprofv3 counter
+    summary of that storage format, or None when the kernel sources changed
+    since it was taken."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "k_collide_dense_uniform512x256x256_hbm_counters.txt")
+    prof = os.path.join(ROOT, TRAFFIC_FILES[storage])
     if not os.path.exists(prof):
         return None
     vals = {}
@@ -338,27 +345,48 @@ def surrogate_leg(lt, torch, n_trees, chunk=1 << 17, scale="small"):
     t0 = time.time()
     sw = SURROGATE_SWEEPS[scale]
 
+    unstable = []
+
     def runs(seeds_by_order):
         out = []
         for order, seeds in seeds_by_order.items():
             for re_h in sw["re_h"]:
                 for iu in (0.0, 0.08):
                     for seed in seeds:
-                        r = S.lbm_samples(order, seed, re_h, iu, stream=stream.cuda_stream)
+                        try:
+                            r = S.lbm_samples(order, seed, re_h, iu, stream=stream.cuda_stream)
+                        except lt.LbmError as e:  # a run that went unstable gives no samples
+                            if e.status != lt.LBM_E_UNSTABLE:
+                                raise
+                            unstable.append((order, seed, re_h, iu))
+                            continue
                         r.update(order=order, re_h=re_h, iu=iu, seed=seed)
                         out.append(r)
+                        if len(out) % 200 == 0:
+                            print(f"surrogate: {len(out)} LBM runs ({time.time() - t0:.0f} s)", file=sys.stderr,
+                                  flush=True)
         return out
 
     train = runs(sw["train"])
     held = runs(sw["held"])
+    if SURROGATE_DUMP:
+        # the training samples and the held-out runs, for studies of the
+        # training settings without repeating the LBM runs
+        hs = np.cumsum([0] + [len(r["feat"]) for r in held])
+        np.savez(SURROGATE_DUMP, X=np.concatenate([r["feat"] for r in train]),
+                 Y=np.concatenate([r["y"] for r in train]),
+                 h_feat=np.concatenate([r["feat"] for r in held]), h_ld=np.concatenate([r["ld"] for r in held]),
+                 h_start=hs, h_area=np.array([r["area_x"] for r in held]), h_cd=np.array([r["cd"] for r in held]),
+                 h_re=np.array([r["re_h"] for r in held]), h_iu=np.array([r["iu"] for r in held]),
+                 h_order=np.array([r["order"] for r in held]))
     lbm_s = time.time() - t0
     X = np.concatenate([r["feat"] for r in train])
     Y = np.concatenate([r["y"] for r in train])
     m = lt.Mlp(seed=3, stream=stream.cuda_stream)
     m.set_scaling(X.mean(0), np.maximum(X.std(0), 1e-3), Y.mean(), Y.std())
     t1 = time.time()
-    losses = m.train(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), epochs=40, batch=256, lr=2e-3,
-                     seed=17)
+    losses = m.train(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), epochs=SURROGATE_TRAIN["epochs"],
+                     batch=SURROGATE_TRAIN["batch"], lr=SURROGATE_TRAIN["lr"], seed=17)
     train_s = time.time() - t1
     err = np.array([abs(S.tree_cd(m, r["feat"], r["ld"], r["area_x"]) - r["cd"]) / r["cd"] for r in held])
     # the analytic model of Eqs. (2), (4) on the same held-out runs (the
@@ -384,14 +412,15 @@ def surrogate_leg(lt, torch, n_trees, chunk=1 << 17, scale="small"):
     m.close()
     return {
         "training": {"lbm_runs": len(train), "samples": int(len(X)), "lbm_seconds": round(lbm_s, 1),
-                     "epochs": 40, "train_seconds": round(train_s, 2), "final_loss": float(losses[-1]),
+                     "epochs": SURROGATE_TRAIN["epochs"], "batch": SURROGATE_TRAIN["batch"],
+                     "lr": SURROGATE_TRAIN["lr"], "train_seconds": round(train_s, 2), "final_loss": float(losses[-1]),
                      "re_d_envelope": [round(env[0], 2), round(env[1], 1)]},
         "held_out": {"runs": len(held), "cd_rel_err_mean": round(float(np.mean(err)), 4),
                      "cd_rel_err_max": round(float(np.max(err)), 4),
                      "cd_rel_err_p90": round(float(np.quantile(err, 0.9)), 4),
                      "analytic_cd_rel_err_mean": round(float(np.mean(err_a)), 4),
                      "mean_err_by_re_h": by_re},
-        "scale": scale,
+        "scale": scale, "unstable_runs": len(unstable),
         "sweep": sweep,
     }
 
@@ -504,7 +533,23 @@ def cpu_leg(lt, arr, nsteps):
     fluid = int((solid == 0).sum())
     cd = sim.last_force[0] / (0.5 * U_IN ** 2 * ax)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"mlups": fluid * nsteps / dt / 1e6, "seconds": dt, "setup_s": setup, "cores": cores, "cd": cd}
+    del sim
+    # the small 64 x 32 x 32 workload (order-1 tree, Re_H = 100), 100 steps, on
+    # one thread and on all of them
+    b1 = O.build_tree(O.cfg1_tree_params(), 0.0, [16.0, 16.0, 16.0])
+    s1 = O.voxelize(b1, 64, 32, 32)
+    l1 = O.links(b1, s1, 64, 32, 32)
+    nu1 = U_IN * O.tree_height(b1) / 100.0
+    small = {}
+    for threads in (1, cores):
+        O.set_threads(threads)
+        sim1 = O.UniformSim(64, 32, 32, O.omega_from_nu(nu1), u_in=U_IN, solid=s1, link=l1, n_branch=len(b1))
+        t1 = time.time()
+        sim1.step(100)
+        small[threads] = int((s1 == 0).sum()) * 100 / (time.time() - t1) / 1e6
+    O.set_threads(cores)
+    return {"mlups": fluid * nsteps / dt / 1e6, "seconds": dt, "setup_s": setup, "cores": cores, "cd": cd,
+            "small_mlups_1_thread": small[1], "small_mlups_all": small[cores]}
 
 
 def main():
@@ -530,6 +575,10 @@ def main():
     ap.add_argument("--surrogate-trees", type=int, default=1_000_000)
     ap.add_argument("--surrogate-scale", choices=list(SURROGATE_SWEEPS), default="small",
                     help="training sweep of the surrogate (large: about 1e5 samples, several minutes)")
+    ap.add_argument("--surrogate-dump", default=None, help=".npz file for the surrogate's samples and held-out runs")
+    ap.add_argument("--surrogate-epochs", type=int, default=40)
+    ap.add_argument("--surrogate-batch", type=int, default=256)
+    ap.add_argument("--surrogate-lr", type=float, default=2e-3)
     ap.add_argument("--surrogate-only", action="store_true", help="run only the drag-surrogate leg (profiling)")
     ap.add_argument("--sweep-only", action="store_true",
                     help="run only the many-tree sweep with an untrained network (profiling its kernels)")
@@ -558,9 +607,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    global TUNE, TUNE_CACHE
+    global TUNE, TUNE_CACHE, SURROGATE_DUMP
     TUNE = not args.no_tune
     TUNE_CACHE = args.tune_cache
+    SURROGATE_DUMP = args.surrogate_dump
+    SURROGATE_TRAIN.update(epochs=args.surrogate_epochs, batch=args.surrogate_batch, lr=args.surrogate_lr)
     if args.amr_only:
         print(json.dumps({"amr_3level": amr_leg(lt, torch, args.amr_steps, 4)}), flush=True)
         return
@@ -586,22 +637,21 @@ def main():
     if r32 is None:
         r32 = r16
 
-    traffic = measured_traffic()
-
     def roof(r, bytes_per_cell):
         kt = r["kernel"]
         avg_ms = kt["collide_ms"] / max(kt["collide_launches"], 1)
         achieved = bytes_per_cell * r["cells"] / (avg_ms * 1e-3) / 1e9
-        # HBM bytes per launch from the committed counter summary (FP32 only;
-        # null when the kernel sources changed since the counters were taken)
-        tr = traffic if (traffic is not None and bytes_per_cell == 216) else None
+        # HBM bytes per launch from the committed counter summary of this
+        # storage (null when the kernel sources changed since it was taken)
+        st = "fp32" if bytes_per_cell == 216 else "fp16"
+        tr = measured_traffic(st)
         out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
                "kernel": "k_collide_dense (even + odd launches)", "avg_launch_ms": round(avg_ms, 5),
                "bytes_per_cell": bytes_per_cell, "tuned": r["tune"]}
         if tr is not None:
-            out["traffic_vs_algorithmic"] = round(tr / (216 * r["cells"]), 4)
-            out["traffic_source"] = "profiles/k_collide_dense_uniform512x256x256_hbm_counters.txt"
+            out["traffic_vs_algorithmic"] = round(tr / (bytes_per_cell * r["cells"]), 4)
+            out["traffic_source"] = TRAFFIC_FILES[st]
         return out
 
     out = {
@@ -633,7 +683,10 @@ def main():
         out["cpu_baseline"] = {"value": round(c["mlups"], 2), "unit": "MLUPS", "cores": c["cores"],
                                "kind": "oracle",
                                "sample": f"full 512x256x256 workload, {args.cpu_steps} FP64 steps "
-                                         f"({c['seconds']:.1f} s; geometry setup {c['setup_s']:.1f} s untimed)"}
+                                         f"({c['seconds']:.1f} s; geometry setup {c['setup_s']:.1f} s untimed)",
+                               "small_64x32x32_100_steps": {"mlups_1_thread": round(c["small_mlups_1_thread"], 2),
+                                                            f"mlups_{c['cores']}_threads":
+                                                                round(c["small_mlups_all"], 2)}}
         out["cd_error"] = {"steps": args.cpu_steps, "cd_oracle": c["cd"],
                            "fp32_rel": abs(cd32 - c["cd"]) / abs(c["cd"]),
                            "fp16_rel": abs(cd16 - c["cd"]) / abs(c["cd"])}

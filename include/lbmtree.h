@@ -100,7 +100,9 @@ typedef struct {
     double re_h;          /* Re_H = u_in H / nu_finest, H = tree height; used when nu <= 0 */
     double nu;            /* finest-level lattice viscosity; > 0 overrides re_h */
     int32_t storage;      /* lbm_storage */
-    int32_t periodic_yz;  /* must be 1: periodic lateral faces */
+    int32_t periodic_yz;  /* 1: periodic lateral (y) and vertical (z) faces; 0: inflow faces there, ghosts
+                             holding f_eq(1, u_in e_x) (Sec. 2.3: inflow conditions on every boundary but
+                             the outlet) */
     double turb_intensity; /* inlet I_u (0 = uniform inflow); synthesis as lbm_inflow_modes */
     double turb_length;    /* longitudinal integral length of the inflow turbulence, finest cells */
     uint64_t turb_seed;

@@ -87,6 +87,7 @@ def lib():
         L.or_links.restype = C.c_int64
         L.or_links.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_int, _u8p, C.c_int64, _i64p, _i8p,
                                _dp, _i32p]
+        L.or_set_threads.argtypes = [C.c_int]
         L.or_area_x.restype = C.c_int64
         L.or_area_x.argtypes = [_u8p, C.c_int, C.c_int, C.c_int]
         _lib = L
@@ -158,6 +159,11 @@ def collide(f, omega1, omega2=1.0, omega_high=1.0, galilean=True, force=None):
     fr = None if force is None else np.ascontiguousarray(force, dtype=np.float64)
     lib().or_collide(_ptr(f), _ptr(out), omega1, omega2, omega_high, int(galilean), _ptr(fr))
     return out
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops."""
+    lib().or_set_threads(int(n))
 
 
 def omega_from_nu(nu: float) -> float:

@@ -37,6 +37,7 @@
  * cell = x + nx*(y + ny*z).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -48,6 +49,9 @@ static int cyof(int i) { return (i / 3) % 3 - 1; }
 static int czof(int i) { return i / 9 - 1; }
 
 /* lattice weight: product of the 1D weights 1/6, 2/3, 1/6 */
+/* threads of the oracle's parallel loops (for timing it at a given count) */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 double or_weight(int i)
 {
     static const double w1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};

@@ -261,13 +261,14 @@ def collide_cell_host(f, omega1, omega2=1.0, galilean=True):
 # ---- grid --------------------------------------------------------------------
 
 def _make_desc(nx, ny, nz, u_in=0.05, re_h=0.0, nu=0.0, block_edge=16, levels=1, storage="fp32", drag_every=1,
-               flags=0, device=0, stream=None, turb_intensity=0.0, turb_length=0.0, turb_seed=0, turb_modes=0):
+               flags=0, device=0, stream=None, turb_intensity=0.0, turb_length=0.0, turb_seed=0, turb_modes=0,
+               periodic_yz=1):
     d = GridDesc()
     d.nx, d.ny, d.nz = nx, ny, nz
     d.block_edge, d.levels = block_edge, levels
     d.u_in, d.re_h, d.nu = u_in, re_h, nu
     d.storage = STORAGE[storage] if isinstance(storage, str) else storage
-    d.periodic_yz = 1
+    d.periodic_yz = int(periodic_yz)
     d.turb_intensity, d.turb_length, d.turb_seed, d.turb_modes = turb_intensity, turb_length, turb_seed, turb_modes
     d.drag_every, d.flags, d.device = drag_every, flags, device
     d.stream = stream
@@ -504,9 +505,9 @@ class Grid:
 
     def __init__(self, nx, ny, nz, u_in=0.05, re_h=0.0, nu=0.0, block_edge=16, levels=1,
                  storage="fp32", drag_every=1, flags=0, device=0, stream=None,
-                 turb_intensity=0.0, turb_length=0.0, turb_seed=0, turb_modes=0):
+                 turb_intensity=0.0, turb_length=0.0, turb_seed=0, turb_modes=0, periodic_yz=1):
         d = _make_desc(nx, ny, nz, u_in, re_h, nu, block_edge, levels, storage, drag_every, flags, device, stream,
-                       turb_intensity, turb_length, turb_seed, turb_modes)
+                       turb_intensity, turb_length, turb_seed, turb_modes, periodic_yz)
         self.desc = d
         self.h = _P()
         _check(lib().lbm_create_grid(C.byref(d), C.byref(self.h)))

@@ -67,6 +67,15 @@ __device__ __forceinline__ float inlet_dev(const CollideArgs &a, const float *pl
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Inflow-type lateral and vertical faces (Sec. 2.3): a population whose
+// source cell lies outside the box in y or z comes from a ghost holding the
+// undisturbed inflow f_eq(1, u_in e_x); these faces take precedence over the
+// inlet and outlet ghosts at the box's edges.
+__device__ __forceinline__ bool lateral_source(const CollideArgs &a, int ys, int zs)
+{
+    return a.lateral && (ys < 0 || ys >= a.ny || zs < 0 || zs >= a.nz);
+}
+
 // Per-lane neighbour addressing: for an offset s in {-1,0,1} along each axis
 // the local part of the neighbour's cell index and its contribution to the
 // 3x3x3 block-offset code.
@@ -124,7 +133,9 @@ __device__ __forceinline__ void load_pre(const CollideArgs &a, uint32_t elem, fl
         for (int k = 0; k < NQ; ++k) {
             int xs = x + qcx(k);
             const int ys = wrapi(y + qcy(k), ny), zs = wrapi(z + qcz(k), nz);
-            if (a.faces && xs < 0) {
+            if (lateral_source(a, y + qcy(k), z + qcz(k))) {
+                g[qopp(k)] = inlet_dev(a, nullptr, qopp(k), 0, 0);
+            } else if (a.faces && xs < 0) {
                 g[qopp(k)] = inlet_dev(a, a.in_prev, qopp(k), ys, zs);
             } else if (a.faces && xs >= nx) {
                 g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)zs * ny + ys];

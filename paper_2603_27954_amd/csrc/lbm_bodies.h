@@ -81,13 +81,26 @@ __device__ __forceinline__ void dense_odd_rowwave(const CollideArgs &a, uint32_t
                 g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)tz * ny + ty];
         }
     }
+    // inflow-type y and z faces (wave-uniform: the wave is one row)
+    const bool ylo = a.lateral && y == 0, yhi = a.lateral && y == ny - 1;
+    const bool zlo = a.lateral && z == 0, zhi = a.lateral && z == nz - 1;
+    const bool lat = ylo || yhi || zlo || zhi;
+    auto outside = [&](int k) {  // x + c_k leaves the box in y or z
+        return (ylo && qcy(k) == -1) || (yhi && qcy(k) == 1) || (zlo && qcz(k) == -1) || (zhi && qcz(k) == 1);
+    };
+    if (lat) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            if (outside(k))
+                g[qopp(k)] = inlet_dev(a, nullptr, qopp(k), 0, 0);
+    }
     collide_rec(g, a, rec);
     // every lane stores every direction (scalar base, 32-bit lane offset); a
     // population that leaves through a face goes to the spare elements, which
     // nothing reads
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
-        const bool leaves = (at_in && qcx(k) == -1) || (at_out && qcx(k) == 1);
+        const bool leaves = (at_in && qcx(k) == -1) || (at_out && qcx(k) == 1) || outside(k);
         stp<S>(const_cast<S *>(bk[k]), leaves ? sink[k] : vx[qcx(k) + 1], g[k]);
     }
     if (at_in) {
@@ -97,10 +110,20 @@ __device__ __forceinline__ void dense_odd_rowwave(const CollideArgs &a, uint32_t
                 stp<S>(a.pop[i], own, inlet_dev(a, a.in_cur, i, ys[1 - qcy(i)], zs[1 - qcz(i)]));
     }
     if (at_out) {
+        // the outlet ghost's populations land on (nx - 1, y + c_y, z + c_z),
+        // unless that lies outside an inflow-type face
 #pragma unroll
         for (int i = 0; i < NQ; ++i)
-            if (qcx(i) == -1)
+            if (qcx(i) == -1 && !outside(i))
                 stp<S>(a.pop[i], (uint32_t)x + (uint32_t)nx * ((uint32_t)ys[qcy(i) + 1] + (uint32_t)ny * zs[qcz(i) + 1]), g[i]);
+    }
+    if (lat) {
+        // populations entering through an inflow-type face for the next
+        // (even) step; last, so they take precedence at the inlet's edges
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            if (outside(qopp(i)))
+                stp<S>(a.pop[i], own, inlet_dev(a, nullptr, i, 0, 0));
     }
 }
 
@@ -171,10 +194,23 @@ __device__ __forceinline__ void collide_dense_item(const CollideArgs &a, int ite
                 g[qopp(k)] = a.gbuf[qopp(k) * pl + (size_t)tz * ny + ty];
         }
     }
+    // inflow-type y and z faces
+    const bool ylo = a.lateral && y == 0, yhi = a.lateral && y == ny - 1;
+    const bool zlo = a.lateral && z == 0, zhi = a.lateral && z == nz - 1;
+    const bool lat = ylo || yhi || zlo || zhi;
+    auto outside = [&](int k) {  // x + c_k leaves the box in y or z
+        return (ylo && qcy(k) == -1) || (yhi && qcy(k) == 1) || (zlo && qcz(k) == -1) || (zhi && qcz(k) == 1);
+    };
+    if (lat) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            if (outside(k))
+                g[qopp(k)] = inlet_dev(a, nullptr, qopp(k), 0, 0);
+    }
     collide_rec(g, a, rec);
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
-        const bool leaves = (at_in && qcx(k) == -1) || (at_out && qcx(k) == 1);
+        const bool leaves = (at_in && qcx(k) == -1) || (at_out && qcx(k) == 1) || outside(k);
         if (!leaves)
             stp<S>(a.pop[k], addr[k], g[k]);
     }
@@ -187,11 +223,20 @@ __device__ __forceinline__ void collide_dense_item(const CollideArgs &a, int ite
     }
     if (at_out) {
         // the outlet ghost (nx, y, z) copies this cell; its populations with
-        // cx = -1 land on (nx - 1, y + cy, z + cz)
+        // cx = -1 land on (nx - 1, y + cy, z + cz), unless that lies outside
+        // an inflow-type face
 #pragma unroll
         for (int i = 0; i < NQ; ++i)
-            if (qcx(i) == -1)
+            if (qcx(i) == -1 && !outside(i))
                 stp<S>(a.pop[i], (uint32_t)x + (uint32_t)nx * ((uint32_t)ys[qcy(i) + 1] + (uint32_t)ny * zs[qcz(i) + 1]), g[i]);
+    }
+    if (lat) {
+        // populations entering through an inflow-type face for the next
+        // (even) step; last, so they take precedence at the inlet's edges
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            if (outside(qopp(i)))
+                stp<S>(a.pop[i], own, inlet_dev(a, nullptr, i, 0, 0));
     }
 }
 

@@ -49,6 +49,7 @@ struct CollideArgs {
     float om1, om2;
     int galilean;
     int faces;                // 1: this level owns the inlet/outlet planes
+    int lateral;              // 1: its y and z faces are inflow faces (ghosts f_eq(1, u_in e_x)); 0: periodic
     int nbx;                  // blocks along x (face detection)
     int ny, nz;               // level box (transverse) in cells
     float u_in;

@@ -122,6 +122,7 @@ static CollideArgs collide_args(lbm_grid *g, int l)
     a.om2 = 1.0f;
     a.galilean = (g->d.flags & LBM_F_NO_GALILEAN) ? 0 : 1;
     a.faces = l == 0 ? 1 : 0;
+    a.lateral = (l == 0 && g->d.periodic_yz == 0) ? 1 : 0;
     a.nbx = v.nbx;
     a.ny = v.ny;
     a.nz = v.nz;
@@ -799,8 +800,8 @@ static lbm_status check_desc(const lbm_grid_desc *d, std::string *msg)
         return (*msg = "need nu > 0 or re_h > 0", LBM_E_INVALID);
     if (d->storage < 0 || d->storage > 2)
         return (*msg = "storage must be LBM_FP32, LBM_FP16_DEV or LBM_BF16_DEV", LBM_E_INVALID);
-    if (d->periodic_yz != 1)
-        return (*msg = "only periodic lateral faces are supported (periodic_yz = 1)", LBM_E_INVALID);
+    if (d->periodic_yz != 0 && d->periodic_yz != 1)
+        return (*msg = "periodic_yz must be 1 (periodic lateral faces) or 0 (inflow faces)", LBM_E_INVALID);
     if (d->drag_every < 0)
         return (*msg = "drag_every must be >= 1", LBM_E_INVALID);
     if (d->flags & LBM_F_PERSISTENT)

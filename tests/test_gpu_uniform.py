@@ -133,3 +133,35 @@ def test_cfg1_full_run_matches_oracle(gpu, storage):
         # storage noise after 1000 steps; C_D stays within the 5e-3 target
         assert du < 3e-2
         assert rel < 5e-3
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+@pytest.mark.parametrize("nx", [64, 80])
+def test_lateral_inflow_faces_match_oracle(gpu, storage, nx):
+    """Inflow-type lateral and vertical faces (periodic_yz = 0, Sec. 2.3): four
+    steps (both A-A parities) from a seeded random state against the oracle,
+    every fluid cell, populations at the faces and edges included; nx = 80
+    takes the odd step without whole-row wavefronts."""
+    ny, nz = 32, 32
+    b = O.build_tree(O.cfg1_tree_params(), 0.0, [16.0, 16.0, 16.0])
+    print(f"[lateral faces] {storage} nx={nx}", flush=True)
+    nu = 0.05 * O.tree_height(b) / 100.0
+    g = gpu.Grid(nx, ny, nz, u_in=0.05, re_h=100.0, storage=storage, periodic_yz=0, drag_every=1)
+    g.set_geometry(b)
+    solid = O.voxelize(b, nx, ny, nz)
+    lk = O.links(b, solid, nx, ny, nz)
+    f0 = _random_state(nx * ny * nz, solid, seed=77)
+    g.set_populations(f0)
+    sim = O.UniformSim(nx, ny, nz, O.omega_from_nu(nu), u_in=0.05, solid=solid, link=lk, n_branch=len(b),
+                       lateral_inflow=True)
+    sim.f[:] = g.get_populations()
+    fl = solid == 0
+    for step in range(4):
+        g.step(1)
+        sim.step(1)
+        err = np.abs(g.get_populations()[:, fl] - sim.f[:, fl]).max()
+        print(f"  step {step + 1}: max |df| = {err:.3e}", flush=True)
+        assert err < TOL_F[storage] * (step + 1)
+    fo = np.array(sim.last_force)
+    assert np.abs(g.drag_series(1)[0] - fo).max() < TOL_FORCE[storage] * np.abs(fo).max()
+    g.close()
