@@ -185,6 +185,9 @@ def amr_leg(lt, torch, steps, warmup):
         res[mode] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
         g.close()
     res["fp16_vs_fp32_mlups"] = round(res["graph_fp16"]["mlups"] / res["graph"]["mlups"], 3)
+    # the stated aim for the FP32 octree steps is 70 % of HBM peak over the step
+    res["step_hbm_frac_target"] = 0.70
+    res["step_hbm_frac_gap"] = round(0.70 - res["graph"]["step_hbm_frac"], 4)
     return res
 
 

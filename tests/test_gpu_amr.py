@@ -20,6 +20,10 @@ CONFIGS = {
     # their wakes the same way)
     "three_level_b8_wake": dict(L=3, B=8, box=(256, 128, 128), com=(96.0, 64.0, 64.0), band=[0, 2, 0],
                                 wake=[0, 48, 32]),
+    # the paper's own tree (Table 2, n = 4 rewrites: trunk and three child
+    # levels, 15 branches) at H = 64 on 8^3 blocks, with a wake
+    "three_level_b8_paper_n4": dict(L=3, B=8, box=(512, 256, 256), com=(192.0, 128.0, 128.0), band=[0, 4, 0],
+                                    wake=[0, 64, 0], tree="paper_n4", H=64.0),
     # four levels (the smallest box whose refined blocks keep one coarse block
     # from the faces): coarse 64x32x32, finest 512x256x256
     "four_level_b8": dict(L=4, B=8, box=(512, 256, 256), com=(192.0, 128.0, 128.0), band=[0, 4, 2, 0],
@@ -34,7 +38,10 @@ TOL_STEP = {"fp32": 4e-6, "fp16": 3e-5}
 def _setup(gpu, name, storage="fp32", with_body=True):
     c = CONFIGS[name]
     nx, ny, nz = c["box"]
-    b = O.build_tree(O.cfg1_tree_params(), 0.0, list(c["com"]))
+    if c.get("tree") == "paper_n4":
+        b = O.build_tree(O.paper_tree_params(3), c["H"], list(c["com"]))
+    else:
+        b = O.build_tree(O.cfg1_tree_params(), 0.0, list(c["com"]))
     nu = U * O.tree_height(b) / 100.0
     g = gpu.Grid(nx, ny, nz, u_in=U, re_h=100.0, block_edge=c["B"], levels=c["L"], storage=storage, drag_every=1)
     g.set_geometry(b, refine={"band": c["band"], "wake": c["wake"]})
@@ -55,6 +62,7 @@ def test_block_maps_match_oracle(gpu, name):
 
 @pytest.mark.parametrize("name,storage", [("two_level_b8", "fp32"), ("three_level_b8", "fp32"),
                                           ("three_level_b8_wake", "fp32"), ("three_level_b8_wake", "fp16"),
+                                          ("three_level_b8_paper_n4", "fp32"),
                                           ("two_level_b16", "fp32"), ("four_level_b8", "fp32"),
                                           ("three_level_b8", "fp16"), ("four_level_b8", "fp16")])
 def test_coarse_steps_match_oracle(gpu, name, storage):
