@@ -32,7 +32,7 @@ STREAM = None
 TUNE = True
 TUNE_CACHE = None  # file of tuned launch shapes shared by runs (None: tune afresh)
 SURROGATE_DUMP = None  # .npz path for the surrogate's training samples and held-out runs (None: not kept)
-SURROGATE_TRAIN = dict(epochs=40, batch=256, lr=2e-3)
+SURROGATE_TRAIN = {}  # overrides of the scale's training settings (epochs, batch, lr)
 NX, NY, NZ, H = 512, 256, 256, 128.0
 RE_H, U_IN = 2500.0, 0.05
 
@@ -329,10 +329,12 @@ MLP_FLOP = 8960  # 2 x (5 x 64 + 64 x 64 + 64) per inference
 SURROGATE_SWEEPS = {
     "small": dict(re_h=(100.0, 200.0, 400.0, 800.0),
                   train={1: range(1000, 1016), 2: range(1100, 1108), 3: range(1200, 1204)},
-                  held={1: range(1057, 1060), 2: range(1127, 1130), 3: range(1212, 1215)}),
+                  held={1: range(1057, 1060), 2: range(1127, 1130), 3: range(1212, 1215)},
+                  fit=dict(epochs=40, batch=256, lr=2e-3)),
     "large": dict(re_h=(100.0, 300.0, 1000.0, 2500.0, 5000.0, 1.0e4, 2.0e4),
                   train={1: range(2000, 2100), 2: range(3000, 3060), 3: range(4000, 4040), 4: range(5000, 5030)},
-                  held={1: range(9000, 9003), 2: range(9100, 9103), 3: range(9200, 9203), 4: range(9300, 9303)}),
+                  held={1: range(9000, 9003), 2: range(9100, 9103), 3: range(9200, 9203), 4: range(9300, 9303)},
+                  fit=dict(epochs=320, batch=256, lr=2e-3)),
 }
 
 
@@ -347,6 +349,7 @@ def surrogate_leg(lt, torch, n_trees, chunk=1 << 17, scale="small"):
     stream = STREAM
     t0 = time.time()
     sw = SURROGATE_SWEEPS[scale]
+    fit = dict(sw["fit"], **SURROGATE_TRAIN)
 
     unstable = []
 
@@ -388,8 +391,8 @@ def surrogate_leg(lt, torch, n_trees, chunk=1 << 17, scale="small"):
     m = lt.Mlp(seed=3, stream=stream.cuda_stream)
     m.set_scaling(X.mean(0), np.maximum(X.std(0), 1e-3), Y.mean(), Y.std())
     t1 = time.time()
-    losses = m.train(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), epochs=SURROGATE_TRAIN["epochs"],
-                     batch=SURROGATE_TRAIN["batch"], lr=SURROGATE_TRAIN["lr"], seed=17)
+    losses = m.train(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), epochs=fit["epochs"],
+                     batch=fit["batch"], lr=fit["lr"], seed=17)
     train_s = time.time() - t1
     err = np.array([abs(S.tree_cd(m, r["feat"], r["ld"], r["area_x"]) - r["cd"]) / r["cd"] for r in held])
     # the analytic model of Eqs. (2), (4) on the same held-out runs (the
@@ -415,8 +418,8 @@ def surrogate_leg(lt, torch, n_trees, chunk=1 << 17, scale="small"):
     m.close()
     return {
         "training": {"lbm_runs": len(train), "samples": int(len(X)), "lbm_seconds": round(lbm_s, 1),
-                     "epochs": SURROGATE_TRAIN["epochs"], "batch": SURROGATE_TRAIN["batch"],
-                     "lr": SURROGATE_TRAIN["lr"], "train_seconds": round(train_s, 2), "final_loss": float(losses[-1]),
+                     "epochs": fit["epochs"], "batch": fit["batch"],
+                     "lr": fit["lr"], "train_seconds": round(train_s, 2), "final_loss": float(losses[-1]),
                      "re_d_envelope": [round(env[0], 2), round(env[1], 1)]},
         "held_out": {"runs": len(held), "cd_rel_err_mean": round(float(np.mean(err)), 4),
                      "cd_rel_err_max": round(float(np.max(err)), 4),
@@ -579,9 +582,9 @@ def main():
     ap.add_argument("--surrogate-scale", choices=list(SURROGATE_SWEEPS), default="small",
                     help="training sweep of the surrogate (large: about 1e5 samples, several minutes)")
     ap.add_argument("--surrogate-dump", default=None, help=".npz file for the surrogate's samples and held-out runs")
-    ap.add_argument("--surrogate-epochs", type=int, default=40)
-    ap.add_argument("--surrogate-batch", type=int, default=256)
-    ap.add_argument("--surrogate-lr", type=float, default=2e-3)
+    ap.add_argument("--surrogate-epochs", type=int, default=None, help="training epochs (default: the scale's)")
+    ap.add_argument("--surrogate-batch", type=int, default=None, help="training batch (default: the scale's)")
+    ap.add_argument("--surrogate-lr", type=float, default=None, help="Adam rate (default: the scale's)")
     ap.add_argument("--surrogate-only", action="store_true", help="run only the drag-surrogate leg (profiling)")
     ap.add_argument("--sweep-only", action="store_true",
                     help="run only the many-tree sweep with an untrained network (profiling its kernels)")
@@ -614,7 +617,8 @@ def main():
     TUNE = not args.no_tune
     TUNE_CACHE = args.tune_cache
     SURROGATE_DUMP = args.surrogate_dump
-    SURROGATE_TRAIN.update(epochs=args.surrogate_epochs, batch=args.surrogate_batch, lr=args.surrogate_lr)
+    SURROGATE_TRAIN.update({k: v for k, v in (("epochs", args.surrogate_epochs), ("batch", args.surrogate_batch),
+                                              ("lr", args.surrogate_lr)) if v is not None})
     if args.amr_only:
         print(json.dumps({"amr_3level": amr_leg(lt, torch, args.amr_steps, 4)}), flush=True)
         return
