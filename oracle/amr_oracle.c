@@ -49,7 +49,9 @@
  *  Trilinear prolongation of a fine ghost g: coarse parent P = g >> 1 and,
  *  per axis, P + s with s = +1 for an odd fine index and -1 for an even one,
  *  weights 3/4 and 1/4.  Restriction of a band cell X: children 2X + {0,1}^3
- *  (solid children skipped), mean density, mass-weighted velocity, mean D.
+ *  (solid children skipped), mean density, mass-weighted velocity, mean D; a
+ *  band cell with no fluid child lies inside the wall and takes the fluid at
+ *  rest (rho = 1, u = 0, D = 0).
  *
  * Populations: f[l][i * N_l + cell], cell = x + nx_l (y + ny_l z).
  */
@@ -450,11 +452,16 @@ static void restrict_band(or_amr *a, int l)
                         D[k] += t[4 + k];
                     cnt += 1.0;
                 }
-                if (cnt == 0.0)
-                    continue;
-                double v[10] = {rho / cnt, mom[0] / rho, mom[1] / rho, mom[2] / rho};
-                for (int k = 0; k < 6; k++)
-                    v[4 + k] = D[k] / cnt;
+                /* a band cell whose children are all solid lies inside the
+                 * wall: the fluid at rest (rho = 1, u = 0, D = 0) */
+                double v[10] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                if (cnt > 0.0) {
+                    v[0] = rho / cnt;
+                    for (int k = 0; k < 3; k++)
+                        v[1 + k] = mom[k] / rho;
+                    for (int k = 0; k < 6; k++)
+                        v[4 + k] = D[k] / cnt;
+                }
                 double fp[Q];
                 or_cell_rebuild(v, a->omega[l], level_dt(a, l), fp);
                 for (int i = 0; i < Q; i++)

@@ -217,6 +217,36 @@ def test_restriction_reproduces_a_linear_field(rho_slope, u_slope):
     assert np.all(err < 1e-14)
 
 
+def test_restriction_of_a_band_cell_inside_the_wall_is_the_fluid_at_rest():
+    """A band cell whose eight children are all solid lies inside the wall: it
+    takes rho = 1, u = 0, D = 0 (the rest equilibrium), whatever its own and
+    its children's populations held, while its neighbours keep the mean of
+    their fluid children."""
+    b = _tree()
+    nu = _nu(b)
+    om = [O.omega_from_nu(nu / 2), O.omega_from_nu(nu)]
+    base = O.AmrSim(2, B, NX, NY, NZ, U, nu, b, band=[0, 8], wake=[0, 0])
+    s0, s1 = base.shape(0), base.shape(1)
+    bc = np.flatnonzero(base.classes(0) == O.CLS_BAND)
+    inside = bc[::97][:6]
+    solid = np.zeros(s1[0] * s1[1] * s1[2], np.uint8)
+    x0, y0, z0 = inside % s0[0], (inside // s0[0]) % s0[1], inside // (s0[0] * s0[1])
+    for q in range(8):
+        solid[(2 * x0 + (q & 1)) + s1[0] * ((2 * y0 + ((q >> 1) & 1)) + s1[1] * (2 * z0 + (q >> 2)))] = 1
+    sim = O.AmrSim(2, B, NX, NY, NZ, U, nu, b, band=[0, 8], wake=[0, 0], solid=solid)
+    n0, n1 = s0[0] * s0[1] * s0[2], s1[0] * s1[1] * s1[2]
+    moving = O.cell_rebuild(np.array([1.02, 0.04, -0.01, 0.02, 1e-4, 0, 0, 0, 0, 0]), om[1], 1.0)
+    sim.set_f(1, np.tile(moving[:, None], (1, n1)))
+    sim.set_f(0, np.full((27, n0), np.nan))
+    sim.restrict_only(0)
+    f0 = sim.get_f(0)
+    rest = O.equilibrium(1.0, [0.0, 0.0, 0.0])
+    assert np.abs(f0[:, inside] - rest[:, None]).max() < 1e-15
+    others = np.setdiff1d(bc, inside)
+    got = np.array([O.cell_transfer(f0[:, c], om[0], 2.0) for c in others[:50]])
+    assert np.abs(got[:, :4] - np.array([1.02, 0.04, -0.01, 0.02])).max() < 1e-14
+
+
 def _vertical_branch():
     """One branch on the axis x = 40, y = 32 from z = 20 to z = 44, diameter 4
     (finest cells): its box spans x 38..42, y 30..34, z 18..46."""
