@@ -611,17 +611,25 @@ __device__ __forceinline__ void amr_restrict_item(const CollideArgs &coarse, con
     }
     __syncthreads();
     const int cell = base + tid;
-    if (tid < CELLS && cell < n && rec[10][tid] != 0.0f) {
-        const float ic = 1.0f / rec[10][tid];
+    if (tid < CELLS && cell < n) {
+        // a band cell with no fluid child lies inside the wall: the fluid at
+        // rest (all transfer quantities zero)
         Transfer tr;
-        tr.drho = rec[0][tid] * ic;
-        const float irho = ic / (1.0f + tr.drho);
-        tr.ux = rec[1][tid] * irho;
-        tr.uy = rec[2][tid] * irho;
-        tr.uz = rec[3][tid] * irho;
+        tr.drho = tr.ux = tr.uy = tr.uz = 0.0f;
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            tr.d[k] = rec[4 + k][tid] * ic;
+            tr.d[k] = 0.0f;
+        if (rec[10][tid] != 0.0f) {
+            const float ic = 1.0f / rec[10][tid];
+            tr.drho = rec[0][tid] * ic;
+            const float irho = ic / (1.0f + tr.drho);
+            tr.ux = rec[1][tid] * irho;
+            tr.uy = rec[2][tid] * irho;
+            tr.uz = rec[3][tid] * irho;
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                tr.d[k] = rec[4 + k][tid] * ic;
+        }
         float g[NQ];
         back_transform(from_transfer(tr, om_c, dt_c), g);
         store_pre<B, S, ODD_C>(coarse, band[cell], g);

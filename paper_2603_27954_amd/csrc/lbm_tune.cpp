@@ -60,6 +60,12 @@ extern "C" lbm_status lbm_autotune(lbm_grid *g, const char *cache_path)
     const std::string key = tune_key(g);
     Choice cached{};
     if (cache_lookup(cache_path, key, &cached)) {
+        // the entry must be a shape the search could have chosen: a tile
+        // that divides a block into whole wavefronts, 64 to 256 threads
+        const int cells = g->B * g->B * g->B;
+        if (cached.threads < 64 || cached.threads > 256 || cached.threads % 64 != 0 || cached.tile < 64 ||
+            cached.tile > cells || cells % cached.tile != 0)
+            return grid_fail(g, LBM_E_INVALID, "tune cache entry for " + key + " has an invalid tile or work-group");
         grid_graphs_clear(g);
         g->threads = cached.threads;
         g->tile = cached.tile;
