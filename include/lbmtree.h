@@ -92,10 +92,14 @@ typedef struct {
     uint64_t seed;
 } lbm_tree_params;
 
+/* Levels of the octree grid: 1 (uniform) .. LBM_MAX_LEVELS; per-level arrays
+ * below hold LBM_MAX_LEVELS entries, of which the first `levels` are used. */
+#define LBM_MAX_LEVELS 8
+
 typedef struct {
     int32_t nx, ny, nz;   /* finest-level cells; multiples of block_edge << (levels-1) */
     int32_t block_edge;   /* 8 or 16 */
-    int32_t levels;       /* 1 (uniform) .. 4 */
+    int32_t levels;       /* 1 (uniform) .. LBM_MAX_LEVELS */
     double u_in;          /* inflow speed along +x, lattice units; Mach sqrt(3) u_in < 0.3 */
     double re_h;          /* Re_H = u_in H / nu_finest, H = tree height; used when nu <= 0 */
     double nu;            /* finest-level lattice viscosity; > 0 overrides re_h */
@@ -121,8 +125,8 @@ typedef struct {
  * refined block has all 26 neighbours at its own level.  Ignored when
  * levels == 1. */
 typedef struct {
-    int32_t band[4];
-    int32_t wake[4];
+    int32_t band[LBM_MAX_LEVELS];
+    int32_t wake[LBM_MAX_LEVELS];
 } lbm_refine_desc;
 
 typedef struct {
@@ -139,12 +143,12 @@ typedef struct {
 
 typedef struct {
     int32_t levels, block_edge, storage;
-    int64_t blocks[4];        /* allocated blocks per level (active + covered + ghost) */
-    int64_t active_cells[4];  /* leaf fluid + solid cells per level */
-    int64_t updated_cells[4]; /* leaf fluid cells per level: the cell updates one level sub-step counts */
+    int64_t blocks[LBM_MAX_LEVELS];        /* allocated blocks per level (active + covered + ghost) */
+    int64_t active_cells[LBM_MAX_LEVELS];  /* leaf fluid + solid cells per level */
+    int64_t updated_cells[LBM_MAX_LEVELS]; /* leaf fluid cells per level: the cell updates one level sub-step counts */
     int64_t links;
     int32_t branches;
-    double omega1[4];
+    double omega1[LBM_MAX_LEVELS];
     double height, area_x, nu_finest;
     size_t device_bytes;
     int32_t tile_cells;       /* cells per work-group of the block-level collide kernel */
@@ -152,7 +156,7 @@ typedef struct {
     int32_t occ_even, occ_odd;/* resident-wave caps per SIMD of the collide kernel (0 = none) */
     int32_t persist_wgs;      /* work-groups of the persistent launch (all resident) */
     int32_t persist_graph;    /* 1: the persistent launch replays from a captured graph */
-    int64_t collided_cells[4];/* cells collided per level sub-step (leaf + band + ghost, solid excluded) */
+    int64_t collided_cells[LBM_MAX_LEVELS];/* cells collided per level sub-step (leaf + band + ghost, solid excluded) */
     int32_t xcd_group;        /* consecutive collide tiles per XCD run (1 = plain dispatch order) */
     int32_t wall_clock_khz;   /* the device's constant real-time clock (hipDeviceAttributeWallClockRate) */
     uint64_t persist_wait_ticks; /* time limit of one wait of the persistent launch, in ticks of that clock */
@@ -401,13 +405,13 @@ lbm_status lbm_inflow_modes(uint64_t seed, int32_t n_modes, double intensity, do
  * run against device memory before allocating it. */
 typedef struct {
     int32_t levels, block_edge;
-    int32_t lattice[4][3];        /* blocks along x, y, z of each level's box */
-    int64_t blocks[4];            /* blocks held per level (leaf + refined + ghost storage) */
-    int64_t leaf_cells[4];        /* leaf cells per level (solid included) */
-    int64_t collided_cells[4];    /* cells collided per level sub-step (leaf + band + ghost) */
-    int64_t updated_cells[4];     /* leaf fluid cells per level (what MLUPS counts) */
-    int64_t work_blocks[4];       /* blocks (dense: 256-cell tiles) holding cells to collide */
-    int64_t work_tiles[4];        /* of those, B^2-cell z-slices holding cells to collide */
+    int32_t lattice[LBM_MAX_LEVELS][3]; /* blocks along x, y, z of each level's box */
+    int64_t blocks[LBM_MAX_LEVELS];            /* blocks held per level (leaf + refined + ghost storage) */
+    int64_t leaf_cells[LBM_MAX_LEVELS];        /* leaf cells per level (solid included) */
+    int64_t collided_cells[LBM_MAX_LEVELS];    /* cells collided per level sub-step (leaf + band + ghost) */
+    int64_t updated_cells[LBM_MAX_LEVELS];     /* leaf fluid cells per level (what MLUPS counts) */
+    int64_t work_blocks[LBM_MAX_LEVELS];       /* blocks (dense: 256-cell tiles) holding cells to collide */
+    int64_t work_tiles[LBM_MAX_LEVELS];        /* of those, B^2-cell z-slices holding cells to collide */
     int64_t links, solid_cells;
     int64_t pop_bytes;            /* population storage of every level in d->storage: the size
                                      lbm_bind_memory needs */

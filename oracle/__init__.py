@@ -335,8 +335,8 @@ class AmrSim:
                  n_branch=0, galilean=True, periodic_x=False):
         self.L, self.B = L, B
         b = np.ascontiguousarray(branches, dtype=np.float64)
-        band = (C.c_int * 4)(*[int(v) for v in (list(band) + [0] * 4)[:4]])
-        wake = (C.c_int * 4)(*[int(v) for v in (list(wake) + [0] * 4)[:4]])
+        band = (C.c_int * 8)(*[int(v) for v in (list(band) + [0] * 8)[:8]])
+        wake = (C.c_int * 8)(*[int(v) for v in (list(wake) + [0] * 8)[:8]])
         self.solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
         if link is None:
             link = {"cell": np.zeros(0, np.int64), "dir": np.zeros(0, np.int8), "q": np.zeros(0),
@@ -428,13 +428,13 @@ def amr_maps(L, B, nx, ny, nz, branches, band, wake):
     without the dense state of AmrSim.  Raises ValueError when a refined region
     comes too close to the box faces."""
     b = np.ascontiguousarray(branches, dtype=np.float64).reshape(-1, 10)
-    bd = (C.c_int * 4)(*[int(v) for v in (list(band) + [0] * 4)[:4]])
-    wk = (C.c_int * 4)(*[int(v) for v in (list(wake) + [0] * 4)[:4]])
+    bd = (C.c_int * 8)(*[int(v) for v in (list(band) + [0] * 8)[:8]])
+    wk = (C.c_int * 8)(*[int(v) for v in (list(wake) + [0] * 8)[:8]])
     maps = []
     for l in range(L):
         h = 1 << (L - 1 - l)
         maps.append(np.zeros((nx // h // B) * (ny // h // B) * (nz // h // B), np.uint8))
-    ptrs = (C.c_void_p * 4)(*([m.ctypes.data for m in maps] + [None] * (4 - L)))
+    ptrs = (C.c_void_p * 8)(*([m.ctypes.data for m in maps] + [None] * (8 - L)))
     if lib().or_amr_maps(L, B, nx, ny, nz, _ptr(b), len(b), bd, wk, ptrs) != 0:
         raise ValueError("invalid refinement: a refined region comes too close to the box faces")
     return maps

@@ -57,6 +57,8 @@
  */
 #include <math.h>
 #include <stdint.h>
+
+#define OR_MAX_LEVELS 8
 #include <stdlib.h>
 #include <string.h>
 
@@ -75,12 +77,13 @@ enum { C_NONE = 0, C_ACTIVE = 1, C_BAND = 2, C_DEEP = 3, C_GHOST = 4 };
 typedef struct {
     int L, B, nx, ny, nz, periodic_x, galilean;
     double u_in, nu_f;
-    int lnx[4], lny[4], lnz[4], nbx[4], nby[4], nbz[4];
-    uint8_t *bmap[4]; /* 0 none, 1 leaf, 2 refined, 3 ghost storage */
-    uint8_t *cls[4];
-    double omega[4];
-    double *f[4], *t[4];
-    double *m0[4], *m1[4];
+    int lnx[OR_MAX_LEVELS], lny[OR_MAX_LEVELS], lnz[OR_MAX_LEVELS];
+    int nbx[OR_MAX_LEVELS], nby[OR_MAX_LEVELS], nbz[OR_MAX_LEVELS];
+    uint8_t *bmap[OR_MAX_LEVELS]; /* 0 none, 1 leaf, 2 refined, 3 ghost storage */
+    uint8_t *cls[OR_MAX_LEVELS];
+    double omega[OR_MAX_LEVELS];
+    double *f[OR_MAX_LEVELS], *t[OR_MAX_LEVELS];
+    double *m0[OR_MAX_LEVELS], *m1[OR_MAX_LEVELS];
     uint8_t *solid;   /* finest box, may be NULL */
     int n_links;
     int64_t *lcell;
@@ -89,7 +92,7 @@ typedef struct {
     int32_t *lbr;
     int64_t *lstart;  /* per finest cell: first link index (links sorted by cell) */
     int n_branch;
-    int64_t steps[4], finest_steps;
+    int64_t steps[OR_MAX_LEVELS], finest_steps;
     double *force_log;  /* 3 per finest step, capacity log_cap */
     double *branch_force; /* 3 * n_branch, last finest step */
     int64_t log_cap, log_n;
@@ -608,8 +611,9 @@ static void advance(or_amr *a, int l)
 
 /* ---- API ------------------------------------------------------------------ */
 
-/* Creates the multi-level state.  branches: n rows of 10 doubles; band/wake:
- * 4 ints each (index = level).  solid/links describe the finest box (solid
+/* Creates the multi-level state (L = 1 .. OR_MAX_LEVELS).  branches: n rows
+ * of 10 doubles; band/wake: L ints each (index = level).  solid/links
+ * describe the finest box (solid
  * may be NULL for a grid without a body).  Returns NULL on an invalid
  * refinement. */
 or_amr *or_amr_create(int L, int B, int nx, int ny, int nz, double u_in, double nu_f, int galilean,
@@ -617,6 +621,8 @@ or_amr *or_amr_create(int L, int B, int nx, int ny, int nz, double u_in, double 
                       const uint8_t *solid, int n_links, const int64_t *lcell, const int8_t *ldir,
                       const double *lq, const int32_t *lbr, int n_branch)
 {
+    if (L < 1 || L > OR_MAX_LEVELS)
+        return NULL;
     or_amr *a = (or_amr *)calloc(1, sizeof(or_amr));
     a->L = L;
     a->B = B;
@@ -778,6 +784,8 @@ void or_amr_branch_force(const or_amr *a, double *out)
 int or_amr_maps(int L, int B, int nx, int ny, int nz, const double *br, int n, const int *band, const int *wake,
                 uint8_t *const *maps)
 {
+    if (L < 1 || L > OR_MAX_LEVELS)
+        return -1;
     or_amr a;
     memset(&a, 0, sizeof a);
     a.L = L;

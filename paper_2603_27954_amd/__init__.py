@@ -18,6 +18,7 @@ LBM_OK, LBM_E_INVALID, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_STATE = 
 LBM_FP32, LBM_FP16_DEV, LBM_BF16_DEV = 0, 1, 2
 LBM_F_NO_GALILEAN, LBM_F_GRAPH, LBM_F_PERSISTENT, LBM_F_AUTOTUNE, LBM_F_FRICTION = 1, 2, 4, 8, 16
 STORAGE = {"fp32": LBM_FP32, "fp16": LBM_FP16_DEV, "bf16": LBM_BF16_DEV}
+MAX_LEVELS = 8  # LBM_MAX_LEVELS
 
 _STATUS_NAMES = {0: "LBM_OK", -1: "LBM_E_INVALID", -2: "LBM_E_NOMEM", -3: "LBM_E_DEVICE",
                  -4: "LBM_E_UNSTABLE", -5: "LBM_E_STATE"}
@@ -51,13 +52,13 @@ class GridDesc(C.Structure):
 
 
 class RefineDesc(C.Structure):
-    _fields_ = [("band", C.c_int32 * 4), ("wake", C.c_int32 * 4)]
+    _fields_ = [("band", C.c_int32 * MAX_LEVELS), ("wake", C.c_int32 * MAX_LEVELS)]
 
 
 class Plan(C.Structure):
-    _fields_ = [("levels", C.c_int32), ("block_edge", C.c_int32), ("lattice", (C.c_int32 * 3) * 4),
-                ("blocks", C.c_int64 * 4), ("leaf_cells", C.c_int64 * 4), ("collided_cells", C.c_int64 * 4),
-                ("updated_cells", C.c_int64 * 4), ("work_blocks", C.c_int64 * 4), ("work_tiles", C.c_int64 * 4),
+    _fields_ = [("levels", C.c_int32), ("block_edge", C.c_int32), ("lattice", (C.c_int32 * 3) * MAX_LEVELS),
+                ("blocks", C.c_int64 * MAX_LEVELS), ("leaf_cells", C.c_int64 * MAX_LEVELS), ("collided_cells", C.c_int64 * MAX_LEVELS),
+                ("updated_cells", C.c_int64 * MAX_LEVELS), ("work_blocks", C.c_int64 * MAX_LEVELS), ("work_tiles", C.c_int64 * MAX_LEVELS),
                 ("links", C.c_int64), ("solid_cells", C.c_int64),
                 ("pop_bytes", C.c_int64)]
 
@@ -81,12 +82,12 @@ class DragResult(C.Structure):
 
 class Info(C.Structure):
     _fields_ = [("levels", C.c_int32), ("block_edge", C.c_int32), ("storage", C.c_int32),
-                ("blocks", C.c_int64 * 4), ("active_cells", C.c_int64 * 4),
-                ("updated_cells", C.c_int64 * 4), ("links", C.c_int64), ("branches", C.c_int32),
-                ("omega1", C.c_double * 4), ("height", C.c_double), ("area_x", C.c_double),
+                ("blocks", C.c_int64 * MAX_LEVELS), ("active_cells", C.c_int64 * MAX_LEVELS),
+                ("updated_cells", C.c_int64 * MAX_LEVELS), ("links", C.c_int64), ("branches", C.c_int32),
+                ("omega1", C.c_double * MAX_LEVELS), ("height", C.c_double), ("area_x", C.c_double),
                 ("nu_finest", C.c_double), ("device_bytes", C.c_size_t), ("tile_cells", C.c_int32),
                 ("threads", C.c_int32), ("occ_even", C.c_int32), ("occ_odd", C.c_int32),
-                ("persist_wgs", C.c_int32), ("persist_graph", C.c_int32), ("collided_cells", C.c_int64 * 4),
+                ("persist_wgs", C.c_int32), ("persist_graph", C.c_int32), ("collided_cells", C.c_int64 * MAX_LEVELS),
                 ("xcd_group", C.c_int32), ("wall_clock_khz", C.c_int32), ("persist_wait_ticks", C.c_uint64)]
 
 
@@ -451,7 +452,7 @@ def plan_levels(branches, refine=None, maps=False, **desc):
         for l in range(L):
             f = 1 << l
             arrs.append(np.zeros((d.nx // s) * f * (d.ny // s) * f * (d.nz // s) * f, np.int8))
-        ptrs = (C.POINTER(C.c_int8) * 4)(*[a.ctypes.data_as(C.POINTER(C.c_int8)) for a in arrs])
+        ptrs = (C.POINTER(C.c_int8) * MAX_LEVELS)(*[a.ctypes.data_as(C.POINTER(C.c_int8)) for a in arrs])
     _check(lib().lbm_plan_levels(C.byref(d), branches, len(branches), C.byref(r) if r else None, C.byref(out),
                                  ptrs))
     res = {"levels": out.levels, "block_edge": out.block_edge,

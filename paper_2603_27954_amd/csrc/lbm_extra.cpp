@@ -15,14 +15,14 @@ using namespace lbm;
 
 namespace {
 
-const uint64_t MAGIC = 0x33544B43544D424CULL;  // checkpoint tag (format 3: force ring, friction sums)
+const uint64_t MAGIC = 0x34544B43544D424CULL;  // checkpoint tag (format 4: up to LBM_MAX_LEVELS levels)
 
 struct CkptHeader {
     uint64_t magic;
     int32_t nx, ny, nz, B, L, storage;
     int64_t coarse_steps, finest_steps, samples, ring_count;
-    int64_t steps[4];
-    int64_t dir_elems[4];
+    int64_t steps[LBM_MAX_LEVELS];
+    int64_t dir_elems[LBM_MAX_LEVELS];
     int32_t nseg;
 };
 
@@ -159,12 +159,12 @@ lbm_status lbm_geometry_build(const lbm_branch *b, int32_t n_b, int32_t nx, int3
 {
     if (!b || n_b <= 0 || nx <= 0 || ny <= 0 || nz <= 0)
         return grid_fail(nullptr, LBM_E_INVALID, "bad geometry arguments");
-    std::vector<uint8_t> s;
+    SolidMask s;
     voxelize(b, n_b, nx, ny, nz, s);
     std::vector<HostLink> links;
-    build_links(b, n_b, nx, ny, nz, s, links);
+    build_links(b, n_b, s, links);
     if (solid)
-        std::memcpy(solid, s.data(), s.size());
+        s.expand(solid);
     const int64_t m = std::min<int64_t>(cap, (int64_t)links.size());
     for (int64_t t = 0; t < m; ++t) {
         if (cell) cell[t] = links[t].cell;
@@ -175,7 +175,7 @@ lbm_status lbm_geometry_build(const lbm_branch *b, int32_t n_b, int32_t nx, int3
     if (n_links)
         *n_links = (int64_t)links.size();
     if (area_x)
-        *area_x = (double)frontal_area(s, nx, ny, nz);
+        *area_x = (double)frontal_area(s);
     return LBM_OK;
 }
 

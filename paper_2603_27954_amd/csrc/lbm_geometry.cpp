@@ -270,53 +270,72 @@ bool tree_fits_box(const lbm_branch *b, int n, int nx, int ny, int nz, double ma
     return true;
 }
 
-void voxelize(const lbm_branch *b, int n, int nx, int ny, int nz, std::vector<uint8_t> &solid)
+int64_t SolidMask::count() const
 {
-    solid.assign((size_t)nx * ny * nz, 0);
+    int64_t c = 0;
+    for (uint8_t v : m)
+        c += v != 0;
+    return c;
+}
+
+void SolidMask::expand(uint8_t *dense) const
+{
+    std::memset(dense, 0, (size_t)nx * ny * nz);
+    for (int z = 0; z < s[2]; ++z)
+        for (int y = 0; y < s[1]; ++y)
+            std::memcpy(dense + (size_t)o[0] + (size_t)nx * ((size_t)(o[1] + y) + (size_t)ny * (o[2] + z)),
+                        m.data() + (size_t)s[0] * ((size_t)y + (size_t)s[1] * z), (size_t)s[0]);
+}
+
+void voxelize(const lbm_branch *b, int n, int nx, int ny, int nz, SolidMask &solid)
+{
+    solid = SolidMask{};
+    solid.nx = nx;
+    solid.ny = ny;
+    solid.nz = nz;
+    const int ext[3] = {nx, ny, nz};
+    std::vector<Shape> shapes;
+    int blo[3] = {ext[0], ext[1], ext[2]}, bhi[3] = {-1, -1, -1};
     for (int i = 0; i < n; ++i) {
-        const Shape s = make_shape(b[i]);
-        int lo[3], hi[3];
-        const int ext[3] = {nx, ny, nz};
+        shapes.push_back(make_shape(b[i]));
         for (int a = 0; a < 3; ++a) {
-            lo[a] = std::max(0, (int)std::floor(s.lo[a] - 0.5));
-            hi[a] = std::min(ext[a] - 1, (int)std::ceil(s.hi[a] - 0.5));
+            blo[a] = std::min(blo[a], std::max(0, (int)std::floor(shapes.back().lo[a] - 0.5)));
+            bhi[a] = std::max(bhi[a], std::min(ext[a] - 1, (int)std::ceil(shapes.back().hi[a] - 0.5)));
+        }
+    }
+    if (n == 0 || blo[0] > bhi[0] || blo[1] > bhi[1] || blo[2] > bhi[2])
+        return;
+    for (int a = 0; a < 3; ++a) {
+        solid.o[a] = blo[a];
+        solid.s[a] = bhi[a] - blo[a] + 1;
+    }
+    solid.m.assign((size_t)solid.s[0] * solid.s[1] * solid.s[2], 0);
+    for (const Shape &sh : shapes) {
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::max(0, (int)std::floor(sh.lo[a] - 0.5));
+            hi[a] = std::min(ext[a] - 1, (int)std::ceil(sh.hi[a] - 0.5));
         }
 #pragma omp parallel for schedule(static)
         for (int z = lo[2]; z <= hi[2]; ++z)
             for (int y = lo[1]; y <= hi[1]; ++y)
                 for (int x = lo[0]; x <= hi[0]; ++x) {
-                    uint8_t &c = solid[(size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z)];
-                    if (!c && inside(s, {x + 0.5, y + 0.5, z + 0.5}))
+                    uint8_t &c = solid.m[(size_t)(x - solid.o[0]) +
+                                         (size_t)solid.s[0] * ((size_t)(y - solid.o[1]) + (size_t)solid.s[1] * (z - solid.o[2]))];
+                    if (!c && inside(sh, {x + 0.5, y + 0.5, z + 0.5}))
                         c = 1;
                 }
     }
 }
 
-int64_t build_links(const lbm_branch *b, int n, int nx, int ny, int nz, const std::vector<uint8_t> &solid,
-                    std::vector<HostLink> &links)
+int64_t build_links(const lbm_branch *b, int n, const SolidMask &solid, std::vector<HostLink> &links)
 {
+    const int nx = solid.nx, ny = solid.ny, nz = solid.nz;
     std::vector<Shape> shapes;
     shapes.reserve(n);
     for (int i = 0; i < n; ++i)
         shapes.push_back(make_shape(b[i]));
-    // coarse bins of 16 cells listing the shapes whose box reaches into them
-    const int BS = 16;
-    const int gx = (nx + BS - 1) / BS, gy = (ny + BS - 1) / BS, gz = (nz + BS - 1) / BS;
-    std::vector<std::vector<int>> bins((size_t)gx * gy * gz);
-    for (int i = 0; i < n; ++i) {
-        int lo[3], hi[3];
-        const int g[3] = {gx, gy, gz};
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = std::max(0, (int)std::floor((shapes[i].lo[a] - 2.0) / BS));
-            hi[a] = std::min(g[a] - 1, (int)std::floor((shapes[i].hi[a] + 2.0) / BS));
-        }
-        for (int z = lo[2]; z <= hi[2]; ++z)
-            for (int y = lo[1]; y <= hi[1]; ++y)
-                for (int x = lo[0]; x <= hi[0]; ++x)
-                    bins[(size_t)x + (size_t)gx * ((size_t)y + (size_t)gy * z)].push_back(i);
-    }
     links.clear();
-    const auto at = [&](int x, int y, int z) { return (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z); };
     // only cells within two cells of the tree's bounding box can have links
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
     {
@@ -327,11 +346,57 @@ int64_t build_links(const lbm_branch *b, int n, int nx, int ny, int nz, const st
                 hi[a] = std::max(hi[a], std::min(ext[a] - 1, (int)std::ceil(sh.hi[a]) + 2));
             }
     }
-    for (int z = lo[2]; z <= hi[2]; ++z)
+    if (n == 0 || lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2])
+        return 0;
+    // bins of 16 cells over that region listing the shapes whose box reaches
+    // into them
+    const int BS = 16;
+    const int gx = (hi[0] - lo[0]) / BS + 1, gy = (hi[1] - lo[1]) / BS + 1, gz = (hi[2] - lo[2]) / BS + 1;
+    std::vector<std::vector<int>> bins((size_t)gx * gy * gz);
+    for (int i = 0; i < n; ++i) {
+        int blo[3], bhi[3];
+        const int g[3] = {gx, gy, gz};
+        for (int a = 0; a < 3; ++a) {
+            blo[a] = std::max(0, (int)std::floor((shapes[i].lo[a] - 2.0 - lo[a]) / BS));
+            bhi[a] = std::min(g[a] - 1, (int)std::floor((shapes[i].hi[a] + 2.0 - lo[a]) / BS));
+        }
+        for (int z = blo[2]; z <= bhi[2]; ++z)
+            for (int y = blo[1]; y <= bhi[1]; ++y)
+                for (int x = blo[0]; x <= bhi[0]; ++x)
+                    bins[(size_t)x + (size_t)gx * ((size_t)y + (size_t)gy * z)].push_back(i);
+    }
+    // cells with a solid cell among their 26 neighbours (y and z wrapped as
+    // below), marked from the solid cells: only those can hold links
+    const int rx = hi[0] - lo[0] + 1, ry = hi[1] - lo[1] + 1, rz = hi[2] - lo[2] + 1;
+    std::vector<uint8_t> near((size_t)rx * ry * rz, 0);
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < solid.s[2]; ++z)
+        for (int y = 0; y < solid.s[1]; ++y)
+            for (int x = 0; x < solid.s[0]; ++x) {
+                if (!solid.m[(size_t)x + (size_t)solid.s[0] * ((size_t)y + (size_t)solid.s[1] * z)])
+                    continue;
+                const int X = solid.o[0] + x, Y = solid.o[1] + y, Z = solid.o[2] + z;
+                for (int k = 0; k < 27; ++k) {
+                    const int fx = X + k % 3 - 1, fy = (Y + (k / 3) % 3 - 1 + ny) % ny, fz = (Z + k / 9 - 1 + nz) % nz;
+                    if (fx < lo[0] || fx > hi[0] || fy < lo[1] || fy > hi[1] || fz < lo[2] || fz > hi[2])
+                        continue;
+                    // neighbouring slices are marked by several threads: atomic byte stores
+                    __atomic_store_n(&near[(size_t)(fx - lo[0]) + (size_t)rx * ((size_t)(fy - lo[1]) + (size_t)ry * (fz - lo[2]))],
+                                     (uint8_t)1, __ATOMIC_RELAXED);
+                }
+            }
+    // links per z-slice in parallel, joined in slice order: (cell, direction)
+    // order as a serial sweep gives
+    std::vector<std::vector<HostLink>> per_z((size_t)rz);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int z = lo[2]; z <= hi[2]; ++z) {
+        std::vector<HostLink> &out = per_z[(size_t)(z - lo[2])];
         for (int y = lo[1]; y <= hi[1]; ++y)
             for (int x = lo[0]; x <= hi[0]; ++x) {
-                const size_t c = at(x, y, z);
-                if (solid[c])
+                if (!near[(size_t)(x - lo[0]) + (size_t)rx * ((size_t)(y - lo[1]) + (size_t)ry * (z - lo[2]))])
+                    continue;
+                const int64_t c = (int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z);
+                if (solid(x, y, z))
                     continue;
                 for (int i = 0; i < 27; ++i) {
                     if (i == 13)
@@ -341,18 +406,18 @@ int64_t build_links(const lbm_branch *b, int n, int nx, int ny, int nz, const st
                     if (sx < 0 || sx >= nx)
                         continue;
                     const int sy = (y + cy + ny) % ny, sz = (z + cz + nz) % nz;
-                    if (!solid[at(sx, sy, sz)])
+                    if (!solid(sx, sy, sz))
                         continue;
                     HostLink L;
-                    L.cell = (int64_t)c;
+                    L.cell = c;
                     L.dir = (int8_t)i;
                     const V3 o{x + 0.5, y + 0.5, z + 0.5}, d{(double)cx, (double)cy, (double)cz};
                     double best = std::numeric_limits<double>::infinity();
                     int bid = -1;
                     const V3 mid = o + 0.5 * d;
-                    const int bxi = std::min(gx - 1, std::max(0, (int)(mid.x / BS)));
-                    const int byi = std::min(gy - 1, std::max(0, (int)(mid.y / BS)));
-                    const int bzi = std::min(gz - 1, std::max(0, (int)(mid.z / BS)));
+                    const int bxi = std::min(gx - 1, std::max(0, (int)std::floor((mid.x - lo[0]) / BS)));
+                    const int byi = std::min(gy - 1, std::max(0, (int)std::floor((mid.y - lo[1]) / BS)));
+                    const int bzi = std::min(gz - 1, std::max(0, (int)std::floor((mid.z - lo[2]) / BS)));
                     for (int si : bins[(size_t)bxi + (size_t)gx * ((size_t)byi + (size_t)gy * bzi)]) {
                         const double t = entry(shapes[si], o, d);
                         if (t < best || (t == best && shapes[si].id < bid)) {
@@ -368,10 +433,13 @@ int64_t build_links(const lbm_branch *b, int n, int nx, int ny, int nz, const st
                     L.branch = bid;
                     // upstream neighbour x - c_i fluid and inside the box
                     const int ux = x - cx;
-                    L.up_fluid = (ux >= 0 && ux < nx) && !solid[at(ux, (y - cy + ny) % ny, (z - cz + nz) % nz)];
-                    links.push_back(L);
+                    L.up_fluid = (ux >= 0 && ux < nx) && !solid(ux, (y - cy + ny) % ny, (z - cz + nz) % nz);
+                    out.push_back(L);
                 }
             }
+    }
+    for (const std::vector<HostLink> &v : per_z)
+        links.insert(links.end(), v.begin(), v.end());
     return (int64_t)links.size();
 }
 
@@ -407,13 +475,13 @@ void branch_wall_normal(const lbm_branch &b, const double x[3], double n[3])
     n[2] = nb.z;
 }
 
-int64_t frontal_area(const std::vector<uint8_t> &solid, int nx, int ny, int nz)
+int64_t frontal_area(const SolidMask &solid)
 {
     int64_t a = 0;
-    for (int z = 0; z < nz; ++z)
-        for (int y = 0; y < ny; ++y) {
-            const uint8_t *row = solid.data() + (size_t)nx * ((size_t)y + (size_t)ny * z);
-            a += std::any_of(row, row + nx, [](uint8_t v) { return v != 0; }) ? 1 : 0;
+    for (int z = 0; z < solid.s[2]; ++z)
+        for (int y = 0; y < solid.s[1]; ++y) {
+            const uint8_t *row = solid.m.data() + (size_t)solid.s[0] * ((size_t)y + (size_t)solid.s[1] * z);
+            a += std::any_of(row, row + solid.s[0], [](uint8_t v) { return v != 0; }) ? 1 : 0;
         }
     return a;
 }

@@ -24,7 +24,7 @@ struct lbm_grid {
     int B = 16, L = 1;
     double nu_f = 0.0, H = 0.0, area_x = 0.0;
     std::vector<lbm_branch> branches;
-    std::vector<uint8_t> solid;
+    lbm::SolidMask solid;
     std::vector<HostLink> links;  // (cell, dir) order
     std::vector<DevLevel> lv;
     AmrPlan amr;
@@ -82,7 +82,7 @@ struct lbm_grid {
         lbm::Phase *d_phases;         // persistent plans only
         unsigned *d_ctr;              // claim / finish counters of the phases
         int n_phases;
-        int64_t level_steps[8];
+        int64_t level_steps[LBM_MAX_LEVELS];
         int64_t coarse, finest, samples, ring;
     };
     std::vector<StepGraph> graphs;

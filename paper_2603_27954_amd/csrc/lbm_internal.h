@@ -1,6 +1,7 @@
 // Internal structures shared by the host runtime and the HIP kernels of
 // liblbmtree.so.  Not part of the public ABI.
 #pragma once
+#include <algorithm>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -158,13 +159,45 @@ struct DevLevel {
     int64_t updated_cells = 0;   // leaf fluid cells (the updates a level sub-step counts)
     int64_t collided_cells = 0;  // cells collided per sub-step (leaf + band + ghost, solid excluded)
     int64_t leaf_cells = 0;
-    // host mirrors
+    // host mirrors.  The block map and the block index cover the stored block
+    // box (first block box_o, extent box_n) of the level's lattice: the whole
+    // lattice for level 0, the blocks around the refined region for finer
+    // levels, so that a level's host tables scale with its blocks, not with
+    // its box.
+    int box_o[3] = {0, 0, 0}, box_n[3] = {0, 0, 0};
     std::vector<int> h_bxyz;          // 3 per block
     std::vector<int> h_nbr;           // 27 per block
-    std::vector<int8_t> h_map;        // block map over the lattice (0 none, 1 leaf, 2 refined, 3 ghost)
-    std::vector<int> h_lattice_to_block;  // -1 when absent
+    std::vector<int8_t> h_map;        // block map over the stored box (0 none, 1 leaf, 2 refined, 3 ghost)
+    std::vector<int> h_lattice_to_block;  // over the stored box, -1 when absent
     std::vector<uint2> h_work, h_work_odd, h_leaf;
     std::vector<uint32_t> h_masks;
+
+    // index of block (bx, by, bz) in the stored box, -1 outside it
+    int64_t block_slot(int bx, int by, int bz) const
+    {
+        bx -= box_o[0];
+        by -= box_o[1];
+        bz -= box_o[2];
+        if ((unsigned)bx >= (unsigned)box_n[0] || (unsigned)by >= (unsigned)box_n[1] || (unsigned)bz >= (unsigned)box_n[2])
+            return -1;
+        return (int64_t)bx + (int64_t)box_n[0] * ((int64_t)by + (int64_t)box_n[1] * bz);
+    }
+    // kind of block (bx, by, bz): 0 none (also outside the stored box)
+    int8_t block_kind(int bx, int by, int bz) const
+    {
+        const int64_t s = block_slot(bx, by, bz);
+        return s < 0 ? (int8_t)0 : h_map[(size_t)s];
+    }
+    // the block map over the whole lattice, x fastest (nbx * nby * nbz bytes)
+    void expand_map(int8_t *dense) const
+    {
+        std::fill(dense, dense + (size_t)nbx * nby * nbz, (int8_t)0);
+        for (int z = 0; z < box_n[2]; ++z)
+            for (int y = 0; y < box_n[1]; ++y)
+                for (int x = 0; x < box_n[0]; ++x)
+                    dense[(size_t)(box_o[0] + x) + (size_t)nbx * ((size_t)(box_o[1] + y) + (size_t)nby * (box_o[2] + z))] =
+                        h_map[(size_t)x + (size_t)box_n[0] * ((size_t)y + (size_t)box_n[1] * z)];
+    }
 };
 
 // launchers (lbm_kernels.hip)

@@ -32,7 +32,10 @@ int64_t level_cell_address(const DevLevel &v, int B, int x, int y, int z)
     z = (z % v.nz + v.nz) % v.nz;
     if (v.dense)
         return (int64_t)x + (int64_t)v.nx * ((int64_t)y + (int64_t)v.ny * z);
-    const int bi = v.h_lattice_to_block[(size_t)(x / B) + (size_t)v.nbx * ((size_t)(y / B) + (size_t)v.nby * (z / B))];
+    const int64_t slot = v.block_slot(x / B, y / B, z / B);
+    if (slot < 0)
+        return -1;
+    const int bi = v.h_lattice_to_block[(size_t)slot];
     if (bi < 0)
         return -1;
     return (int64_t)bi * B * B * B + (x % B) + B * ((y % B) + B * (z % B));
@@ -44,20 +47,20 @@ int64_t level_cell_address(const DevLevel &v, int B, int x, int y, int z)
 static void index_level(DevLevel &v, int level)
 {
     std::vector<std::array<int, 3>> coords;
-    for (int z = 0; z < v.nbz; ++z)
-        for (int y = 0; y < v.nby; ++y)
-            for (int x = 0; x < v.nbx; ++x)
-                if (v.h_map[(size_t)x + (size_t)v.nbx * ((size_t)y + (size_t)v.nby * z)] != 0)
+    for (int z = v.box_o[2]; z < v.box_o[2] + v.box_n[2]; ++z)
+        for (int y = v.box_o[1]; y < v.box_o[1] + v.box_n[1]; ++y)
+            for (int x = v.box_o[0]; x < v.box_o[0] + v.box_n[0]; ++x)
+                if (v.block_kind(x, y, z) != 0)
                     coords.push_back({x, y, z});
     std::sort(coords.begin(), coords.end(), [](const std::array<int, 3> &a, const std::array<int, 3> &b) {
         return morton(a[0], a[1], a[2]) < morton(b[0], b[1], b[2]);
     });
     v.nb = (int)coords.size();
-    v.h_lattice_to_block.assign((size_t)v.nbx * v.nby * v.nbz, -1);
+    v.h_lattice_to_block.assign(v.h_map.size(), -1);
     v.h_bxyz.assign(3 * (size_t)(v.nb + 1), -1000000);
     for (int i = 0; i < v.nb; ++i) {
         const auto &c = coords[i];
-        v.h_lattice_to_block[(size_t)c[0] + (size_t)v.nbx * ((size_t)c[1] + (size_t)v.nby * c[2])] = i;
+        v.h_lattice_to_block[(size_t)v.block_slot(c[0], c[1], c[2])] = i;
         v.h_bxyz[3 * i] = c[0];
         v.h_bxyz[3 * i + 1] = c[1];
         v.h_bxyz[3 * i + 2] = c[2];
@@ -78,10 +81,11 @@ static void index_level(DevLevel &v, int level)
                     y = (y + v.nby) % v.nby;
                     z = (z + v.nbz) % v.nbz;
                 }
-                if (x < 0 || y < 0 || z < 0 || x >= v.nbx || y >= v.nby || z >= v.nbz)
+                const int64_t slot = v.block_slot(x, y, z);
+                if (x < 0 || y < 0 || z < 0 || x >= v.nbx || y >= v.nby || z >= v.nbz || slot < 0)
                     val = v.nb;
                 else {
-                    const int bi = v.h_lattice_to_block[(size_t)x + (size_t)v.nbx * ((size_t)y + (size_t)v.nby * z)];
+                    const int bi = v.h_lattice_to_block[(size_t)slot];
                     val = bi < 0 ? v.nb : bi;
                 }
             }
@@ -189,15 +193,101 @@ struct RefineRule {
     }
 };
 
+// Block map of one level over a stored box of its lattice (whole lattice
+// NX x NY x NZ; stored box from o, extent n), grown on demand: finer levels
+// store only the blocks around the refined region.
 struct Lattice {
-    int nx, ny, nz;
+    int NX = 0, NY = 0, NZ = 0;
+    int o[3] = {0, 0, 0}, n[3] = {0, 0, 0};
     std::vector<int8_t> m;  // 0 none, 1 leaf, 2 refined, 3 ghost storage
-    int8_t &at(int x, int y, int z) { return m[(size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z)]; }
+    int64_t slot(int x, int y, int z) const
+    {
+        x -= o[0];
+        y -= o[1];
+        z -= o[2];
+        if ((unsigned)x >= (unsigned)n[0] || (unsigned)y >= (unsigned)n[1] || (unsigned)z >= (unsigned)n[2])
+            return -1;
+        return (int64_t)x + (int64_t)n[0] * ((int64_t)y + (int64_t)n[1] * z);
+    }
+    bool in_lattice(int x, int y, int z) const { return x >= 0 && y >= 0 && z >= 0 && x < NX && y < NY && z < NZ; }
+    // -1 outside the lattice, 0 for blocks outside the stored box
     int8_t get(int x, int y, int z) const
     {
-        if (x < 0 || y < 0 || z < 0 || x >= nx || y >= ny || z >= nz)
+        if (!in_lattice(x, y, z))
             return -1;
-        return m[(size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z)];
+        const int64_t s = slot(x, y, z);
+        return s < 0 ? (int8_t)0 : m[(size_t)s];
+    }
+    // (x, y, z) must lie in the lattice; the stored box grows to hold it
+    int8_t &at(int x, int y, int z)
+    {
+        int64_t s = slot(x, y, z);
+        if (s < 0) {
+            const int lo[3] = {x, y, z}, hi[3] = {x, y, z};
+            reshape(lo, hi, 8);
+            s = slot(x, y, z);
+        }
+        return m[(size_t)s];
+    }
+    // stored box = the current one joined with [lo, hi] grown by margin,
+    // clipped to the lattice; entries keep their values
+    void reshape(const int lo_in[3], const int hi_in[3], int margin)
+    {
+        const int N[3] = {NX, NY, NZ};
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::max(0, lo_in[a] - margin);
+            hi[a] = std::min(N[a] - 1, hi_in[a] + margin);
+            if (n[a] > 0) {
+                lo[a] = std::min(lo[a], o[a]);
+                hi[a] = std::max(hi[a], o[a] + n[a] - 1);
+            }
+        }
+        Lattice t;
+        t.NX = NX;
+        t.NY = NY;
+        t.NZ = NZ;
+        for (int a = 0; a < 3; ++a) {
+            t.o[a] = lo[a];
+            t.n[a] = hi[a] - lo[a] + 1;
+        }
+        t.m.assign((size_t)t.n[0] * t.n[1] * t.n[2], 0);
+        for (int z = 0; z < n[2]; ++z)
+            for (int y = 0; y < n[1]; ++y)
+                for (int x = 0; x < n[0]; ++x)
+                    t.m[(size_t)t.slot(o[0] + x, o[1] + y, o[2] + z)] =
+                        m[(size_t)x + (size_t)n[0] * ((size_t)y + (size_t)n[1] * z)];
+        *this = std::move(t);
+    }
+    // stored box = the blocks present grown by margin (clipped)
+    void fit(int margin)
+    {
+        int lo[3] = {NX, NY, NZ}, hi[3] = {-1, -1, -1};
+        for (int z = 0; z < n[2]; ++z)
+            for (int y = 0; y < n[1]; ++y)
+                for (int x = 0; x < n[0]; ++x)
+                    if (m[(size_t)x + (size_t)n[0] * ((size_t)y + (size_t)n[1] * z)] != 0) {
+                        const int c[3] = {o[0] + x, o[1] + y, o[2] + z};
+                        for (int a = 0; a < 3; ++a) {
+                            lo[a] = std::min(lo[a], c[a]);
+                            hi[a] = std::max(hi[a], c[a]);
+                        }
+                    }
+        if (hi[0] < 0)
+            return;
+        Lattice t;
+        t.NX = NX;
+        t.NY = NY;
+        t.NZ = NZ;
+        t.reshape(lo, hi, margin);
+        for (int z = 0; z < n[2]; ++z)
+            for (int y = 0; y < n[1]; ++y)
+                for (int x = 0; x < n[0]; ++x) {
+                    const int8_t v = m[(size_t)x + (size_t)n[0] * ((size_t)y + (size_t)n[1] * z)];
+                    if (v != 0)
+                        t.m[(size_t)t.slot(o[0] + x, o[1] + y, o[2] + z)] = v;
+                }
+        *this = std::move(t);
     }
 };
 
@@ -222,7 +312,7 @@ bool make_refined(std::vector<Lattice> &lat, int l, int bx, int by, int bz)
 }  // namespace
 
 lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *b, int n_b,
-                        const lbm_refine_desc *refine, const std::vector<uint8_t> &solid,
+                        const lbm_refine_desc *refine, const SolidMask &solid,
                         std::vector<DevLevel> &lv, AmrPlan &plan, std::string *msg)
 {
     plan.pairs.clear();
@@ -242,29 +332,39 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
     if (L == 1) {
         DevLevel &v = lv[0];
         v.h_map.assign((size_t)v.nbx * v.nby * v.nbz, 1);
+        v.box_n[0] = v.nbx;
+        v.box_n[1] = v.nby;
+        v.box_n[2] = v.nbz;
         v.leaf_cells = (int64_t)d.nx * d.ny * d.nz;
-        dense_tiles(v, [&](int64_t c) { return solid[(size_t)c] == 0; }, v.h_work, &v.updated_cells);
+        dense_tiles(v, [&](int64_t c) { return !solid.cell(c); }, v.h_work, &v.updated_cells);
         v.collided_cells = v.updated_cells;
         v.h_leaf = v.h_work;
         return LBM_OK;
     }
 
     // ---- block maps ----------------------------------------------------------
+    // level 0 stores its whole lattice; finer levels store a box around their
+    // blocks that grows as blocks appear
     std::vector<Lattice> lat(L);
     for (int l = 0; l < L; ++l) {
-        lat[l].nx = lv[l].nbx;
-        lat[l].ny = lv[l].nby;
-        lat[l].nz = lv[l].nbz;
-        lat[l].m.assign((size_t)lv[l].nbx * lv[l].nby * lv[l].nbz, (int8_t)(l == 0 ? 1 : 0));
+        lat[l].NX = lv[l].nbx;
+        lat[l].NY = lv[l].nby;
+        lat[l].NZ = lv[l].nbz;
+    }
+    {
+        const int lo[3] = {0, 0, 0}, hi[3] = {lv[0].nbx - 1, lv[0].nby - 1, lv[0].nbz - 1};
+        lat[0].reshape(lo, hi, 0);
+        std::fill(lat[0].m.begin(), lat[0].m.end(), (int8_t)1);
     }
     RefineRule rule(b, n_b, refine);
     for (int l = 1; l < L; ++l) {
         Lattice &P = lat[l - 1];
         const double bf = (double)B * (double)(1 << (L - l));
-        for (int z = 0; z < P.nz; ++z)
-            for (int y = 0; y < P.ny; ++y)
-                for (int x = 0; x < P.nx; ++x)
-                    if (P.at(x, y, z) != 0 && rule.wants(l, x, y, z, bf)) {
+        const int o[3] = {P.o[0], P.o[1], P.o[2]}, e[3] = {P.n[0], P.n[1], P.n[2]};
+        for (int z = o[2]; z < o[2] + e[2]; ++z)
+            for (int y = o[1]; y < o[1] + e[1]; ++y)
+                for (int x = o[0]; x < o[0] + e[0]; ++x)
+                    if (P.get(x, y, z) > 0 && rule.wants(l, x, y, z, bf)) {
                         P.at(x, y, z) = 2;
                         for (int s = 0; s < 8; ++s)
                             lat[l].at(2 * x + (s & 1), 2 * y + ((s >> 1) & 1), 2 * z + (s >> 2)) = 1;
@@ -274,10 +374,11 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
         changed = false;
         for (int l = L - 2; l >= 1; --l) {
             Lattice &T = lat[l];
-            for (int z = 0; z < T.nz; ++z)
-                for (int y = 0; y < T.ny; ++y)
-                    for (int x = 0; x < T.nx; ++x) {
-                        if (T.at(x, y, z) != 2)
+            const int o[3] = {T.o[0], T.o[1], T.o[2]}, e[3] = {T.n[0], T.n[1], T.n[2]};
+            for (int z = o[2]; z < o[2] + e[2]; ++z)
+                for (int y = o[1]; y < o[1] + e[1]; ++y)
+                    for (int x = o[0]; x < o[0] + e[0]; ++x) {
+                        if (T.get(x, y, z) != 2)
                             continue;
                         for (int k = 0; k < 27; ++k) {
                             const int X = x + k % 3 - 1, Y = y + (k / 3) % 3 - 1, Z = z + k / 9 - 1;
@@ -299,27 +400,28 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
     }
     for (int l = 0; l < L - 1; ++l) {
         const Lattice &T = lat[l];
-        for (int z = 0; z < T.nz; ++z)
-            for (int y = 0; y < T.ny; ++y)
-                for (int x = 0; x < T.nx; ++x)
-                    if (T.m[(size_t)x + (size_t)T.nx * ((size_t)y + (size_t)T.ny * z)] == 2 &&
-                        (x < 1 || y < 1 || z < 1 || x > T.nx - 2 || y > T.ny - 2 || z > T.nz - 2)) {
+        for (int z = T.o[2]; z < T.o[2] + T.n[2]; ++z)
+            for (int y = T.o[1]; y < T.o[1] + T.n[1]; ++y)
+                for (int x = T.o[0]; x < T.o[0] + T.n[0]; ++x)
+                    if (T.get(x, y, z) == 2 &&
+                        (x < 1 || y < 1 || z < 1 || x > T.NX - 2 || y > T.NY - 2 || z > T.NZ - 2)) {
                         *msg = "a refined region comes within one block of the box faces";
                         return LBM_E_INVALID;
                     }
     }
     for (int l = 1; l < L; ++l) {
         Lattice &T = lat[l];
+        T.fit(1);  // room for the ghost-storage blocks around the present ones
         std::vector<int8_t> add(T.m.size(), 0);
-        for (int z = 0; z < T.nz; ++z)
-            for (int y = 0; y < T.ny; ++y)
-                for (int x = 0; x < T.nx; ++x) {
-                    if (T.at(x, y, z) != 0)
+        for (int z = T.o[2]; z < T.o[2] + T.n[2]; ++z)
+            for (int y = T.o[1]; y < T.o[1] + T.n[1]; ++y)
+                for (int x = T.o[0]; x < T.o[0] + T.n[0]; ++x) {
+                    if (T.get(x, y, z) != 0)
                         continue;
                     for (int k = 0; k < 27; ++k) {
                         const int8_t v = T.get(x + k % 3 - 1, y + (k / 3) % 3 - 1, z + k / 9 - 1);
                         if (v == 1 || v == 2) {
-                            add[(size_t)x + (size_t)T.nx * ((size_t)y + (size_t)T.ny * z)] = 1;
+                            add[(size_t)T.slot(x, y, z)] = 1;
                             break;
                         }
                     }
@@ -330,6 +432,10 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
     }
     for (int l = 0; l < L; ++l) {
         lv[l].h_map = lat[l].m;
+        for (int a = 0; a < 3; ++a) {
+            lv[l].box_o[a] = lat[l].o[a];
+            lv[l].box_n[a] = lat[l].n[a];
+        }
         if (l > 0)
             index_level(lv[l], l);
     }
@@ -363,9 +469,7 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
         return 0;
     };
     const int cells = B * B * B;
-    auto finest_solid = [&](int x, int y, int z) {
-        return solid[(size_t)x + (size_t)d.nx * ((size_t)y + (size_t)d.ny * z)] != 0;
-    };
+    auto finest_solid = [&](int x, int y, int z) { return solid(x, y, z); };
     for (int l = 0; l < L; ++l) {
         DevLevel &v = lv[l];
         const bool finest = l == L - 1;
@@ -510,9 +614,9 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
                 pr.h_band_child.push_back(sol ? FULL_MASK : addr_of(F, fx, fy, fz));
             }
         };
-        for (int bz = 0; bz < C.nbz; ++bz)
-            for (int by = 0; by < C.nby; ++by)
-                for (int bx = 0; bx < C.nbx; ++bx) {
+        for (int bz = C.box_o[2]; bz < C.box_o[2] + C.box_n[2]; ++bz)
+            for (int by = C.box_o[1]; by < C.box_o[1] + C.box_n[1]; ++by)
+                for (int bx = C.box_o[0]; bx < C.box_o[0] + C.box_n[0]; ++bx) {
                     if (lat[l].get(bx, by, bz) != 2)
                         continue;
                     for (int c = 0; c < cells; ++c) {

@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "../../include/lbmtree.h"
+#include "lbm_geometry.h"
 #include "lbm_internal.h"
 
 namespace lbm {
@@ -41,7 +42,7 @@ struct AmrPlan {
 using Alloc = std::function<lbm_status(void **, size_t)>;
 
 lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *b, int n_b,
-                        const lbm_refine_desc *refine, const std::vector<uint8_t> &solid,
+                        const lbm_refine_desc *refine, const SolidMask &solid,
                         std::vector<DevLevel> &lv, AmrPlan &plan, std::string *msg);
 
 // element address of level cell (x, y, z) (dense: x + nx (y + ny z); blocks:

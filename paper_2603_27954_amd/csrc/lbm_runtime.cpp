@@ -325,10 +325,9 @@ static lbm_status build_friction(lbm_grid *g)
     auto leaf_fluid = [&](int x, int y, int z) -> int64_t {
         if (x < 0 || x >= d.nx || y < 0 || y >= d.ny || z < 0 || z >= d.nz)
             return -1;
-        if (g->solid[(size_t)x + (size_t)d.nx * ((size_t)y + (size_t)d.ny * z)])
+        if (g->solid(x, y, z))
             return -1;
-        if (!fv.dense && fv.h_map[(size_t)(x / g->B) + (size_t)fv.nbx * ((size_t)(y / g->B) +
-                                                                         (size_t)fv.nby * (z / g->B))] != 1)
+        if (!fv.dense && fv.block_kind(x / g->B, y / g->B, z / g->B) != 1)
             return -1;
         return level_cell_address(fv, g->B, x, y, z);
     };
@@ -518,15 +517,16 @@ static const size_t MAX_GRAPHS = 64;
 
 // parity of every level, and which finest sub-steps of the coarse step
 // sample the force (the finest step count after sub-step j is f0 + j + 1)
+// A coarse step's launches depend on each level's A-A parity and on which of
+// its finest sub-steps take force samples; the samples fall where
+// (finest_steps + j + 1) is a multiple of drag_every, a pattern fixed by
+// finest_steps mod drag_every.
 static uint64_t step_key(const lbm_grid *g)
 {
     uint64_t k = 0;
     for (int l = 0; l < g->L; ++l)
         k |= (uint64_t)(g->lv[l].steps & 1) << l;
-    const int sub = 1 << (g->L - 1);
-    for (int j = 0; j < sub; ++j)
-        if ((g->finest_steps + j + 1) % g->d.drag_every == 0)
-            k |= 1ull << (8 + j);
+    k |= (uint64_t)(g->finest_steps % g->d.drag_every) << LBM_MAX_LEVELS;
     return k;
 }
 
@@ -568,7 +568,7 @@ static lbm_status graph_step(lbm_grid *g)
     // capture one coarse step; its host bookkeeping runs as in an eager step
     lbm_grid::StepGraph sg{};
     sg.key = key;
-    int64_t steps0[8] = {0};
+    int64_t steps0[LBM_MAX_LEVELS] = {0};
     for (int l = 0; l < g->L; ++l)
         steps0[l] = g->lv[l].steps;
     const int64_t c0 = g->coarse_steps, f0 = g->finest_steps, s0 = g->samples, r0 = g->ring_count;
@@ -642,7 +642,7 @@ static lbm_status persistent_step(lbm_grid *g)
     // eager step
     lbm_grid::StepGraph sg{};
     sg.key = key;
-    int64_t steps0[8] = {0};
+    int64_t steps0[LBM_MAX_LEVELS] = {0};
     for (int l = 0; l < g->L; ++l)
         steps0[l] = g->lv[l].steps;
     const int64_t c0 = g->coarse_steps, f0 = g->finest_steps, s0 = g->samples, r0 = g->ring_count;
@@ -787,7 +787,7 @@ static lbm_status check_desc(const lbm_grid_desc *d, std::string *msg)
     const int B = d->block_edge;
     if (B != 8 && B != 16)
         return (*msg = "block_edge must be 8 or 16", LBM_E_INVALID);
-    if (d->levels < 1 || d->levels > 4)
+    if (d->levels < 1 || d->levels > LBM_MAX_LEVELS)
         return (*msg = "levels must be 1..4", LBM_E_INVALID);
     const int unit = B << (d->levels - 1);
     if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0 || d->nx % unit || d->ny % unit || d->nz % unit)
@@ -863,6 +863,7 @@ lbm_status lbm_create_grid(const lbm_grid_desc *d, lbm_grid **out)
     g->B = B;
     g->L = d->levels;
     g->tile = B * B;  // one z-slice of a block per work-group
+    g->threads = std::min(256, g->tile);
     // measured defaults (uniform 512x256x256): streaming even steps run best
     // with 3 (FP32) or 4 (16-bit) waves per SIMD; odd steps are register-bound
     g->occ_even = d->storage == LBM_FP32 ? 3 : 4;
@@ -947,8 +948,8 @@ lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b, const
         return fail(g, LBM_E_INVALID, "finest viscosity out of range");
 
     voxelize(b, n_b, d.nx, d.ny, d.nz, g->solid);
-    build_links(b, n_b, d.nx, d.ny, d.nz, g->solid, g->links);
-    g->area_x = (double)frontal_area(g->solid, d.nx, d.ny, d.nz);
+    build_links(b, n_b, g->solid, g->links);
+    g->area_x = (double)frontal_area(g->solid);
 
     // block grid of every level
     std::string msg;
@@ -1360,11 +1361,13 @@ static void level_dense_cells(const lbm_grid *g, int l, std::vector<uint32_t> &c
     const int B = g->B;
     cells.clear();
     pos.clear();
-    for (int z = 0; z < v.nz; ++z)
-        for (int y = 0; y < v.ny; ++y)
-            for (int x = 0; x < v.nx; ++x) {
-                const int bx = x / B, by = y / B, bz = z / B;
-                const int8_t kind = v.h_map[(size_t)bx + (size_t)v.nbx * ((size_t)by + (size_t)v.nby * bz)];
+    // only the stored block box can hold cells
+    const int x0 = v.box_o[0] * B, y0 = v.box_o[1] * B, z0 = v.box_o[2] * B;
+    const int x1 = x0 + v.box_n[0] * B, y1 = y0 + v.box_n[1] * B, z1 = z0 + v.box_n[2] * B;
+    for (int z = z0; z < z1; ++z)
+        for (int y = y0; y < y1; ++y)
+            for (int x = x0; x < x1; ++x) {
+                const int8_t kind = v.block_kind(x / B, y / B, z / B);
                 if (kind != 1 && kind != 2)
                     continue;
                 cells.push_back((uint32_t)level_cell_address(v, B, x, y, z));
@@ -1448,7 +1451,7 @@ lbm_status lbm_get_cells(lbm_grid *g, int32_t level, int64_t n, const int64_t *c
         if (c < 0 || c >= N)
             continue;
         const int x = (int)(c % v.nx), y = (int)((c / v.nx) % v.ny), z = (int)(c / ((int64_t)v.nx * v.ny));
-        const int8_t kind = v.h_map[(size_t)(x / B) + (size_t)v.nbx * ((size_t)(y / B) + (size_t)v.nby * (z / B))];
+        const int8_t kind = v.block_kind(x / B, y / B, z / B);
         if (kind != 1 && kind != 2)
             continue;
         addr.push_back((uint32_t)level_cell_address(v, B, x, y, z));
@@ -1547,7 +1550,7 @@ lbm_status lbm_get_solid(lbm_grid *g, uint8_t *solid)
         return fail(g, LBM_E_INVALID, "null argument");
     if (g->state != 1)
         return fail(g, LBM_E_STATE, "set_geometry first");
-    std::memcpy(solid, g->solid.data(), g->solid.size());
+    g->solid.expand(solid);
     return LBM_OK;
 }
 
@@ -1595,10 +1598,10 @@ lbm_status lbm_plan_levels(const lbm_grid_desc *d, const lbm_branch *b, int32_t 
         return fail(nullptr, LBM_E_INVALID, msg);
     if (d->levels > 1 && !refine)
         return fail(nullptr, LBM_E_INVALID, "refinement bands required when levels > 1");
-    std::vector<uint8_t> solid;
+    SolidMask solid;
     std::vector<HostLink> links;
     voxelize(b, n_b, d->nx, d->ny, d->nz, solid);
-    build_links(b, n_b, d->nx, d->ny, d->nz, solid, links);
+    build_links(b, n_b, solid, links);
     std::vector<DevLevel> lv;
     AmrPlan plan;
     const int B = d->block_edge;
@@ -1609,8 +1612,7 @@ lbm_status lbm_plan_levels(const lbm_grid_desc *d, const lbm_branch *b, int32_t 
     out->levels = d->levels;
     out->block_edge = B;
     out->links = (int64_t)links.size();
-    for (uint8_t v : solid)
-        out->solid_cells += v != 0;
+    out->solid_cells = solid.count();
     const size_t eb = storage_bytes(d->storage);
     for (int l = 0; l < d->levels; ++l) {
         const DevLevel &v = lv[l];
@@ -1633,7 +1635,7 @@ lbm_status lbm_plan_levels(const lbm_grid_desc *d, const lbm_branch *b, int32_t 
         out->lattice[l][1] = v.nby;
         out->lattice[l][2] = v.nbz;
         if (maps && maps[l])
-            std::memcpy(maps[l], v.h_map.data(), v.h_map.size());
+            v.expand_map(maps[l]);
     }
     return LBM_OK;
 }
@@ -1665,7 +1667,7 @@ lbm_status lbm_plan_phases(const lbm_grid_desc *d, const lbm_branch *b, int32_t 
     g.H = tree_height(b, n_b);
     g.nu_f = dd.nu > 0.0 ? dd.nu : dd.u_in * g.H / dd.re_h;
     voxelize(b, n_b, dd.nx, dd.ny, dd.nz, g.solid);
-    build_links(b, n_b, dd.nx, dd.ny, dd.nz, g.solid, g.links);
+    build_links(b, n_b, g.solid, g.links);
     lbm_status st = build_levels(dd, g.B, g.L, b, n_b, refine, g.solid, g.lv, g.amr, &msg);
     if (st != LBM_OK)
         return fail(nullptr, st, msg);
@@ -1713,7 +1715,7 @@ lbm_status lbm_get_block_map(lbm_grid *g, int32_t level, int8_t *map)
         return fail(g, LBM_E_STATE, "set_geometry first");
     if (level < 0 || level >= g->L)
         return fail(g, LBM_E_INVALID, "level out of range");
-    std::memcpy(map, g->lv[level].h_map.data(), g->lv[level].h_map.size());
+    g->lv[level].expand_map(map);
     return LBM_OK;
 }
 

@@ -180,6 +180,68 @@ def test_planned_block_maps_with_wake_match_oracle_at_full_size(lt, name):
     assert (want[0] == 2).sum() > (bands_only[0] == 2).sum()
 
 
+# Five to seven levels (8^3 blocks) around the paper's n = 4 tree (Table 2)
+# in the paper's 32H x 16H x 16H domain with the centre of mass at
+# (8H, 8H, 8H): the surface refined to H/64 .. H/256 and the wake two levels
+# above the finest
+DEEP = {
+    "five_level_H64": dict(L=5, H=64.0, band=[0, 64, 32, 16, 4], wake=[0, 0, 128, 0, 0]),
+    "six_level_H128": dict(L=6, H=128.0, band=[0, 128, 64, 32, 16, 4], wake=[0, 0, 0, 256, 0, 0]),
+    "seven_level_H256": dict(L=7, H=256.0, band=[0, 256, 128, 64, 32, 16, 8], wake=[0, 0, 0, 0, 512, 0, 0]),
+}
+
+
+def _paper_tree(lt, n, H, com):
+    wq = 0.5 ** 0.5
+    p = lt.tree_params(2, n - 1, 100.0, 30.0, [0.8, 0.8], [wq, wq], [0.0, 0.0], [30.0, -30.0], [137.0, 137.0])
+    arr = lt.tree_generate(p)
+    lt.tree_place(arr, H, list(com))
+    return arr
+
+
+@pytest.mark.parametrize("name", list(DEEP))
+def test_planned_block_maps_of_deep_octrees_match_oracle(lt, name):
+    """Grids of five to seven levels (the paper's surface resolution needs
+    six or seven above a dense coarse level): block maps bit for bit against
+    the oracle's refinement rule, although the library keeps each finer
+    level's map over the blocks around its refined region only."""
+    c = DEEP[name]
+    H, L = c["H"], c["L"]
+    nx, ny, nz = int(32 * H), int(16 * H), int(16 * H)
+    arr = _paper_tree(lt, 4, H, (8 * H, 8 * H, 8 * H))
+    b = lt.branches_to_numpy(arr)
+    want = O.amr_maps(L, 8, nx, ny, nz, b, c["band"], c["wake"])
+    plan = lt.plan_levels(arr, refine={"band": c["band"], "wake": c["wake"]}, maps=True, nx=nx, ny=ny, nz=nz,
+                          u_in=0.05, re_h=2500.0, block_edge=8, levels=L)
+    for l in range(L):
+        assert np.array_equal(plan["maps"][l].astype(np.uint8), want[l]), f"level {l}"
+        assert (want[l] == 1).any(), f"level {l} has leaf blocks"
+    assert plan["levels"] == L
+
+
+def test_plan_of_the_paper_tree_at_h512_stays_sparse(lt):
+    """The n = 4 tree in the paper's 32H x 16H x 16H domain at H = 512 finest
+    cells (six levels, coarse H/16): the finest lattice has 2.1e9 blocks and
+    the finest box 1.1e12 cells, so dense host maps or masks could not be
+    built; the plan holds the tree's own extent and finishes in seconds."""
+    import time
+    H = 512.0
+    arr = _paper_tree(lt, 4, H, (8 * H, 8 * H, 8 * H))
+    t0 = time.time()
+    plan = lt.plan_levels(arr, refine={"band": [0, 256, 128, 64, 32, 16], "wake": [0, 0, 0, 1024, 0, 0]},
+                          nx=int(32 * H), ny=int(16 * H), nz=int(16 * H), u_in=0.05, re_h=2500.0, block_edge=8,
+                          levels=6, storage="fp16")
+    dt = time.time() - t0
+    assert plan["lattice"][5] == (2048, 1024, 1024)
+    assert 0.99 * 512 * 256 * 256 < plan["leaf_cells"][0] < 512 * 256 * 256  # dense level 0, refined around the tree
+    assert all(c > 0 for c in plan["leaf_cells"])
+    assert plan["solid_cells"] > 1_000_000 and plan["links"] > plan["solid_cells"] // 10
+    # 27 deviations of 2 bytes per stored cell (blocks + the spare block per level)
+    cells = 512 * 256 * 256 + sum((b + 1) * 512 for b in plan["blocks"][1:])
+    assert abs(plan["pop_bytes"] - 54 * cells) < 0.01 * plan["pop_bytes"] + 64 * 1024 * 6
+    print(f"  H/512 plan: {dt:.1f} s, leaf cells {sum(plan['leaf_cells']):,}, {plan['pop_bytes'] / 1e9:.2f} GB")
+
+
 def test_plan_rejects_refinement_at_the_faces(lt):
     b = O.build_tree(O.cfg1_tree_params(), 0.0, [40.0, 20.0, 32.0])
     with pytest.raises(lt.LbmError) as e:
