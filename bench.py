@@ -267,52 +267,107 @@ def amr4_leg(lt, torch, steps, warmup):
 # 4H long on level 1 (H/32), two levels coarser than the surface as in the
 # paper (H/256 wake against H/1024 surface).  Re_H = 2500, the lowest of the
 # paper's runs.
-PAPER = dict(n=4, H=128.0, re_h=2500.0, band=[0, 32, 16, 8], wake=[0, 512, 0, 0])
+# The n = 4 tree of Table 2 in the paper's 32H x 16H x 16H domain on 8^3
+# blocks with a dense coarse level at H/16: at H = 128 finest cells (four
+# levels, wake H/32), and at the paper's surface resolution H/1024 (seven
+# levels, wake at the paper's H/256 for 2H downstream).  Bands in finest cells.
+PAPER = dict(n=4, H=128.0, re_h=2500.0, levels=4, band=[0, 32, 16, 8], wake=[0, 512, 0, 0], storage="fp32",
+             wake_level=1)
+PAPER1024 = dict(n=4, H=1024.0, re_h=2500.0, levels=7, band=[0, 512, 256, 128, 64, 32, 16],
+                 wake=[0, 0, 0, 0, 2048, 0, 0], storage="fp16", wake_level=4, shapes_from="paper H/128")
 
 
-def paper_tree_leg(lt, torch, steps, warmup):
-    """The n = 4 tree of Table 2 in the paper's domain at H = 128: device memory,
-    cell counts per level, MLUPS and C_D (graph replay, FP32, tuned tiles)."""
-    import tempfile
-    stream = STREAM
-    H = PAPER["H"]
-    nx, ny, nz = int(32 * H), int(16 * H), int(16 * H)
+def _paper_tree(lt, cfg):
+    H = cfg["H"]
     wq = 0.5 ** 0.5
-    p = lt.tree_params(2, PAPER["n"] - 1, 100.0, 30.0, [0.8, 0.8], [wq, wq], [0.0, 0.0], [30.0, -30.0],
+    p = lt.tree_params(2, cfg["n"] - 1, 100.0, 30.0, [0.8, 0.8], [wq, wq], [0.0, 0.0], [30.0, -30.0],
                        [137.0, 137.0])
     arr = lt.tree_generate(p)
     lt.tree_place(arr, H, [8 * H, 8 * H, 8 * H])
-    g = lt.Grid(nx, ny, nz, u_in=U_IN, re_h=PAPER["re_h"], block_edge=8, levels=4, storage="fp32", drag_every=1,
-                flags=lt.LBM_F_GRAPH, stream=stream.cuda_stream)
+    return arr
+
+
+def _shapes_of_paper128(lt, storage):
+    """Launch shapes the autotuner picks on the paper tree at H = 128 (four
+    levels of 8^3 blocks, the same kernels), for grids too large to search:
+    one candidate there costs milliseconds, at H/1024 seconds."""
+    import tempfile
+    H = PAPER["H"]
+    g = lt.Grid(int(32 * H), int(16 * H), int(16 * H), u_in=U_IN, re_h=PAPER["re_h"], block_edge=8,
+                levels=PAPER["levels"], storage=storage, drag_every=1, stream=STREAM.cuda_stream)
+    g.set_geometry(_paper_tree(lt, PAPER), refine={"band": PAPER["band"], "wake": PAPER["wake"]})
+    g.autotune(os.path.join(tempfile.mkdtemp(), "tune.txt"))
+    i = g.info()
+    g.close()
+    return i["threads"], i["tile_cells"], i["occ_even"], i["occ_odd"], i["xcd_group"]
+
+
+def paper_tree_leg(lt, torch, steps, warmup, cfg=PAPER):
+    """The n = 4 tree of Table 2 in the paper's domain (cfg: PAPER at H = 128,
+    PAPER1024 at the paper's H/1024): device memory, cell counts per level,
+    set-up time, MLUPS and C_D (graph replay, tuned tiles)."""
+    import tempfile
+    stream = STREAM
+    H, L = cfg["H"], cfg["levels"]
+    nx, ny, nz = int(32 * H), int(16 * H), int(16 * H)
+    arr = _paper_tree(lt, cfg)
+    shapes = None
+    if TUNE and cfg.get("shapes_from"):
+        t1 = time.time()
+        shapes = _shapes_of_paper128(lt, cfg["storage"])
+        print(f"paper tree H/{int(H)}: launch shapes {shapes} tuned on the tree at H/128 in {time.time() - t1:.1f} s",
+              file=sys.stderr, flush=True)
+    g = lt.Grid(nx, ny, nz, u_in=U_IN, re_h=cfg["re_h"], block_edge=8, levels=L, storage=cfg["storage"],
+                drag_every=1, flags=lt.LBM_F_GRAPH, stream=stream.cuda_stream)
     t0 = time.time()
-    g.set_geometry(arr, refine={"band": PAPER["band"], "wake": PAPER["wake"]})
+    g.set_geometry(arr, refine={"band": cfg["band"], "wake": cfg["wake"]})
     setup = time.time() - t0
-    if TUNE:
+    print(f"paper tree H/{int(H)}: geometry and {L}-level grid set up in {setup:.1f} s", file=sys.stderr, flush=True)
+    if shapes is not None:
+        # applied through a one-entry tune cache keyed as the library keys it
+        path = os.path.join(tempfile.mkdtemp(), "tune.txt")
+        key = f"nx{nx}_ny{ny}_nz{nz}_B8_L{L}_S{lt.STORAGE[cfg['storage']]}_links{g.info()['links']}"
+        with open(path, "w") as f:
+            f.write(key + " " + " ".join(str(int(v)) for v in shapes) + "\n")
+        g.autotune(path)
+    elif TUNE:
+        t1 = time.time()
         g.autotune(TUNE_CACHE or os.path.join(tempfile.mkdtemp(), "tune.txt"))
+        print(f"paper tree H/{int(H)}: launch shapes tuned in {time.time() - t1:.1f} s", file=sys.stderr, flush=True)
     info = g.info()
-    leaf = info["updated_cells"][:4]
-    upd = sum(leaf[l] << l for l in range(4))
-    work = sum(info["collided_cells"][l] << l for l in range(4))
+    if shapes is not None:
+        assert (info["threads"], info["tile_cells"]) == tuple(shapes[:2])
+    leaf = info["updated_cells"][:L]
+    upd = sum(leaf[l] << l for l in range(L))
+    work = sum(info["collided_cells"][l] << l for l in range(L))
     g.step(warmup)
     g.drag()
     torch.cuda.synchronize()
+    print(f"paper tree H/{int(H)}: {warmup} warm-up coarse steps done", file=sys.stderr, flush=True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     g.step(steps)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    print(f"paper tree H/{int(H)}: {steps} timed coarse steps in {ms:.1f} ms", file=sys.stderr, flush=True)
     d = g.drag()
     g.close()
     b = lt.branches_to_numpy(arr)
+    bpc = 216.0 if cfg["storage"] == "fp32" else 108.0
+    wake_dx = int(H) >> (L - 1 - cfg["wake_level"])
     return {"workload": f"paper binary tree n=4 (Table 2), domain 32Hx16Hx16H = {nx}x{ny}x{nz} finest cells, "
-                        f"COM (8H,8H,8H), 8^3 blocks, 4 levels H/16..H/128, wake H/32, Re_H=2500, FP32",
-            "coarse_steps": steps, "mlups": round(upd * steps / (ms * 1e-3) / 1e6, 1),
-            "ms_per_coarse_step": round(ms / steps, 4),
-            "step_hbm_frac": round(216.0 * work * steps / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                        f"COM (8H,8H,8H), 8^3 blocks, {L} levels H/16..H/{int(H)}, wake H/{wake_dx}, "
+                        f"Re_H={cfg['re_h']:g}, {cfg['storage'].upper()}",
+            "coarse_steps": steps, "finest_steps_per_coarse_step": 1 << (L - 1),
+            "mlups": round(upd * steps / (ms * 1e-3) / 1e6, 1), "ms_per_coarse_step": round(ms / steps, 4),
+            "step_hbm_frac": round(bpc * work * steps / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
             "cd": round(d["cd"], 5), "d0_over_h": round(b[0, 6] / info["height"], 4),
-            "grid": {"blocks": info["blocks"][:4], "leaf_fluid_cells": leaf, "updates_per_coarse_step": upd,
-                     "total_leaf_cells": int(sum(info["active_cells"][:4])), "links": info["links"],
+            "launch_shapes": {"threads": info["threads"], "tile": info["tile_cells"], "occ_even": info["occ_even"],
+                              "occ_odd": info["occ_odd"], "xcd_group": info["xcd_group"],
+                              "tuned_on": cfg.get("shapes_from") or "this grid"},
+            "grid": {"blocks": info["blocks"][:L], "leaf_fluid_cells": leaf, "updates_per_coarse_step": upd,
+                     "total_leaf_cells": int(sum(info["active_cells"][:L])), "links": info["links"],
                      "device_gb": round(info["device_bytes"] / 1e9, 2), "setup_s": round(setup, 1),
                      "finest_dx_over_h": round(1.0 / H, 5)}}
 
@@ -575,8 +630,10 @@ def main():
     ap.add_argument("--amr-only", action="store_true", help="run only the three-level AMR leg (profiling)")
     ap.add_argument("--amr4-steps", type=int, default=16, help="timed coarse steps of the four-level leg")
     ap.add_argument("--paper-steps", type=int, default=16, help="timed coarse steps of the paper-tree leg")
+    ap.add_argument("--paper1024-steps", type=int, default=4,
+                    help="timed coarse steps (64 finest steps each) of the paper-tree leg at H/1024 (--legs paper1024)")
     ap.add_argument("--legs", default=None,
-                    help="comma list of legs to run alone and print (amr3, amr4, paper): profiling")
+                    help="comma list of legs to run alone and print (amr3, amr4, paper, paper1024)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the drag-surrogate leg")
     ap.add_argument("--surrogate-trees", type=int, default=1_000_000)
     ap.add_argument("--surrogate-scale", choices=list(SURROGATE_SWEEPS), default="small",
@@ -625,7 +682,8 @@ def main():
     if args.legs:
         legs = {"amr3": lambda: amr_leg(lt, torch, args.amr_steps, 4),
                 "amr4": lambda: amr4_leg(lt, torch, args.amr4_steps, 2),
-                "paper": lambda: paper_tree_leg(lt, torch, args.paper_steps, 2)}
+                "paper": lambda: paper_tree_leg(lt, torch, args.paper_steps, 2),
+                "paper1024": lambda: paper_tree_leg(lt, torch, args.paper1024_steps, 1, PAPER1024)}
         print(json.dumps({k: legs[k]() for k in args.legs.split(",")}), flush=True)
         return
     if args.sweep_only:
