@@ -275,6 +275,11 @@ PAPER = dict(n=4, H=128.0, re_h=2500.0, levels=4, band=[0, 32, 16, 8], wake=[0, 
              wake_level=1)
 PAPER1024 = dict(n=4, H=1024.0, re_h=2500.0, levels=7, band=[0, 512, 256, 128, 64, 32, 16],
                  wake=[0, 0, 0, 0, 2048, 0, 0], storage="fp16", wake_level=4, shapes_from="paper H/128")
+# the paper's other two trees at their surface resolutions: n = 6 at H/1024,
+# n = 8 at H/2048 (eight levels, coarse H/16)
+PAPER1024_N6 = dict(PAPER1024, n=6)
+PAPER2048_N8 = dict(n=8, H=2048.0, re_h=2500.0, levels=8, band=[0, 1024, 512, 256, 128, 64, 32, 16],
+                    wake=[0, 0, 0, 0, 4096, 0, 0, 0], storage="fp16", wake_level=4, shapes_from="paper H/128")
 
 
 def _paper_tree(lt, cfg):
@@ -356,7 +361,7 @@ def paper_tree_leg(lt, torch, steps, warmup, cfg=PAPER):
     b = lt.branches_to_numpy(arr)
     bpc = 216.0 if cfg["storage"] == "fp32" else 108.0
     wake_dx = int(H) >> (L - 1 - cfg["wake_level"])
-    return {"workload": f"paper binary tree n=4 (Table 2), domain 32Hx16Hx16H = {nx}x{ny}x{nz} finest cells, "
+    return {"workload": f"paper binary tree n={cfg['n']} (Table 2), domain 32Hx16Hx16H = {nx}x{ny}x{nz} finest cells, "
                         f"COM (8H,8H,8H), 8^3 blocks, {L} levels H/16..H/{int(H)}, wake H/{wake_dx}, "
                         f"Re_H={cfg['re_h']:g}, {cfg['storage'].upper()}",
             "coarse_steps": steps, "finest_steps_per_coarse_step": 1 << (L - 1),
@@ -633,7 +638,8 @@ def main():
     ap.add_argument("--paper1024-steps", type=int, default=4,
                     help="timed coarse steps (64 finest steps each) of the paper-tree leg at H/1024 (--legs paper1024)")
     ap.add_argument("--legs", default=None,
-                    help="comma list of legs to run alone and print (amr3, amr4, paper, paper1024)")
+                    help="comma list of legs to run alone and print (amr3, amr4, paper, paper1024, paper1024n6, "
+                         "paper2048n8)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the drag-surrogate leg")
     ap.add_argument("--surrogate-trees", type=int, default=1_000_000)
     ap.add_argument("--surrogate-scale", choices=list(SURROGATE_SWEEPS), default="small",
@@ -683,7 +689,9 @@ def main():
         legs = {"amr3": lambda: amr_leg(lt, torch, args.amr_steps, 4),
                 "amr4": lambda: amr4_leg(lt, torch, args.amr4_steps, 2),
                 "paper": lambda: paper_tree_leg(lt, torch, args.paper_steps, 2),
-                "paper1024": lambda: paper_tree_leg(lt, torch, args.paper1024_steps, 1, PAPER1024)}
+                "paper1024": lambda: paper_tree_leg(lt, torch, args.paper1024_steps, 1, PAPER1024),
+                "paper1024n6": lambda: paper_tree_leg(lt, torch, args.paper1024_steps, 1, PAPER1024_N6),
+                "paper2048n8": lambda: paper_tree_leg(lt, torch, max(1, args.paper1024_steps // 2), 1, PAPER2048_N8)}
         print(json.dumps({k: legs[k]() for k in args.legs.split(",")}), flush=True)
         return
     if args.sweep_only:

@@ -447,25 +447,30 @@ lbm_status build_levels(const lbm_grid_desc &d, int B, int L, const lbm_branch *
             return -1;
         return lat[l].get(x / B, y / B, z / B);
     };
+    // the kinds of the blocks that the cell window [x - r, x + r]^3 meets
+    // (every block of that range holds a cell of the window): 1 when one of
+    // them is a leaf (or, with refined_too, refined)
+    auto fdiv = [&](int v) { return v >= 0 ? v / B : -((-v + B - 1) / B); };
+    auto window_meets = [&](int l, int x, int y, int z, int r, bool refined_too) -> bool {
+        const int x0 = fdiv(x - r), x1 = fdiv(x + r), y0 = fdiv(y - r), y1 = fdiv(y + r);
+        const int z0 = fdiv(z - r), z1 = fdiv(z + r);
+        for (int bz = z0; bz <= z1; ++bz)
+            for (int by = y0; by <= y1; ++by)
+                for (int bx = x0; bx <= x1; ++bx) {
+                    const int8_t v = lat[l].get(bx, by, bz);
+                    if (v == 1 || (refined_too && v == 2))
+                        return true;
+                }
+        return false;
+    };
     auto cell_class = [&](int l, int x, int y, int z) -> int {
         const int8_t m = block_of(l, x, y, z);
         if (m == 1)
             return 1;
-        if (m == 2) {
-            for (int dz = -2; dz <= 2; ++dz)
-                for (int dy = -2; dy <= 2; ++dy)
-                    for (int dx = -2; dx <= 2; ++dx)
-                        if (block_of(l, x + dx, y + dy, z + dz) == 1)
-                            return 2;
-            return 3;
-        }
-        if (m == 3) {
-            for (int k = 0; k < 27; ++k) {
-                const int8_t v = block_of(l, x + k % 3 - 1, y + (k / 3) % 3 - 1, z + k / 9 - 1);
-                if (v == 1 || v == 2)
-                    return 4;
-            }
-        }
+        if (m == 2)  // band: a leaf cell within Chebyshev distance 2
+            return window_meets(l, x, y, z, 2, false) ? 2 : 3;
+        if (m == 3)  // ghost: a leaf or refined cell among the 26 neighbours
+            return window_meets(l, x, y, z, 1, true) ? 4 : 0;
         return 0;
     };
     const int cells = B * B * B;

@@ -145,6 +145,15 @@ def test_planned_block_maps_match_oracle(lt, case):
     for l in range(case["L"]):
         assert np.array_equal(plan["maps"][l].astype(np.uint8), sim.block_map(l)), f"level {l}"
     solid = O.voxelize(b, nx, ny, nz)
+    # cell classes: leaf cells (class active), and the cells each level
+    # sub-step collides (active and band, minus the finest level's solid)
+    for l in range(case["L"]):
+        cls = sim.classes(l)
+        sol = solid.astype(bool) if l == case["L"] - 1 else np.zeros(cls.shape, bool)
+        assert plan["leaf_cells"][l] == int((cls == O.CLS_ACTIVE).sum()), f"level {l}"
+        assert plan["updated_cells"][l] == int(((cls == O.CLS_ACTIVE) & ~sol).sum()), f"level {l}"
+        assert plan["collided_cells"][l] == int((((cls == O.CLS_ACTIVE) | (cls == O.CLS_BAND)) & ~sol).sum()), \
+            f"level {l}"
     assert plan["solid_cells"] == int(solid.sum())
     assert plan["links"] == len(O.links(b, solid, nx, ny, nz)["cell"])
 
