@@ -775,6 +775,7 @@ def main():
     if not args.no_amr:
         out["amr_4level_fp16_turbulent"] = amr4_leg(lt, torch, args.amr4_steps, 2)
         out["paper_tree_n4"] = paper_tree_leg(lt, torch, args.paper_steps, 2)
+        out["paper_tree_n4_h1024"] = paper_tree_leg(lt, torch, args.paper1024_steps, 1, PAPER1024)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(lt, torch, args.surrogate_trees, scale=args.surrogate_scale)
     print(json.dumps(out), flush=True)

@@ -268,13 +268,17 @@ lbm_status lbm_get_fields(lbm_grid *g, int32_t level, double *rho, double *u);
 
 /* Finest-level solid mask (uint8 over the finest box) and the link table in
  * (cell, direction) order: cell index over the finest box, direction pointing
- * into the solid, q, branch id. */
+ * into the solid, q, branch id.  The library itself holds the mask only over
+ * the box bounding the tree; lbm_get_solid writes the whole finest box
+ * (nx * ny * nz bytes, caller-owned), so it suits boxes that fit host memory. */
 lbm_status lbm_get_solid(lbm_grid *g, uint8_t *solid);
 lbm_status lbm_get_links(lbm_grid *g, int64_t cap, int64_t *cell, int8_t *dir, double *q,
                          int32_t *branch, int64_t *n);
 
-/* Block map of level l over its block lattice (nbx_l * nby_l * nbz_l int8):
- * 0 none, 1 leaf, 2 refined (covered by level l+1), 3 ghost storage. */
+/* Block map of level l over its block lattice (nbx_l * nby_l * nbz_l int8,
+ * caller-owned): 0 none, 1 leaf, 2 refined (covered by level l+1), 3 ghost
+ * storage.  The library holds each level above 0 only over the blocks around
+ * its refined region and writes zeros elsewhere. */
 lbm_status lbm_get_block_map(lbm_grid *g, int32_t level, int8_t *map);
 
 /* ---- learned per-branch drag surrogate ---------------------------------------
@@ -418,7 +422,8 @@ typedef struct {
 } lbm_plan;
 
 /* maps may be NULL; otherwise maps[l] (may be NULL) receives level l's block
- * map (lattice[l] product int8, values as lbm_get_block_map).  Errors as
+ * map (lattice[l] product int8, values as lbm_get_block_map; pass NULL for
+ * lattices too large for host memory: the plan itself does not need them).  Errors as
  * lbm_create_grid and lbm_set_geometry (LBM_E_INVALID), the message in
  * lbm_last_error(NULL). */
 lbm_status lbm_plan_levels(const lbm_grid_desc *d, const lbm_branch *b, int32_t n_b,
