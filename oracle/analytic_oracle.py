@@ -24,6 +24,15 @@ an inflow turbulence intensity of 8 % it is Re_cr = 1.4e4, which places the
 crisis near Re_H = 1.5e5.  The paper reports both onsets (Sec. 4.1, 4.2).
 Between the two intensities Re_cr is interpolated log-linearly in I_u.
 
+Friction split (Eqs. (3), (5), (6)).  A branch's friction drag is
+F_f = C_f(Re_D) (rho U^2 / 2) L D sin^3(alpha) (Eq. (3)); C_F-est sums it over
+the branches over (rho U^2 / 2) A_x (Eq. (5)) and C_P-est = C_D-est - C_F-est
+(Eq. (6)).  The paper takes C_f of a cylinder normal to the flow from its own
+LBM runs and prints no values, so C_f here is a table the caller passes: nodes
+(log10 Re_D, C_f) joined by power laws (straight lines in log10 Re_D against
+ln C_f), and the first and last segments' power laws continued below and above
+the table.
+
 Frontal area for the many-tree sweeps: the union of the branches' projected
 capsules is rasterised on the (y, z) plane.  A capsule is the branch axis
 swept by the branch radius; its projection along x is the 2D capsule of the
@@ -92,3 +101,31 @@ def projected_area(b, h):
         d2 = (Y - t * dy) ** 2 + (Z - t * dz) ** 2
         cover[np.ix_(jz, jy)] |= d2 <= r[k] ** 2
     return cover.sum() * h * h
+
+
+def cylinder_cf(re, lg_nodes, cf_nodes):
+    """C_f(Re_D) of a cylinder normal to the flow from the table (lg_nodes
+    strictly increasing log10 Re_D, cf_nodes > 0): the power law through the
+    two nodes of the segment that holds log10 Re_D, the end segments continued
+    past the table."""
+    lg_nodes = np.asarray(lg_nodes, dtype=np.float64)
+    ln_cf = np.log(np.asarray(cf_nodes, dtype=np.float64))
+    lg = np.log10(np.asarray(re, dtype=np.float64))
+    i = np.clip(np.searchsorted(lg_nodes, lg, side="right") - 1, 0, len(lg_nodes) - 2)
+    t = (lg - lg_nodes[i]) / (lg_nodes[i + 1] - lg_nodes[i])
+    return np.exp((1.0 - t) * ln_cf[i] + t * ln_cf[i + 1])
+
+
+def tree_cf_est(b, re_h, height, area_x, table):
+    """C_F-est of Eq. (5) for one tree at each Re_H in re_h: the friction
+    forces of Eq. (3) summed over the branches, with C_f from table =
+    (lg_nodes, cf_nodes)."""
+    L, D, alpha, _ = branch_geometry(b)
+    w = L * D * np.sin(alpha) ** 3
+    re_h = np.atleast_1d(np.asarray(re_h, dtype=np.float64))
+    return np.array([np.sum(cylinder_cf(r * D / height, *table) * w) for r in re_h]) / area_x
+
+
+def tree_cp_est(b, re_h, height, area_x, table, intensity=0.0):
+    """C_P-est of Eq. (6): the total estimate less the friction estimate."""
+    return tree_cd_est(b, re_h, height, area_x, intensity) - tree_cf_est(b, re_h, height, area_x, table)

@@ -107,6 +107,47 @@ def test_single_normal_cylinder_reduces_to_its_drag_coefficient():
         assert np.allclose(c, want, rtol=1e-12, atol=1e-15)
 
 
+def test_friction_estimate_of_a_hand_tree_with_a_constant_cf():
+    """Eqs. (3), (5) with C_f = 0.3 at every Re_D on three branches: a vertical
+    one (L D = 1, sin^3 = 1), one at 45 degrees to the flow (L = sqrt 2,
+    D = 0.25, sin^3 = 2^(-3/2): L D sin^3 = 1/8) and one along the flow (no
+    share); A_x = 2 gives 0.3 * 1.125 / 2."""
+    b = np.array([_capsule((0, 0, 0), (0, 0, 2), 0.5), _capsule((0, 0, 2), (1, 0, 3), 0.25),
+                  _capsule((0, 0, 2), (1.5, 0, 2), 0.2)])
+    table = ([1.0, 2.0, 4.0], [0.3, 0.3, 0.3])
+    got = A.tree_cf_est(b, [1e2, 1e5, 1e8], 3.0, 2.0, table)
+    assert np.allclose(got, 0.16875, rtol=1e-13)
+
+
+def test_friction_table_is_a_power_law_between_and_beyond_its_nodes():
+    """A table sampled from C_f = 4 Re^(-1/2) reproduces that law everywhere,
+    below and above its nodes too: one normal branch with A_x = L D and
+    D / H = 1/10 gives C_F-est = 4 (Re_H / 10)^(-1/2): 4 at Re_H = 10,
+    4 / sqrt(30) = 0.7302967433 at 300, 0.04 at 1e5.  A table with a kink
+    (C_f = 1, 0.1, 0.1 at Re_D = 1, 10, 1000) takes the geometric mean
+    sqrt(0.1) at Re_D = sqrt(10), stays at 0.1 above, and continues the first
+    slope to 10 at Re_D = 0.1."""
+    L, D, H = 10.0, 1.0, 10.0
+    b = np.array([_capsule((0, 0, 0), (0, 0, L), D)])
+    law = ([1.0, 2.0, 3.0], [4.0 / math.sqrt(10.0), 0.4, 4.0 / math.sqrt(1000.0)])
+    got = A.tree_cf_est(b, [10.0, 300.0, 1e5], H, L * D, law)
+    assert np.allclose(got, [4.0, 0.7302967433, 0.04], rtol=1e-9)
+    kink = ([0.0, 1.0, 3.0], [1.0, 0.1, 0.1])
+    got = A.cylinder_cf([math.sqrt(10.0), 100.0, 1e4, 0.1], *kink)
+    assert np.allclose(got, [0.316227766, 0.1, 0.1, 10.0], rtol=1e-9)
+
+
+def test_pressure_estimate_is_the_total_less_the_friction():
+    """Eq. (6) on one normal branch at Re_D = 1000: C_D-est = 1.1 (the
+    subcritical correlation), C_F-est = 4 / sqrt(1000) = 0.1264911064 from the
+    power-law table, so C_P-est = 0.9735088936."""
+    L, D, H = 10.0, 1.0, 10.0
+    b = np.array([_capsule((0, 0, 0), (0, 0, L), D)])
+    law = ([1.0, 2.0, 3.0], [4.0 / math.sqrt(10.0), 0.4, 4.0 / math.sqrt(1000.0)])
+    got = A.tree_cp_est(b, [1e4], H, L * D, law)
+    assert np.allclose(got, 0.9735088936, rtol=1e-7)
+
+
 def test_crisis_of_the_paper_trees_starts_near_3e6_and_softens_with_n():
     """The paper finds the crisis near Re_H ~ 3e6 for every n and a less steep
     drop as the number of generations n grows (Sec. 4.1).  Onset here: the
