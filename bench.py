@@ -500,10 +500,13 @@ def sweep_trees(lt, torch, m, env, n_trees, chunk=1 << 17):
                             jitter=5.0, seed=0)
     re_h = 10.0 ** np.linspace(3.0, 9.0, 25)
     orders = 1 + (np.arange(n_trees) % 6)
-    sweep_ms = analytic_ms = area_ms = gen_s = 0.0
+    from paper_2603_27954_amd.cylinder import load_cf_table
+    cf_table = load_cf_table()
+    sweep_ms = analytic_ms = split_ms = area_ms = gen_s = 0.0
     n_branch = 0
     sum_s = np.zeros(len(re_h))
     sum_a = np.zeros(len(re_h))
+    sum_f = np.zeros(len(re_h))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for c0 in range(0, n_trees, chunk):
         o = orders[c0:c0 + chunk]
@@ -530,21 +533,31 @@ def sweep_trees(lt, torch, m, env, n_trees, chunk=1 << 17):
         e1.record(stream)
         e1.synchronize()
         analytic_ms += e0.elapsed_time(e1)
+        # the friction split of Eqs. (3), (5), (6) with the LBM C_f table
+        cdf, cff, cpf = torch.empty_like(cd), torch.empty_like(cd), torch.empty_like(cd)
+        e0.record(stream)
+        lt.analytic_split(rd, sd, area, cdf, cff, re_h, cf_table, 0.0, cpf, stream.cuda_stream)
+        e1.record(stream)
+        e1.synchronize()
+        split_ms += e0.elapsed_time(e1)
         n_branch += len(rec)
         sum_s += cd.double().sum(0).cpu().numpy()
         sum_a += cda.double().sum(0).cpu().numpy()
-        del rd, sd, area, cd, cda
+        sum_f += cff.double().sum(0).cpu().numpy()
+        del rd, sd, area, cd, cda, cdf, cff, cpf
     inferences = n_branch * len(re_h)
     tflops = MLP_FLOP * inferences / (sweep_ms * 1e-3) / 1e12
     return {"trees": n_trees, "branches": n_branch, "re_h": [1e3, 1e9, len(re_h)], "inferences": inferences,
             "surrogate_ms": round(sweep_ms, 2), "inferences_per_s": round(inferences / (sweep_ms * 1e-3), 1),
-            "analytic_ms": round(analytic_ms, 2), "frontal_area_ms": round(area_ms, 2),
+            "analytic_ms": round(analytic_ms, 2), "analytic_split_ms": round(split_ms, 2),
+            "frontal_area_ms": round(area_ms, 2),
             "host_tree_generation_s": round(gen_s, 2),
             "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4),
                          "flop_per_inference": MLP_FLOP, "dtype": "bf16 operands, fp32 accumulate"},
             "mean_cd_surrogate": [round(v / n_trees, 4) for v in sum_s],
-            "mean_cd_analytic": [round(v / n_trees, 4) for v in sum_a]}
+            "mean_cd_analytic": [round(v / n_trees, 4) for v in sum_a],
+            "mean_cf_analytic": [round(v / n_trees, 5) for v in sum_f]}
 
 
 def sweep_only_leg(lt, torch, n_trees):

@@ -178,7 +178,12 @@ lbm_status lbm_create_grid(const lbm_grid_desc *d, lbm_grid **out);
  * block grid and its refinement (refine may be NULL when levels == 1), uploads
  * everything and initialises f = f_eq(1, u_in) in fluid (Sec. 2.3).
  * Fails with LBM_E_INVALID when a branch or refined region comes within one
- * block of the box faces.  device_bytes_out (may be NULL) receives the device
+ * block of the box faces (two cells on one level).  One exception, on one
+ * level with periodic y and z faces: a branch parallel to y whose axis runs
+ * past both y faces by its radius plus two cells is the same at every y of
+ * the box, so the periodic wrap makes it an infinitely long cylinder (the
+ * single-cylinder runs behind the C_f table of lbm_analytic_split).
+ * device_bytes_out (may be NULL) receives the device
  * memory the library allocated (memory bound with lbm_bind_memory excluded). */
 lbm_status lbm_set_geometry(lbm_grid *g, const lbm_branch *b, int32_t n_b,
                             const lbm_refine_desc *refine, size_t *device_bytes_out);
@@ -383,6 +388,26 @@ lbm_status lbm_surrogate_sweep(lbm_mlp *m, const lbm_sweep_desc *d);
 /* The analytic model of Eqs. (2) and (4), C_D = sum_b C_d(Re_b) L_b D_b
  * sin^3(alpha_b) / A_x, on the same inputs (re_d_lo / re_d_hi unused). */
 lbm_status lbm_analytic_sweep(const lbm_sweep_desc *d, void *stream);
+
+/* Friction coefficient C_f(Re_D) of a cylinder normal to the flow, as a table
+ * (Sec. 2.4: the paper takes it from its own LBM runs of single cylinders and
+ * prints no values).  Between consecutive nodes C_f follows the power law
+ * through them (linear in log10 Re_D against ln C_f); below the first node and
+ * above the last the end segments' power laws continue. */
+typedef struct {
+    const double *lg_re;  /* host: n nodes of log10 Re_D, strictly increasing */
+    const double *cf;     /* host: n values of C_f, finite and > 0 */
+    int32_t n;            /* 2 .. 32 */
+} lbm_cf_table;
+
+/* The friction / pressure split of the analytic model, Eqs. (3), (5), (6):
+ * d->cd receives C_D-est as lbm_analytic_sweep does, cf (device, n_trees x
+ * n_re floats, row per tree) C_F-est = sum_b C_f(Re_b) L_b D_b sin^3(alpha_b)
+ * / A_x with C_f from t, and cp (device, same shape; may be NULL) C_P-est =
+ * C_D-est - C_F-est.  One pass over the branch records for all three.
+ * LBM_E_INVALID for a bad description or table (nothing launched); ordered on
+ * stream, returns when done. */
+lbm_status lbm_analytic_split(const lbm_sweep_desc *d, const lbm_cf_table *t, float *cf, float *cp, void *stream);
 
 /* Host-only surrogate features of a tree's branches at Re_H (rows of 5 floats
  * in feat): log10(Re_H D / H), the angle alpha between the branch axis and the

@@ -135,6 +135,7 @@ def lib():
         "lbm_frontal_area": [_P, _P, C.c_int32, C.c_double, _P, _P],
         "lbm_surrogate_sweep": [_P, _P],
         "lbm_analytic_sweep": [_P, _P],
+        "lbm_analytic_split": [_P, _P, _P, _P, _P],
         "lbm_branch_features": [C.POINTER(Branch), C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_float), _dp],
         "lbm_inflow_modes": [C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp],
         "lbm_plan_levels": [C.POINTER(GridDesc), C.POINTER(Branch), C.c_int32, C.POINTER(RefineDesc),
@@ -297,6 +298,10 @@ class SweepDesc(C.Structure):
                 ("cd", _P)]
 
 
+class CfTable(C.Structure):
+    _fields_ = [("lg_re", _dp), ("cf", _dp), ("n", C.c_int32)]
+
+
 def tree_batch(params, seed0, orders):
     """Branch records (n_branches, 10) float32 and offsets (n_trees + 1) int64
     of seeded trees (lbm_tree_batch)."""
@@ -336,6 +341,24 @@ def analytic_sweep(rec, start, area, cd, re_h, intensity=0.0, stream=None):
     d, keep = _sweep_desc(rec, start, area, cd, re_h, intensity, (1.0, 1.0))
     _check(lib().lbm_analytic_sweep(C.byref(d), stream))
     return cd
+
+
+def analytic_split(rec, start, area, cd, cf, re_h, table, intensity=0.0, cp=None, stream=None):
+    """C_D-est into cd, C_F-est into cf and (when given) C_P-est into cp, all
+    torch device tensors (n_trees, n_re); table = (log10 Re_D nodes, C_f)."""
+    d, keep = _sweep_desc(rec, start, area, cd, re_h, intensity, (1.0, 1.0))
+    need = (start.shape[0] - 1) * len(keep)
+    for t in (cd, cf) + ((cp,) if cp is not None else ()):
+        if t.element_size() != 4 or t.numel() < need:
+            raise ValueError(f"outputs: float32 device tensors of n_trees x n_re = {need} values")
+    lg = np.ascontiguousarray(table[0], dtype=np.float64)
+    cv = np.ascontiguousarray(table[1], dtype=np.float64)
+    if lg.shape != cv.shape:
+        raise ValueError("table: as many C_f values as nodes")
+    t = CfTable(_dptr(lg), _dptr(cv), len(lg))
+    _check(lib().lbm_analytic_split(C.byref(d), C.byref(t), _dptr_t(cf), _dptr_t(cp) if cp is not None else None,
+                                    stream))
+    return cd, cf, cp
 
 
 class Mlp:

@@ -255,12 +255,22 @@ static void branch_extent(const Shape &s, int a, double *lo, double *hi)
     *hi = std::max(std::max(p0[a], p1[a]) + disc, p1[a] + s.r);
 }
 
-bool tree_fits_box(const lbm_branch *b, int n, int nx, int ny, int nz, double margin)
+bool spans_y(const lbm_branch &b, int ny, double margin)
+{
+    const double r = 0.5 * b.diameter;
+    return b.p0[0] == b.p1[0] && b.p0[2] == b.p1[2] && std::min(b.p0[1], b.p1[1]) <= -r - margin &&
+           std::max(b.p0[1], b.p1[1]) >= ny + r + margin;
+}
+
+bool tree_fits_box(const lbm_branch *b, int n, int nx, int ny, int nz, double margin, bool y_spans_ok)
 {
     const double ext[3] = {(double)nx, (double)ny, (double)nz};
     for (int i = 0; i < n; ++i) {
         const Shape s = make_shape(b[i]);
+        const bool span = y_spans_ok && spans_y(b[i], ny, margin);
         for (int a = 0; a < 3; ++a) {
+            if (a == 1 && span)
+                continue;
             double lo, hi;
             branch_extent(s, a, &lo, &hi);
             if (lo < margin || hi > ext[a] - margin)

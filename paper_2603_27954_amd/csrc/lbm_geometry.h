@@ -46,7 +46,13 @@ struct SolidMask {
 int tree_generate(const lbm_tree_params &p, std::vector<lbm_branch> &out);
 double tree_height(const lbm_branch *b, int n);
 void tree_place(lbm_branch *b, int n, double target_h, const double com[3]);
-bool tree_fits_box(const lbm_branch *b, int n, int nx, int ny, int nz, double margin);
+// A branch parallel to y whose axis runs past both y faces by its radius plus
+// margin: within the box it is the same at every y, so a periodic y wrap keeps
+// it whole (an infinitely long cylinder).
+bool spans_y(const lbm_branch &b, int ny, double margin);
+// every branch at least margin inside the box; with y_spans_ok, branches that
+// span y are exempt from the y test
+bool tree_fits_box(const lbm_branch *b, int n, int nx, int ny, int nz, double margin, bool y_spans_ok = false);
 void voxelize(const lbm_branch *b, int n, int nx, int ny, int nz, SolidMask &solid);
 int64_t build_links(const lbm_branch *b, int n, const SolidMask &solid, std::vector<HostLink> &links);
 int64_t frontal_area(const SolidMask &solid);

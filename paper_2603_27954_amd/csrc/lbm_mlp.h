@@ -67,11 +67,26 @@ struct SweepArgs {
     const float *area;         // per tree A_x / H^2
     float *cd;                 // n_trees x n_re
 };
+// Friction coefficient table of a cylinder normal to the flow: on segment k
+// (log10 Re_D >= lg[k] for k >= 1; the first segment also below lg[1], the last
+// also above the table) log2 C_f = a2[k] + s2[k] log10 Re_D.
+constexpr int CF_MAX_NODES = 32;
+struct CfArgs {
+    int n_seg;                 // nodes - 1
+    float lg[CF_MAX_NODES];    // segment start, log10 Re_D
+    float a2[CF_MAX_NODES];    // intercept of log2 C_f
+    float s2[CF_MAX_NODES];    // slope of log2 C_f over log10 Re_D
+    float *cf;                 // n_trees x n_re friction estimates
+    float *cp;                 // n_trees x n_re pressure estimates, or null
+};
 // surrogate: sum_b y_b L_b D_b / A_x with y_b from the network (extrapolated
 // through the cylinder curve outside the envelope)
 hipError_t launch_tree_sweep(const MlpDev &d, const SweepArgs &a, hipStream_t s);
 // analytic model: sum_b C_d(Re_b) L_b D_b sin^3(alpha_b) / A_x
 hipError_t launch_analytic_sweep(const SweepArgs &a, hipStream_t s);
+// the same, and sum_b C_f(Re_b) L_b D_b sin^3(alpha_b) / A_x into c.cf, the
+// difference of the two into c.cp
+hipError_t launch_analytic_split(const SweepArgs &a, const CfArgs &c, hipStream_t s);
 // frontal area of each tree (units of H^2): union of the branches' projected
 // capsules rasterised with pixel edge h (units of H); -1 when the tree does
 // not fit AREA_PIX pixels per side

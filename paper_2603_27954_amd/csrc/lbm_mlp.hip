@@ -405,21 +405,47 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_
     }
 }
 
-__global__ void __launch_bounds__(64) k_analytic_sweep(SweepArgs a)
+// C_f of the table at log10 Re_D = lg: the segment is picked by selects over
+// the (wave-uniform) segment starts, so no lane indexes the table.
+__device__ __forceinline__ float cylinder_cf(const CfArgs &c, float lg)
+{
+    float a2 = c.a2[0], s2 = c.s2[0];
+    for (int k = 1; k < c.n_seg; ++k) {
+        const bool up = lg >= c.lg[k];
+        a2 = up ? c.a2[k] : a2;
+        s2 = up ? c.s2[k] : s2;
+    }
+    return __builtin_amdgcn_exp2f(fmaf(s2, lg, a2));
+}
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(64) k_analytic_sweep(SweepArgs a, CfArgs c)
 {
     const int lane = threadIdx.x, tree = blockIdx.x;
     const int64_t b0 = a.tree_start[tree], b1 = a.tree_start[tree + 1];
     const float ln_rc = logf(a.re_cr), inv = 1.0f / a.area[tree];
     for (int q = 0; q < a.n_re; ++q) {
-        float acc = 0.0f;
+        float acc = 0.0f, accf = 0.0f;
         for (int64_t br = b0 + lane; br < b1; br += 64) {
             const float *rc = a.rec + br * SWEEP_REC;
             const float sn = sinf(rc[1] * 0.01745329252f);
-            acc = fmaf(cylinder_cd(a.lg_re[q] + rc[0], ln_rc), rc[4] * sn * sn * sn, acc);
+            const float lg = a.lg_re[q] + rc[0], w = rc[4] * sn * sn * sn;
+            acc = fmaf(cylinder_cd(lg, ln_rc), w, acc);
+            if constexpr (SPLIT)
+                accf = fmaf(cylinder_cf(c, lg), w, accf);
         }
         const float sum = wave_sum_f(acc);
+        const size_t o = (size_t)tree * a.n_re + q;
         if (lane == 0)
-            a.cd[(size_t)tree * a.n_re + q] = sum * inv;
+            a.cd[o] = sum * inv;
+        if constexpr (SPLIT) {
+            const float sumf = wave_sum_f(accf);
+            if (lane == 0) {
+                c.cf[o] = sumf * inv;
+                if (c.cp)
+                    c.cp[o] = (sum - sumf) * inv;
+            }
+        }
     }
 }
 
@@ -638,7 +664,15 @@ hipError_t launch_analytic_sweep(const SweepArgs &a, hipStream_t s)
 {
     if (a.n_trees <= 0 || a.n_re <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_analytic_sweep, dim3(a.n_trees), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_analytic_sweep<false>, dim3(a.n_trees), dim3(64), 0, s, a, CfArgs{});
+    return hipGetLastError();
+}
+
+hipError_t launch_analytic_split(const SweepArgs &a, const CfArgs &c, hipStream_t s)
+{
+    if (a.n_trees <= 0 || a.n_re <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_analytic_sweep<true>, dim3(a.n_trees), dim3(64), 0, s, a, c);
     return hipGetLastError();
 }
 

@@ -831,7 +831,8 @@ static lbm_status check_branches(const lbm_grid_desc &d, const lbm_branch *b, in
             return (*msg = "branch of zero length", LBM_E_INVALID);
     }
     const int margin = d.levels == 1 ? 2 : d.block_edge << (d.levels - 1);
-    if (!tree_fits_box(b, n_b, d.nx, d.ny, d.nz, margin))
+    // one level with periodic y: a cylinder spanning y is allowed
+    if (!tree_fits_box(b, n_b, d.nx, d.ny, d.nz, margin, d.levels == 1 && d.periodic_yz != 0))
         return (*msg = "tree comes too close to the box faces", LBM_E_INVALID);
     return LBM_OK;
 }

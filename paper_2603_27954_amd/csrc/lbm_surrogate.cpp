@@ -457,6 +457,36 @@ lbm_status lbm_analytic_sweep(const lbm_sweep_desc *d, void *stream)
     return LBM_OK;
 }
 
+lbm_status lbm_analytic_split(const lbm_sweep_desc *d, const lbm_cf_table *t, float *cf, float *cp, void *stream)
+{
+    SweepArgs a;
+    lbm_status st = sweep_args(d, a);
+    if (st != LBM_OK)
+        return st;
+    if (!t || !t->lg_re || !t->cf || t->n < 2 || t->n > CF_MAX_NODES || !cf)
+        return mfail(LBM_E_INVALID, "bad friction table or output");
+    for (int k = 0; k < t->n; ++k) {
+        if (!std::isfinite(t->lg_re[k]) || !std::isfinite(t->cf[k]) || !(t->cf[k] > 0.0))
+            return mfail(LBM_E_INVALID, "friction table: finite nodes and C_f > 0 required");
+        if (k > 0 && !(t->lg_re[k] > t->lg_re[k - 1]))
+            return mfail(LBM_E_INVALID, "friction table: log10 Re_D nodes must increase strictly");
+    }
+    CfArgs c{};
+    c.n_seg = t->n - 1;
+    for (int k = 0; k < c.n_seg; ++k) {
+        const double l0 = std::log2(t->cf[k]), l1 = std::log2(t->cf[k + 1]);
+        const double s2 = (l1 - l0) / (t->lg_re[k + 1] - t->lg_re[k]);
+        c.lg[k] = (float)t->lg_re[k];
+        c.s2[k] = (float)s2;
+        c.a2[k] = (float)(l0 - s2 * t->lg_re[k]);
+    }
+    c.cf = cf;
+    c.cp = cp;
+    MHIP(launch_analytic_split(a, c, (hipStream_t)stream));
+    MHIP(hipStreamSynchronize((hipStream_t)stream));
+    return LBM_OK;
+}
+
 lbm_status lbm_mlp_predict(lbm_mlp *m, const float *x, int64_t n, float *y)
 {
     if (!m || !x || !y || n < 0)

@@ -63,6 +63,31 @@ def test_valid_description_without_device_reports_device_error(lt):
     assert e.value.status == lt.LBM_E_DEVICE
 
 
+@pytest.mark.parametrize("lg, cf", [
+    ([1.0], [0.5]),                      # one node
+    ([1.0, 1.0], [0.5, 0.4]),            # nodes not increasing
+    ([2.0, 1.0], [0.5, 0.4]),
+    ([1.0, 2.0], [0.5, 0.0]),            # C_f must be > 0
+    ([1.0, 2.0], [0.5, -0.1]),
+    ([1.0, float("nan")], [0.5, 0.4]),
+    ([1.0, 2.0], [0.5, float("inf")]),
+    (list(range(33)), [0.1] * 33),       # more than 32 nodes
+])
+def test_friction_table_rejected_on_host(lt, lg, cf):
+    """lbm_analytic_split validates the C_f table before any device work (the
+    device pointers here are never dereferenced)."""
+    fake = C.c_void_p(256)
+    re_h = np.array([1e4, 1e5])
+    d = lt.SweepDesc()
+    d.rec, d.tree_start, d.n_trees = fake, fake, 1
+    d.re_h, d.n_re = re_h.ctypes.data_as(C.POINTER(C.c_double)), 2
+    d.area, d.cd = fake, fake
+    lg, cf = np.array(lg, dtype=np.float64), np.array(cf, dtype=np.float64)
+    t = lt.CfTable(lg.ctypes.data_as(C.POINTER(C.c_double)), cf.ctypes.data_as(C.POINTER(C.c_double)), len(lg))
+    st = lt.lib().lbm_analytic_split(C.byref(d), C.byref(t), fake, None, None)
+    assert st == lt.LBM_E_INVALID
+
+
 def _lib_tree(lt, p: O.TreeParams, target_h, com):
     lp = lt.tree_params(p.m, p.order, p.s0, p.w0, p.len_ratio, p.wid_ratio, p.pre_roll, p.pitch,
                         p.post_roll, p.jitter, p.seed)
@@ -88,12 +113,16 @@ def test_tree_generator_matches_oracle(lt, case):
     assert np.allclose(got, ref, rtol=0, atol=1e-9 * max(1.0, h))
 
 
-@pytest.mark.parametrize("case", ["cfg1", "seeded3_small"])
+@pytest.mark.parametrize("case", ["cfg1", "seeded3_small", "cylinder_spanning_y"])
 def test_voxels_links_area_match_oracle(lt, case):
-    """P11: accelerated voxeliser / link builder equal the brute-force oracle."""
+    """P11: accelerated voxeliser / link builder equal the brute-force oracle
+    (with wrapped y and z neighbours, also for a cylinder that spans y)."""
     if case == "cfg1":
         nx, ny, nz = 64, 32, 32
         b = O.build_tree(O.cfg1_tree_params(), 0.0, [16.0, 16.0, 16.0])
+    elif case == "cylinder_spanning_y":
+        nx, ny, nz = 96, 16, 48
+        b = np.array([[24.3, -16.0, 23.7, 24.3, 32.0, 23.7, 11.0, 0.0, -1.0, 0.0]])
     else:
         nx, ny, nz = 192, 96, 96
         b = O.build_tree(O.seeded3_tree_params(3, 2), 48.0, [48.0, 48.0, 48.0])
@@ -249,6 +278,23 @@ def test_plan_of_the_paper_tree_at_h512_stays_sparse(lt):
     cells = 512 * 256 * 256 + sum((b + 1) * 512 for b in plan["blocks"][1:])
     assert abs(plan["pop_bytes"] - 54 * cells) < 0.01 * plan["pop_bytes"] + 64 * 1024 * 6
     print(f"  H/512 plan: {dt:.1f} s, leaf cells {sum(plan['leaf_cells']):,}, {plan['pop_bytes'] / 1e9:.2f} GB")
+
+
+def test_only_a_y_parallel_cylinder_may_cross_the_y_faces(lt):
+    """On one level with periodic y a branch along y that runs past both y
+    faces is accepted; one that ends inside the box near a y face, is tilted,
+    or sits on a two-level grid is not."""
+    def plan(b, levels=1):
+        return lt.plan_levels(np.array(b, dtype=np.float64), refine={"band": [0, 8], "wake": [0, 0]} if levels > 1
+                              else None, nx=128, ny=32, nz=128, u_in=0.05, nu=0.01, block_edge=16, levels=levels)
+    ok = [[64.0, -8.0, 64.0, 64.0, 40.0, 64.0, 8.0, 0, -1, 0]]
+    plan(ok)
+    for bad, levels in (([[64.0, 1.0, 64.0, 64.0, 40.0, 64.0, 8.0, 0, -1, 0]], 1),
+                        ([[64.0, -8.0, 64.0, 65.0, 40.0, 64.0, 8.0, 0, -1, 0]], 1),
+                        (ok, 2)):
+        with pytest.raises(lt.LbmError) as e:
+            plan(bad, levels)
+        assert e.value.status == lt.LBM_E_INVALID
 
 
 def test_plan_rejects_refinement_at_the_faces(lt):

@@ -57,6 +57,39 @@ def test_uniform_friction_matches_oracle(gpu, storage):
     g.close()
 
 
+def test_spanning_cylinder_friction_matches_oracle(gpu):
+    """The geometry of the C_f runs: one cylinder along y through the periodic
+    y faces (D = 11 cells, Re_D = 20), friction and drag after 40 steps
+    against the oracle (FP32, tolerance as above)."""
+    print("[friction] cylinder spanning y, 96x16x48", flush=True)
+    nx, ny, nz = 96, 16, 48
+    D = 11.0
+    b = np.array([[24.3, -16.0, 23.7, 24.3, 32.0, 23.7, D, 0.0, -1.0, 0.0]])
+    nu = U * D / 20.0
+    om = O.omega_from_nu(nu)
+    g = gpu.Grid(nx, ny, nz, u_in=U, nu=nu, drag_every=1, flags=gpu.LBM_F_FRICTION)
+    g.set_geometry(b)
+    solid = O.voxelize(b, nx, ny, nz)
+    lk = O.links(b, solid, nx, ny, nz)
+    sim = O.UniformSim(nx, ny, nz, om, u_in=U, solid=solid, link=lk, n_branch=1)
+    steps = 40
+    g.step(steps)
+    d = g.drag()
+    tot, fx = np.zeros(3), np.zeros(3)
+    for _ in range(steps):
+        sim.step(1)
+        t, _p = F.tree_friction_force(sim.f, om, solid, lk, (nx, ny, nz), b)
+        tot += t / steps
+        fx += sim.last_force / steps
+    err = np.abs(d["friction"] - tot).max() / abs(tot[0])
+    errd = np.abs(d["force"] - fx).max() / abs(fx[0])
+    print(f"  friction x gpu {d['friction'][0]:.6e} oracle {tot[0]:.6e} (rel err {err:.2e}); "
+          f"drag rel err {errd:.2e}", flush=True)
+    assert err < TOL["fp32"] and errd < 1e-4
+    assert 0.0 < tot[0] < fx[0]
+    g.close()
+
+
 def test_two_level_friction_matches_oracle(gpu):
     """Friction sampled at the end of each coarse step (drag_every = 2) on the
     finest level of a two-level grid, against the oracle's finest level with
@@ -84,3 +117,23 @@ def test_two_level_friction_matches_oracle(gpu):
               f"(rel {e:.2e})", flush=True)
     assert worst < TOL["fp32"]
     g.close()
+
+
+def test_cylinder_friction_share_falls_with_re(gpu):
+    """The C_f generator of the analytic friction model (Sec. 2.4) on one long
+    cylinder normal to the flow (D = 16 cells, 5 % blockage): in the steady
+    regime at Re_D = 40 the skin friction carries about a third of the drag
+    (classical steady solutions of the cylinder; 0.25 to 0.45 allowed, C_d
+    1.3 to 2.0 with the blockage), and C_f and its share of C_d fall as Re_D
+    grows from 20 to 100."""
+    from paper_2603_27954_amd import cylinder
+    res = {}
+    for re in (20.0, 40.0, 100.0):
+        print(f"[cylinder] Re_D {re:g}", flush=True)
+        res[re] = cylinder.cylinder_coefficients(gpu, re, diameter=16.0, passes=2.0,
+                                                 log=lambda s: print(" ", s, flush=True))
+    cd, cf = res[40.0]
+    assert 1.3 < cd < 2.0
+    assert 0.25 < cf / cd < 0.45
+    assert res[20.0][1] > res[40.0][1] > res[100.0][1]
+    assert res[20.0][1] / res[20.0][0] > cf / cd > res[100.0][1] / res[100.0][0]

@@ -194,6 +194,55 @@ def test_many_tree_sweeps_match_oracle(gpu, intensity):
         assert err.max() < 5e-3, f"tree {i} surrogate: {err.max():.2e}"
 
 
+@pytest.mark.parametrize("intensity", [0.0, 0.08])
+def test_analytic_friction_split_matches_oracle(gpu, intensity):
+    """C_D-est, C_F-est and C_P-est of Eqs. (3)-(6) per tree and per Re_H
+    against the oracle, with a seeded C_f table shaped like a cylinder's
+    (about 2.5 Re^(-0.55), 10 % noise) on 8 nodes; Re_D from about 5 to 1e8
+    runs the power laws below and above the table too.  C_D-est is the plain
+    sweep's, bit for bit."""
+    import torch
+
+    import oracle as O
+    from oracle import analytic_oracle as A
+    rng = np.random.default_rng(31)
+    lg = np.linspace(0.5, 4.0, 8)
+    cf_nodes = 2.5 * (10.0 ** lg) ** -0.55 * (1.0 + 0.1 * rng.uniform(-1.0, 1.0, 8))
+    params = gpu.tree_params(3, 3, 1.0, 0.3, [0.7] * 3, [0.7] * 3, [0.0, 120.0, 240.0], [35.0] * 3, [90.0] * 3,
+                             jitter=5.0, seed=0)
+    orders = [1, 2, 3, 4, 5, 0, 3, 2]
+    rec, start = gpu.tree_batch(params, 700, orders)
+    rd, sd = torch.from_numpy(rec).cuda(), torch.from_numpy(start).cuda()
+    n = len(orders)
+    area = torch.empty(n, dtype=torch.float32, device="cuda")
+    gpu.frontal_area(rd, sd, 1.0 / 256, area)
+    ag = area.cpu().numpy().astype(np.float64)
+    re_h = 10.0 ** np.linspace(3, 9, 25)
+    shape = (n, len(re_h))
+    cd0 = torch.empty(shape, dtype=torch.float32, device="cuda")
+    gpu.analytic_sweep(rd, sd, area, cd0, re_h, intensity)
+    cd, cf, cp = (torch.empty(shape, dtype=torch.float32, device="cuda") for _ in range(3))
+    gpu.analytic_split(rd, sd, area, cd, cf, re_h, (lg, cf_nodes), intensity, cp)
+    cd0, cd, cf, cp = (t.cpu().numpy().astype(np.float64) for t in (cd0, cd, cf, cp))
+    assert np.array_equal(cd, cd0)
+    worst = 0.0
+    for i, o in enumerate(orders):
+        b = O.build_tree(O.seeded3_tree_params(o, 700 + i), 1.0, [0.0, 0.0, 0.0])
+        want_d = A.tree_cd_est(b, re_h, 1.0, ag[i], intensity)
+        want_f = A.tree_cf_est(b, re_h, 1.0, ag[i], (lg, cf_nodes))
+        want_p = A.tree_cp_est(b, re_h, 1.0, ag[i], (lg, cf_nodes), intensity)
+        assert np.allclose(cd[i], want_d, rtol=2e-4), f"tree {i} C_D-est"
+        # FP32 sums of FP32 power laws: a few ulps per branch
+        ef = np.abs(cf[i] - want_f) / want_f
+        assert ef.max() < 1e-4, f"tree {i} C_F-est: {ef.max():.2e}"
+        # C_P-est = C_D-est - C_F-est carries both errors
+        ep = np.abs(cp[i] - want_p) / want_d
+        assert ep.max() < 3e-4, f"tree {i} C_P-est: {ep.max():.2e}"
+        worst = max(worst, ef.max())
+    print(f"  I_u {intensity}: C_F-est max rel err {worst:.2e}; C_F / C_D at Re_H 1e3 "
+          f"{np.mean(cf[:, 0] / cd[:, 0]):.3f}, at 1e9 {np.mean(cf[:, -1] / cd[:, -1]):.4f}", flush=True)
+
+
 def _paper_params(gpu, n):
     """The binary family of Table 2 with n rewrites (n generations: trunk and
     n - 1 child levels, the reading that reproduces Table 3)."""
