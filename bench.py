@@ -282,6 +282,12 @@ PAPER2048_N8 = dict(n=8, H=2048.0, re_h=2500.0, levels=8, band=[0, 1024, 512, 25
                     wake=[0, 0, 0, 0, 4096, 0, 0, 0], storage="fp16", wake_level=4, shapes_from="paper H/128")
 
 
+# the n = 6 tree at H/512 (six levels, wake at H/256) for the drag split of
+# the LBM against the analytic model's
+PAPER512_N6 = dict(n=6, H=512.0, re_h=2500.0, levels=6, band=[0, 256, 128, 64, 32, 16],
+                   wake=[0, 0, 0, 0, 1024, 0], storage="fp32", wake_level=4, shapes_from="paper H/128")
+
+
 def _paper_tree(lt, cfg):
     H = cfg["H"]
     wq = 0.5 ** 0.5
@@ -375,6 +381,78 @@ def paper_tree_leg(lt, torch, steps, warmup, cfg=PAPER):
                      "total_leaf_cells": int(sum(info["active_cells"][:L])), "links": info["links"],
                      "device_gb": round(info["device_bytes"] / 1e9, 2), "setup_s": round(setup, 1),
                      "finest_dx_over_h": round(1.0 / H, 5)}}
+
+
+def paper_split_leg(lt, torch, cfg=PAPER512_N6, warm_flow_times=3.0, mean_flow_times=3.0):
+    """Drag split of one of the paper's trees, LBM against the analytic model
+    (Sec. 2.4 Eqs. (2)-(6), Sec. 3 Eqs. (7)-(9)): C_D, C_F and C_P = C_D - C_F
+    of the LBM, averaged over mean_flow_times flow times H/U after
+    warm_flow_times, and C_D-est, C_F-est, C_P-est of the same tree at the same
+    Re_H (synthetic cylinder C_d curve, the C_f table from LBM runs of single
+    cylinders), both normalised by the LBM's voxel frontal area."""
+    import tempfile
+    from paper_2603_27954_amd.cylinder import load_cf_table
+    stream = STREAM
+    H, L = cfg["H"], cfg["levels"]
+    nx, ny, nz = int(32 * H), int(16 * H), int(16 * H)
+    arr = _paper_tree(lt, cfg)
+    shapes = _shapes_of_paper128(lt, cfg["storage"]) if TUNE else None
+    coarse = 1 << (L - 1)
+    g = lt.Grid(nx, ny, nz, u_in=U_IN, re_h=cfg["re_h"], block_edge=8, levels=L, storage=cfg["storage"],
+                drag_every=coarse, flags=lt.LBM_F_GRAPH | lt.LBM_F_FRICTION, stream=stream.cuda_stream)
+    t0 = time.time()
+    g.set_geometry(arr, refine={"band": cfg["band"], "wake": cfg["wake"]})
+    print(f"paper split n={cfg['n']} H/{int(H)}: {L}-level grid set up in {time.time() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    if shapes is not None:
+        path = os.path.join(tempfile.mkdtemp(), "tune.txt")
+        key = f"nx{nx}_ny{ny}_nz{nz}_B8_L{L}_S{lt.STORAGE[cfg['storage']]}_links{g.info()['links']}"
+        with open(path, "w") as f:
+            f.write(key + " " + " ".join(str(int(v)) for v in shapes) + "\n")
+        g.autotune(path)
+    info = g.info()
+    per_flow_time = max(1, int(round(H / U_IN / coarse)))  # coarse steps per H/U
+    t0 = time.time()
+    for k in range(int(warm_flow_times)):
+        g.step(per_flow_time)
+        d = g.drag()
+        print(f"  warm-up flow time {k + 1}: C_D {d['cd']:.4f} C_F {d['cf']:.4f} ({time.time() - t0:.1f} s)",
+              file=sys.stderr, flush=True)
+    acc = {"cd": 0.0, "cf": 0.0}
+    n_mean = int(mean_flow_times)
+    for k in range(n_mean):
+        g.step(per_flow_time)
+        d = g.drag()
+        acc["cd"] += d["cd"] / n_mean
+        acc["cf"] += d["cf"] / n_mean
+        print(f"  averaged flow time {k + 1}: C_D {d['cd']:.4f} C_F {d['cf']:.4f} ({time.time() - t0:.1f} s)",
+              file=sys.stderr, flush=True)
+    area_lbm = d["area_x"]
+    height = d["height"]
+    g.close()
+    # the analytic model on the same tree at unit height
+    wq = 0.5 ** 0.5
+    p = lt.tree_params(2, cfg["n"] - 1, 100.0, 30.0, [0.8, 0.8], [wq, wq], [0.0, 0.0], [30.0, -30.0],
+                       [137.0, 137.0])
+    rec, start = lt.tree_batch(p, 0, [cfg["n"] - 1])
+    rd, sd = torch.from_numpy(rec).cuda(), torch.from_numpy(start).cuda()
+    area_raster = torch.empty(1, dtype=torch.float32, device="cuda")
+    lt.frontal_area(rd, sd, 1.0 / 256, area_raster, stream.cuda_stream)
+    area = torch.full((1,), area_lbm / height ** 2, dtype=torch.float32, device="cuda")
+    cd, cf, cp = (torch.empty((1, 1), dtype=torch.float32, device="cuda") for _ in range(3))
+    lt.analytic_split(rd, sd, area, cd, cf, [cfg["re_h"]], load_cf_table(), 0.0, cp, stream.cuda_stream)
+    est = {"cd": float(cd.cpu()[0, 0]), "cf": float(cf.cpu()[0, 0]), "cp": float(cp.cpu()[0, 0])}
+    lbm = {"cd": acc["cd"], "cf": acc["cf"], "cp": acc["cd"] - acc["cf"]}
+    return {"workload": f"paper binary tree n={cfg['n']} (Table 2), domain 32Hx16Hx16H = {nx}x{ny}x{nz} finest "
+                        f"cells, {L} levels H/16..H/{int(H)}, wake H/256, Re_H={cfg['re_h']:g}, "
+                        f"{cfg['storage'].upper()}; means over {n_mean} flow times H/U after {int(warm_flow_times)}",
+            "lbm": {k: round(v, 4) for k, v in lbm.items()},
+            "analytic": {k: round(v, 4) for k, v in est.items()},
+            "analytic_over_lbm": {k: round(est[k] / lbm[k], 3) for k in lbm},
+            "area_x_over_h2": {"voxels": round(area_lbm / height ** 2, 5),
+                               "raster_h_over_256": round(float(area_raster.cpu()[0]), 5)},
+            "links": info["links"], "device_gb": round(info["device_bytes"] / 1e9, 2),
+            "coarse_steps": per_flow_time * (int(warm_flow_times) + n_mean)}
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -652,7 +730,7 @@ def main():
                     help="timed coarse steps (64 finest steps each) of the paper-tree leg at H/1024 (--legs paper1024)")
     ap.add_argument("--legs", default=None,
                     help="comma list of legs to run alone and print (amr3, amr4, paper, paper1024, paper1024n6, "
-                         "paper2048n8)")
+                         "paper2048n8, paper_split)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the drag-surrogate leg")
     ap.add_argument("--surrogate-trees", type=int, default=1_000_000)
     ap.add_argument("--surrogate-scale", choices=list(SURROGATE_SWEEPS), default="small",
@@ -704,7 +782,8 @@ def main():
                 "paper": lambda: paper_tree_leg(lt, torch, args.paper_steps, 2),
                 "paper1024": lambda: paper_tree_leg(lt, torch, args.paper1024_steps, 1, PAPER1024),
                 "paper1024n6": lambda: paper_tree_leg(lt, torch, args.paper1024_steps, 1, PAPER1024_N6),
-                "paper2048n8": lambda: paper_tree_leg(lt, torch, max(1, args.paper1024_steps // 2), 1, PAPER2048_N8)}
+                "paper2048n8": lambda: paper_tree_leg(lt, torch, max(1, args.paper1024_steps // 2), 1, PAPER2048_N8),
+                "paper_split": lambda: paper_split_leg(lt, torch)}
         print(json.dumps({k: legs[k]() for k in args.legs.split(",")}), flush=True)
         return
     if args.sweep_only:
