@@ -384,7 +384,8 @@ def paper_tree_leg(lt, torch, steps, warmup, cfg=PAPER):
 
 
 def paper_split_leg(lt, torch, cfg=PAPER512_N6, warm_flow_times=3.0, mean_flow_times=3.0):
-    """Drag split of one of the paper's trees, LBM against the analytic model
+    """Drag split of one of the paper's trees (cfg: n = 6 at H/512, or at the
+    paper's H/1024 with paper_split1024), LBM against the analytic model
     (Sec. 2.4 Eqs. (2)-(6), Sec. 3 Eqs. (7)-(9)): C_D, C_F and C_P = C_D - C_F
     of the LBM, averaged over mean_flow_times flow times H/U after
     warm_flow_times, and C_D-est, C_F-est, C_P-est of the same tree at the same
@@ -396,7 +397,10 @@ def paper_split_leg(lt, torch, cfg=PAPER512_N6, warm_flow_times=3.0, mean_flow_t
     H, L = cfg["H"], cfg["levels"]
     nx, ny, nz = int(32 * H), int(16 * H), int(16 * H)
     arr = _paper_tree(lt, cfg)
+    t0 = time.time()
     shapes = _shapes_of_paper128(lt, cfg["storage"]) if TUNE else None
+    print(f"paper split n={cfg['n']} H/{int(H)}: launch shapes {shapes} tuned on the tree at H/128 in "
+          f"{time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     coarse = 1 << (L - 1)
     g = lt.Grid(nx, ny, nz, u_in=U_IN, re_h=cfg["re_h"], block_edge=8, levels=L, storage=cfg["storage"],
                 drag_every=coarse, flags=lt.LBM_F_GRAPH | lt.LBM_F_FRICTION, stream=stream.cuda_stream)
@@ -730,7 +734,7 @@ def main():
                     help="timed coarse steps (64 finest steps each) of the paper-tree leg at H/1024 (--legs paper1024)")
     ap.add_argument("--legs", default=None,
                     help="comma list of legs to run alone and print (amr3, amr4, paper, paper1024, paper1024n6, "
-                         "paper2048n8, paper_split)")
+                         "paper2048n8, paper_split, paper_split1024)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the drag-surrogate leg")
     ap.add_argument("--surrogate-trees", type=int, default=1_000_000)
     ap.add_argument("--surrogate-scale", choices=list(SURROGATE_SWEEPS), default="small",
@@ -783,7 +787,8 @@ def main():
                 "paper1024": lambda: paper_tree_leg(lt, torch, args.paper1024_steps, 1, PAPER1024),
                 "paper1024n6": lambda: paper_tree_leg(lt, torch, args.paper1024_steps, 1, PAPER1024_N6),
                 "paper2048n8": lambda: paper_tree_leg(lt, torch, max(1, args.paper1024_steps // 2), 1, PAPER2048_N8),
-                "paper_split": lambda: paper_split_leg(lt, torch)}
+                "paper_split": lambda: paper_split_leg(lt, torch),
+                "paper_split1024": lambda: paper_split_leg(lt, torch, dict(PAPER1024_N6, storage="fp32"), 2.0, 3.0)}
         print(json.dumps({k: legs[k]() for k in args.legs.split(",")}), flush=True)
         return
     if args.sweep_only:
