@@ -254,13 +254,14 @@ def test_paper_tree_crisis_curves_match_oracle(gpu):
     """The drag-crisis curves of the paper's trees n = 4, 6, 8 (Sec. 4.1 and
     4.2, with the synthetic cylinder curve of the analytic model): frontal area
     and C_D-est(Re_H) from 1e3 to 1e9 at I_u = 0 and 8 % on the GPU against the
-    oracle; the crisis sets in near Re_H = 3e6 under uniform inflow and an order
+    oracle, with its friction and pressure parts (a power-law C_f table); the crisis sets in near Re_H = 3e6 under uniform inflow and an order
     of magnitude earlier at I_u = 8 %, and the drop softens as n grows."""
     import torch
 
     import oracle as O
     from oracle import analytic_oracle as A
     re_h = 10.0 ** np.linspace(3, 9, 31)  # at most 32 Re_H per sweep
+    table = ([1.0, 2.0, 3.0, 4.0], [2.5 * 10.0 ** (-0.55 * k) for k in (1.0, 2.0, 3.0, 4.0)])
     onsets, steepest, slopes = {}, {}, {}
     for n in (4, 6, 8):
         rec, start = gpu.tree_batch(_paper_params(gpu, n), 0, [n - 1])
@@ -279,6 +280,12 @@ def test_paper_tree_crisis_curves_match_oracle(gpu):
             got = cd.cpu().numpy()[0].astype(np.float64)
             want = A.tree_cd_est(b, re_h, 1.0, ag, iu)
             assert np.allclose(got, want, rtol=2e-4)
+            # the friction split of the same curve with a power-law table
+            cf, cp = (torch.empty((1, len(re_h)), dtype=torch.float32, device="cuda") for _ in range(2))
+            gpu.analytic_split(rd, sd, area, cd, cf, re_h, table, iu, cp)
+            want_f = A.tree_cf_est(b, re_h, 1.0, ag, table)
+            assert np.allclose(cf.cpu().numpy()[0], want_f, rtol=1e-4)
+            assert np.allclose(cp.cpu().numpy()[0], want - want_f, rtol=0, atol=3e-4 * want.max())
             ref = got[np.searchsorted(re_h, 1e5)]
             onsets[(n, iu)] = re_h[np.argmax((re_h > 1e5) & (got < 0.9 * ref))]
             s = np.diff(np.log(got)) / np.diff(np.log(re_h))
