@@ -734,7 +734,8 @@ def main():
                     help="timed coarse steps (64 finest steps each) of the paper-tree leg at H/1024 (--legs paper1024)")
     ap.add_argument("--legs", default=None,
                     help="comma list of legs to run alone and print (amr3, amr4, paper, paper1024, paper1024n6, "
-                         "paper2048n8, paper_split, paper_split1024, paper_split1024n4, paper_split1024n8)")
+                         "paper2048n8, paper_split, paper_split_re, paper_split1024, paper_split1024n4, "
+                         "paper_split1024n8)")
     ap.add_argument("--split-mean-flow-times", type=float, default=3.0,
                     help="flow times H/U averaged by the paper_split1024n8 leg (after two of warm-up)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the drag-surrogate leg")
@@ -791,6 +792,8 @@ def main():
                 "paper2048n8": lambda: paper_tree_leg(lt, torch, max(1, args.paper1024_steps // 2), 1, PAPER2048_N8),
                 "paper_split": lambda: paper_split_leg(lt, torch),
                 "paper_split1024": lambda: paper_split_leg(lt, torch, dict(PAPER1024_N6, storage="fp32"), 2.0, 3.0),
+                "paper_split_re": lambda: {f"re_h_{r:g}": paper_split_leg(lt, torch, dict(PAPER512_N6, re_h=r))
+                                           for r in (2.0e4, 6.0e4, 1.2e5)},
                 "paper_split1024n4": lambda: paper_split_leg(lt, torch, dict(PAPER1024, storage="fp32"), 2.0, 3.0),
                 "paper_split1024n8": lambda: paper_split_leg(lt, torch, dict(PAPER1024, n=8, storage="fp32"), 2.0,
                                                              args.split_mean_flow_times)}
